@@ -1,0 +1,173 @@
+/*
+ * tvdeblur -- lagged-diffusivity total-variation deblurring with reflective
+ * and anti-reflective boundary conditions and fast-transform
+ * preconditioners, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Z.-J. Bai, M. Donatelli, S. Serra-Capizzano, "Fast Preconditioners
+ * for Total Variation Deblurring with Anti-Reflective Boundary Conditions"
+ * (arXiv 1011.5964).
+ *
+ * Problem solved (Section 1, eqs. (nbf), (mp), (fp)): given an observed image
+ * v (ny x nx), a normalised, quadrantally symmetric PSF h ((2my+1) x (2mx+1),
+ * sum h = 1; Section 2 restricts fast diagonalisation to this case), the
+ * boundary condition used for the blur H (reflective or anti-reflective,
+ * Section 2) and alpha > 0, beta > 0, return
+ *     u ~ argmin 1/2 ||H u - v||^2 + alpha sum sqrt(|grad u|^2 + beta^2)
+ * computed by the lagged-diffusivity fixed point
+ *     (H^T H + alpha L(u^k)) u^{k+1} = H^T v,   u^0 = v          (eq. (fp))
+ * with each linear system solved by preconditioned conjugate gradients
+ * warm-started at u^k and stopped at ||r|| / ||r_0|| < inner_tol (Section 5).
+ * L(u^k) is the zero-Neumann TV diffusion operator with cell diffusivity
+ * 1/sqrt(|grad u^k|^2 + beta^2) (forward differences, unit grid spacing).
+ * Preconditioners (Section 3): none, the diagonal D = I + alpha diag(L)
+ * (eq. (D)), X, D_X = D^{1/2} X D^{1/2}, and X_D for the scaled system
+ * (eq. (scalesys)), where X is R (DCT-II, reflective) or M (DST-I on the
+ * interior, S^ = diag(1, S_{n-2}, 1), anti-reflective); Section 3.2 gives
+ * their 2D (tensor) forms.
+ *
+ * Conventions for every entry point
+ *  - Images are dense row-major ny x nx arrays (element (i, j) at i*nx + j),
+ *    resident in device memory of the handle's device and owned by the
+ *    caller; the library never frees or retains them.  Element type is
+ *    double for TVD_F64 handles and float for TVD_F32_MIXED handles.
+ *  - Host pointers are named *_host; everything else named *_dev is device.
+ *  - Work is queued on the handle's HIP stream; calls return after that
+ *    stream has completed the call's work, unless stated otherwise.
+ *  - Return value 0 (TVD_OK) on success or a negative TVD_E* code.  The
+ *    message for the last failure is returned by tvdeblur_last_error().
+ *    No C++ exception or abort crosses this interface.
+ *  - A handle must not be used from two host threads at once.
+ */
+#ifndef TVDEBLUR_H
+#define TVDEBLUR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tvdeblur_handle* tvdeblur_t;
+
+/* status codes */
+#define TVD_OK           0
+#define TVD_EINVAL      -1   /* bad argument, NaN/Inf parameter, aliasing buffers */
+#define TVD_ENOTSYM     -2   /* PSF not quadrantally symmetric (to 1e-12 max|h|) */
+#define TVD_ENORM       -3   /* |sum h - 1| > 1e-12 (no silent renormalisation) */
+#define TVD_ESIZE       -4   /* PSF too large for the image / image too small */
+#define TVD_ESTATE      -5   /* solve before set_psf / set_bc, or op before setup */
+#define TVD_EDEVICE     -6   /* HIP runtime error (message in last_error) */
+#define TVD_EBREAKDOWN  -7   /* PCG curvature p^T A p <= 0 (singular system) */
+#define TVD_ENOMEM      -8   /* device allocation failed */
+
+/* precision of a handle */
+#define TVD_F64        0     /* all vectors and arithmetic in IEEE double */
+#define TVD_F32_MIXED  1     /* float vectors, convolution, stencil and
+                                transforms; every inner product, the CG
+                                scalars, the stopping test, the fixed-point
+                                change and the preconditioner eigenvalue
+                                setup in double */
+
+/* boundary condition of the blur H (Section 2) */
+#define TVD_BC_REFLECTIVE      1
+#define TVD_BC_ANTIREFLECTIVE  2
+
+/* preconditioner (columns I, D, X, D_X, X_D of Tables 1-3) */
+#define TVD_PREC_NONE  0
+#define TVD_PREC_DIAG  1
+#define TVD_PREC_X     2
+#define TVD_PREC_D_X   3
+#define TVD_PREC_X_D   4
+
+#define TVD_MAX_OUTER  256
+
+typedef struct {
+    double alpha;              /* regularisation weight, > 0 (0 allowed only with TVD_PREC_NONE/X) */
+    double beta;               /* smoothing of |grad u|, > 0 */
+    int    max_outer;          /* fixed-point steps K, 1..TVD_MAX_OUTER */
+    double fp_tol;             /* stop when ||u^{k+1}-u^k||/||u^{k+1}|| < fp_tol; 0 = run exactly K */
+    double inner_tol;          /* PCG stop ||r|| < inner_tol ||r_0|| (strict); >= 0 */
+    int    max_inner;          /* PCG iteration cap per step, >= 1 */
+    int    precond;            /* TVD_PREC_* (default choice: TVD_PREC_X_D) */
+    const void* u0_dev;        /* initial iterate, or NULL for u^0 = v (Section 5) */
+    const int*  replay_host;   /* NULL, or max_outer PCG iteration counts to run exactly
+                                  (stopping test skipped); used to compare with a
+                                  reference that took the same number of steps */
+    void*  iterates_dev;       /* NULL, or room for (max_outer+1) images: u^0..u^K are
+                                  stored there (checkpoints for the adjoint) */
+} tvd_params;
+
+typedef struct {
+    int    outer_steps;                    /* fixed-point steps taken */
+    int    inner_iters[TVD_MAX_OUTER];     /* PCG iterations of each step */
+    double relres[TVD_MAX_OUTER];          /* final ||r||/||r_0|| of each step */
+    double fp_change[TVD_MAX_OUTER];       /* ||u^{k+1}-u^k|| / ||u^{k+1}|| */
+    int    all_converged;                  /* every step met inner_tol */
+    int    breakdown;                      /* a step stopped on p^T A p <= 0 */
+    long long total_inner_iters;
+    double time_total_s;                   /* wall time of the call */
+    double time_setup_s;                   /* per-step setup (diffusivity, eigenvalues) */
+    double time_inner_s;                   /* PCG loops */
+} tvd_stats;
+
+/* Create a handle for ny x nx images on the current HIP device, queuing
+ * work on hip_stream (a hipStream_t; NULL = the null stream).  ny, nx >= 3.
+ * Errors: TVD_EINVAL, TVD_ESIZE, TVD_EDEVICE. */
+int tvdeblur_create(tvdeblur_t* out, int ny, int nx, int precision, void* hip_stream);
+
+/* Copy the PSF (host, row-major py x px, both odd; centre at (py/2, px/2)).
+ * Checks: odd sizes; quadrantal symmetry h(a,b) = h(-a,b) = h(a,-b) to
+ * 1e-12 max|h| (Section 2, 2D case); |sum h - 1| <= 1e-12 (the normalised
+ * PSF of eq. (blur1d)); finite entries.  The PSF half-widths must satisfy
+ * m <= n-1 for anti-reflective and m <= n for reflective BCs (checked at
+ * set_bc and solve).  Errors: TVD_EINVAL, TVD_ENOTSYM, TVD_ENORM. */
+int tvdeblur_set_psf(tvdeblur_t h, const double* psf_host, int py, int px);
+
+/* Boundary condition of H: TVD_BC_REFLECTIVE or TVD_BC_ANTIREFLECTIVE
+ * (Section 2).  L(u) is always zero-Neumann.  Errors: TVD_EINVAL, TVD_ESIZE. */
+int tvdeblur_set_bc(tvdeblur_t h, int bc);
+
+/* Run the fixed-point / PCG method (eq. (fp)) on v_dev, writing u_dev.
+ * v_dev and u_dev must not alias.  stats (host, may be NULL) is filled in.
+ * Non-convergence of an inner solve within max_inner is not an error (the
+ * paper caps iterations too): it shows in stats.all_converged.
+ * Errors: TVD_EINVAL, TVD_ESTATE, TVD_ESIZE, TVD_EDEVICE, TVD_ENOMEM,
+ * TVD_EBREAKDOWN (u_dev then holds the last iterate). */
+int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev,
+                   const tvd_params* p, tvd_stats* stats);
+
+/* Release the handle and its device workspace. NULL is accepted. */
+int tvdeblur_destroy(tvdeblur_t h);
+
+/* Message of the last failure on h (or of the last failed create when h is
+ * NULL).  Valid until the next call on h. */
+const char* tvdeblur_last_error(tvdeblur_t h);
+
+/* ---- single operators, for verification of each step on its own ---- */
+
+/* y = H x, the blur under the handle's BC (Section 2). */
+int tvdeblur_op_blur(tvdeblur_t h, const void* x_dev, void* y_dev);
+
+/* y = H^T x. */
+int tvdeblur_op_blur_adjoint(tvdeblur_t h, const void* x_dev, void* y_dev);
+
+/* Per-fixed-point-step setup from the iterate uk_dev: diffusivity
+ * kappa(u^k), D = I + alpha diag(L(u^k)) (eq. (D)) and the preconditioner
+ * eigenvalues of the chosen variant (Section 3.2).  Kept in the handle for
+ * the two calls below. */
+int tvdeblur_op_setup(tvdeblur_t h, const void* uk_dev, double alpha, double beta, int precond);
+
+/* y = (H^T H + alpha L(u^k)) x with the state of the last op_setup (eq. (fp)). */
+int tvdeblur_op_normal(tvdeblur_t h, const void* x_dev, void* y_dev);
+
+/* z = P^{-1} r for the preconditioner of the last op_setup. */
+int tvdeblur_op_precond(tvdeblur_t h, const void* r_dev, void* z_dev);
+
+/* Copy an internal array of the last op_setup into dst_dev as ny x nx
+ * doubles: 0 = kappa, 1 = scaling s (D^{-1/2}, or 1), 2 = eigenvalues mu,
+ * 3 = lambda_H (PSF symbol on the BC grid), 4 = D. */
+int tvdeblur_op_export(tvdeblur_t h, int which, void* dst_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVDEBLUR_H */

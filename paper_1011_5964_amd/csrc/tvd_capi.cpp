@@ -1,0 +1,882 @@
+// C-ABI of libtvdeblur (include/tvdeblur.h): handle state, per-solve and
+// per-step setup, and the host side of the fixed-point / PCG loop.  The host
+// only queues kernels; the CG scalars stay on the device and the host reads
+// back one small control block per fixed-point step (and at polling points).
+#include "../../include/tvdeblur.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tvd_internal.hpp"
+
+namespace tvd {
+
+namespace {
+
+std::string g_create_error;
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define TVD_HIP(expr)                                                  \
+    do {                                                               \
+        hipError_t _e = (expr);                                        \
+        if (_e != hipSuccess) throw ::tvd::HipError{_e, #expr};             \
+    } while (0)
+
+struct ApiError {
+    int code;
+    std::string msg;
+};
+
+class DeviceArena {
+   public:
+    ~DeviceArena() { release(); }
+    void* alloc(size_t bytes) {
+        void* p = nullptr;
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) throw ApiError{TVD_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+        ptrs_.push_back(p);
+        return p;
+    }
+    template <typename T>
+    T* upload(const std::vector<double>& host, hipStream_t s) {
+        std::vector<T> tmp(host.begin(), host.end());
+        T* d = static_cast<T*>(alloc(tmp.size() * sizeof(T)));
+        TVD_HIP(hipMemcpyAsync(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        TVD_HIP(hipStreamSynchronize(s));
+        return d;
+    }
+    void release() {
+        for (void* p : ptrs_) (void)hipFree(p);
+        ptrs_.clear();
+    }
+
+   private:
+    std::vector<void*> ptrs_;
+};
+
+class SolverBase {
+   public:
+    virtual ~SolverBase() = default;
+    virtual void build(const std::vector<double>& psf, int py, int px, int bc) = 0;
+    virtual void solve(const void* v, void* u, const tvd_params& p, tvd_stats& st) = 0;
+    virtual void op_blur(const void* x, void* y, bool adjoint) = 0;
+    virtual void op_setup(const void* uk, double alpha, double beta, int variant) = 0;
+    virtual void op_normal(const void* x, void* y) = 0;
+    virtual void op_precond(const void* r, void* z) = 0;
+    virtual void op_export(int which, void* dst) = 0;
+};
+
+template <typename T>
+class Solver final : public SolverBase {
+   public:
+    Solver(int ny, int nx, hipStream_t s, size_t max_lds) : ny_(ny), nx_(nx), N_(size_t(ny) * nx), s_(s), max_lds_(max_lds) {
+        TVD_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_st_), sizeof(PcgState), hipHostMallocDefault));
+        TVD_HIP(hipEventCreate(&ev_a_));
+        TVD_HIP(hipEventCreate(&ev_b_));
+        TVD_HIP(hipEventCreate(&ev_c_));
+    }
+    ~Solver() override {
+        if (host_st_) (void)hipHostFree(host_st_);
+        (void)hipEventDestroy(ev_a_);
+        (void)hipEventDestroy(ev_b_);
+        (void)hipEventDestroy(ev_c_);
+    }
+
+    // ---------------------------------------------------------------- build
+    void build(const std::vector<double>& psf, int py, int px, int bc) override {
+        geo_.release();
+        bc_ = bc;
+        const PsfFactors f = factor_psf(psf.data(), py, px);
+        my_ = f.my;
+        mx_ = f.mx;
+        rank_ = f.rank;
+        // 1D blur matrices of each factor with the BC folded in, and bands
+        std::vector<double> hy, hx, hty, htx, ky, kx;
+        for (int r = 0; r < rank_; ++r) {
+            const std::vector<double> Hy = blur_matrix_1d(f.gy[r], ny_, bc);
+            const std::vector<double> Hx = blur_matrix_1d(f.gx[r], nx_, bc);
+            append(hy, band_of(Hy, ny_, my_));
+            append(hx, band_of(Hx, nx_, mx_));
+            append(hty, band_of(transpose(Hy, ny_), ny_, my_));
+            append(htx, band_of(transpose(Hx, nx_), nx_, mx_));
+            if (rank_ == 1) {
+                ky = band_of(matmul_tn(Hy, Hy, ny_), ny_, 2 * my_);
+                kx = band_of(matmul_tn(Hx, Hx, nx_), nx_, 2 * mx_);
+            }
+        }
+        Hy_ = geo_.upload<T>(hy, s_);
+        Hx_ = geo_.upload<T>(hx, s_);
+        HTy_ = geo_.upload<T>(hty, s_);
+        HTx_ = geo_.upload<T>(htx, s_);
+        fused_ = false;
+        if (rank_ == 1) {
+            Ky_ = geo_.upload<T>(ky, s_);
+            Kx_ = geo_.upload<T>(kx, s_);
+            BandArgs<T> probe = band_base();
+            probe.wy = 2 * my_;
+            probe.wx = 2 * mx_;
+            probe.nterms = 1;
+            probe.kap = reinterpret_cast<const T*>(1);
+            ty_fused_ = pick_ty(probe);
+            fused_ = ty_fused_ > 0;
+        }
+        {
+            BandArgs<T> probe = band_base();
+            probe.wy = my_;
+            probe.wx = mx_;
+            probe.nterms = rank_;
+            ty_h_ = pick_ty(probe);
+            probe.kap = reinterpret_cast<const T*>(1);
+            probe.S = reinterpret_cast<const T*>(1);
+            ty_ht_ = pick_ty(probe);
+            if (ty_h_ == 0 || ty_ht_ == 0) throw ApiError{TVD_ESIZE, "PSF too large for the device's LDS tile"};
+        }
+        // symbol eigenvalues
+        lamh_host_ = symbol_eigenvalues(psf.data(), py, px, ny_, nx_, bc);
+        std::vector<double> l2(lamh_host_.size());
+        for (size_t k = 0; k < l2.size(); ++k) l2[k] = lamh_host_[k] * lamh_host_[k];
+        lamh2_ = geo_.upload<double>(l2, s_);
+        lamh_ = geo_.upload<double>(lamh_host_, s_);
+        // transform plans
+        make_plan(planX_, nx_);
+        if (ny_ == nx_) planY_ = planX_;
+        else make_plan(planY_, ny_);
+        gx_ = line_geom<T>(ny_, planX_.M);  // row pass: lines are rows (ny of them)
+        gy_ = line_geom<T>(nx_, planY_.M);  // column pass: lines are columns
+        if (gx_.lds + kStaticLds > max_lds_ || gy_.lds + kStaticLds > max_lds_)
+            throw ApiError{TVD_ESIZE, "transform length too large for the device's LDS"};
+        // basis matrices for the eigenvalue setup
+        make_basis(ny_, Wy_, Puy_, Puly_, Ply_);
+        if (ny_ == nx_) {
+            Wx_ = Wy_;
+            Pux_ = Puy_;
+            Pulx_ = Puly_;
+            Plx_ = Ply_;
+        } else {
+            make_basis(nx_, Wx_, Pux_, Pulx_, Plx_);
+        }
+        // work buffers
+        auto A = [&](size_t elems) { return static_cast<T*>(geo_.alloc(elems * sizeof(T))); };
+        auto D = [&](size_t elems) { return static_cast<double*>(geo_.alloc(elems * sizeof(double))); };
+        U_ = A(N_);
+        X_ = A(N_);
+        R_ = A(N_);
+        Pb_[0] = A(N_);
+        Pb_[1] = A(N_);
+        Q_ = A(N_);
+        Z_ = A(N_);
+        T1_ = A(N_);
+        T2_ = A(N_);
+        B_ = A(N_);
+        Kap_ = A(N_);
+        Sap_ = A(N_);
+        MuInv_ = A(N_);
+        Tmp_ = A(N_);
+        Kapd_ = D(N_);
+        Smu_ = D(N_);
+        Dd_ = D(N_);
+        for (auto& p : Aop_) p = D(N_);
+        for (auto& p : Bop_) p = D(N_);
+        for (auto& p : Yg_) p = D(N_);
+        for (auto& p : Zg_) p = D(N_);
+        Sd_ = D(N_);
+        LamX_ = D(N_);
+        LamY_ = D(N_);
+        LamD_ = D(N_);
+        Mu_ = D(N_);
+        nb_band_ = band_blocks(ny_, nx_, fused_ ? ty_fused_ : ty_ht_);
+        const int cap = std::max({nb_band_, gx_.blocks, gy_.blocks, 1024, 1024});
+        pq_ = D(cap);
+        rr_[0] = D(cap);
+        rr_[1] = D(cap);
+        rz_[0] = D(cap);
+        rz_[1] = D(cap);
+        fp_ = D(2 * 1024);
+        st_ = static_cast<PcgState*>(geo_.alloc(sizeof(PcgState)));
+        // GEMM problem tables (pointers are fixed for the handle's life)
+        std::vector<GemmProblem> s1, s2;
+        for (int t = 0; t < 3; ++t) s1.push_back(gp(ny_, nx_, nx_, 0, {{Aop_[t], Wx_, 1.0}}, Yg_[t]));
+        for (int t = 0; t < 3; ++t) s1.push_back(gp(ny_, nx_, ny_, 1, {{Wy_, Bop_[t], 1.0}}, Zg_[t]));
+        s1.push_back(gp(ny_, nx_, ny_, 1, {{Wy_, Smu_, 1.0}}, Sd_));
+        s2.push_back(gp(ny_, nx_, ny_, 1, {{Puy_, Yg_[0], 1.0}, {Puly_, Yg_[1], -2.0}, {Ply_, Yg_[2], 1.0}}, LamX_));
+        s2.push_back(gp(ny_, nx_, nx_, 0, {{Zg_[0], Pux_, 1.0}, {Zg_[1], Pulx_, -2.0}, {Zg_[2], Plx_, 1.0}}, LamY_));
+        s2.push_back(gp(ny_, nx_, nx_, 0, {{Sd_, Wx_, 1.0}}, LamD_));
+        gemm1_ = static_cast<GemmProblem*>(geo_.alloc(s1.size() * sizeof(GemmProblem)));
+        gemm2_ = static_cast<GemmProblem*>(geo_.alloc(s2.size() * sizeof(GemmProblem)));
+        TVD_HIP(hipMemcpyAsync(gemm1_, s1.data(), s1.size() * sizeof(GemmProblem), hipMemcpyHostToDevice, s_));
+        TVD_HIP(hipMemcpyAsync(gemm2_, s2.data(), s2.size() * sizeof(GemmProblem), hipMemcpyHostToDevice, s_));
+        TVD_HIP(hipStreamSynchronize(s_));
+        have_setup_ = false;
+    }
+
+    // ------------------------------------------------------------ operators
+    // y = (sum_r By_r (x) Bx_r) x
+    void blur_apply(const T* x, T* y, bool adjoint) {
+        BandArgs<T> a = band_base();
+        a.wy = my_;
+        a.wx = mx_;
+        a.nterms = rank_;
+        a.By = adjoint ? HTy_ : Hy_;
+        a.Bx = adjoint ? HTx_ : Hx_;
+        a.X = x;
+        a.Y = y;
+        launch(a, ty_h_);
+    }
+
+    // y = A x (fresh input), or the residual Bvec - A x with ||.||^2 partials.
+    void normal_apply(const T* x, T* y, const T* bvec, double* rr_out) {
+        if (fused_) {
+            BandArgs<T> a = band_base();
+            a.wy = 2 * my_;
+            a.wx = 2 * mx_;
+            a.nterms = 1;
+            a.By = Ky_;
+            a.Bx = Kx_;
+            a.X = x;
+            a.kap = Kap_;
+            a.alpha = alpha_;
+            a.Bvec = bvec;
+            a.Y = y;
+            a.dot_part = rr_out;
+            a.dotmode = rr_out ? 2 : 0;
+            a.st = st_;
+            launch(a, ty_fused_);
+        } else {
+            blur_apply(x, Tmp_, false);
+            BandArgs<T> a = band_base();
+            a.wy = my_;
+            a.wx = mx_;
+            a.nterms = rank_;
+            a.By = HTy_;
+            a.Bx = HTx_;
+            a.X = Tmp_;
+            a.kap = Kap_;
+            a.alpha = alpha_;
+            a.S = x;
+            a.Bvec = bvec;
+            a.Y = y;
+            a.dot_part = rr_out;
+            a.dotmode = rr_out ? 2 : 0;
+            a.st = st_;
+            launch(a, ty_ht_);
+        }
+    }
+
+    // PCG direction update fused with q = A p and <p, q> partials.
+    void normal_apply_update(int it) {
+        const T* pold = Pb_[(it + 1) & 1];
+        T* pnew = Pb_[it & 1];
+        BandArgs<T> a = band_base();
+        a.X = pold;
+        a.Z = Z_;
+        a.Xnew = pnew;
+        a.rz_new = rz_[(it - 1) & 1];
+        a.rz_old = it >= 2 ? rz_[it & 1] : nullptr;
+        a.n_rz = n_rz_;
+        a.st = st_;
+        if (fused_) {
+            a.wy = 2 * my_;
+            a.wx = 2 * mx_;
+            a.nterms = 1;
+            a.By = Ky_;
+            a.Bx = Kx_;
+            a.kap = Kap_;
+            a.alpha = alpha_;
+            a.Y = Q_;
+            a.dot_part = pq_;
+            a.dotmode = 1;
+            launch(a, ty_fused_);
+        } else {
+            a.wy = my_;
+            a.wx = mx_;
+            a.nterms = rank_;
+            a.By = Hy_;
+            a.Bx = Hx_;
+            a.Y = Tmp_;
+            launch(a, ty_h_);
+            BandArgs<T> b = band_base();
+            b.wy = my_;
+            b.wx = mx_;
+            b.nterms = rank_;
+            b.By = HTy_;
+            b.Bx = HTx_;
+            b.X = Tmp_;
+            b.kap = Kap_;
+            b.alpha = alpha_;
+            b.S = pnew;
+            b.Y = Q_;
+            b.dot_part = pq_;
+            b.dotmode = 1;
+            b.st = st_;
+            launch(b, ty_ht_);
+        }
+        n_pq_ = nb_band_;
+    }
+
+    // Per-step setup from u^k: kappa, D, s, mu.
+    void setup(const T* uk, double alpha, double beta, int variant) {
+        alpha_ = alpha;
+        beta_ = beta;
+        variant_ = variant;
+        TVD_HIP(launch_kappa<T>(ny_, nx_, uk, alpha, beta, variant, Kap_, Kapd_, Sap_, Smu_, Dd_, s_));
+        if (variant >= TVD_PREC_X) {
+            TVD_HIP(launch_gemm_operands(ny_, nx_, Kapd_, Smu_, Aop_[0], Aop_[1], Aop_[2], Bop_[0], Bop_[1],
+                                         Bop_[2], s_));
+            const int use_d = variant == TVD_PREC_X_D;
+            TVD_HIP(launch_gemm(gemm1_, use_d ? 7 : 6, ny_, nx_, s_));
+            TVD_HIP(launch_gemm(gemm2_, use_d ? 3 : 2, ny_, nx_, s_));
+            TVD_HIP(launch_mu<T>(int(N_), lamh2_, LamX_, LamY_, LamD_, use_d, alpha, Mu_, MuInv_, s_));
+        }
+        have_setup_ = true;
+    }
+
+    // z = P^{-1} r of the current setup (stand-alone operator).
+    void precond_apply(const T* r, T* z) {
+        TVD_HIP(launch_init_state(st_, 0.0, s_));
+        if (variant_ <= TVD_PREC_DIAG) {
+            int nb = 0;
+            TVD_HIP(launch_diag_update<T>(int(N_), nullptr, const_cast<T*>(r), nullptr, nullptr,
+                                          variant_ == TVD_PREC_DIAG ? Sap_ : nullptr, z, nullptr, 0, nullptr, 0,
+                                          rr_[1], rz_[0], st_, 0, 0, 0, nullptr, 0, &nb, s_));
+            return;
+        }
+        rowpass(0, false, const_cast<T*>(r), nullptr, 0);
+        colpass(0, false, 0);
+        rowpass_inv(z, const_cast<T*>(r), rz_[0]);
+    }
+
+    // -------------------------------------------------------------- solve
+    void solve(const void* vv, void* uu, const tvd_params& p, tvd_stats& st) override {
+        const auto t0 = std::chrono::steady_clock::now();
+        const T* v = static_cast<const T*>(vv);
+        T* uout = static_cast<T*>(uu);
+        std::memset(&st, 0, sizeof(st));
+        st.all_converged = 1;
+        T* iters_out = static_cast<T*>(p.iterates_dev);
+        // b = H^T v, u^0
+        blur_apply(v, B_, true);
+        TVD_HIP(hipMemcpyAsync(U_, p.u0_dev ? p.u0_dev : vv, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        float ms_setup = 0, ms_inner = 0;
+        int prev_iters = 8;
+        for (int k = 0; k < p.max_outer; ++k) {
+            if (iters_out)
+                TVD_HIP(hipMemcpyAsync(iters_out + size_t(k) * N_, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+            TVD_HIP(hipEventRecord(ev_a_, s_));
+            setup(U_, p.alpha, p.beta, p.precond);
+            TVD_HIP(hipEventRecord(ev_b_, s_));
+            const int maxit = p.replay_host ? p.replay_host[k] : p.max_inner;
+            const double tol = p.replay_host ? 0.0 : p.inner_tol;
+            pcg(maxit, tol, prev_iters);
+            TVD_HIP(hipEventRecord(ev_c_, s_));
+            TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+            TVD_HIP(hipStreamSynchronize(s_));
+            float a = 0, b = 0;
+            TVD_HIP(hipEventElapsedTime(&a, ev_a_, ev_b_));
+            TVD_HIP(hipEventElapsedTime(&b, ev_b_, ev_c_));
+            ms_setup += a;
+            ms_inner += b;
+            const PcgState hs = *host_st_;
+            st.inner_iters[k] = hs.iters;
+            st.relres[k] = hs.relres;
+            st.fp_change[k] = hs.fp_change;
+            st.total_inner_iters += hs.iters;
+            st.outer_steps = k + 1;
+            prev_iters = std::max(1, hs.iters);
+            std::swap(U_, X_);
+            if (hs.done != 1 && hs.iters >= maxit && !p.replay_host) st.all_converged = 0;
+            if (hs.done == 2) {
+                st.breakdown = 1;
+                st.all_converged = 0;
+                break;
+            }
+            if (p.fp_tol > 0.0 && hs.fp_change < p.fp_tol) break;
+        }
+        if (iters_out)
+            TVD_HIP(hipMemcpyAsync(iters_out + size_t(st.outer_steps) * N_, U_, N_ * sizeof(T),
+                                   hipMemcpyDeviceToDevice, s_));
+        TVD_HIP(hipMemcpyAsync(uout, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        TVD_HIP(hipStreamSynchronize(s_));
+        st.time_setup_s = ms_setup * 1e-3;
+        st.time_inner_s = ms_inner * 1e-3;
+        st.time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (st.breakdown) throw ApiError{TVD_EBREAKDOWN, "PCG breakdown: p^T A p <= 0"};
+    }
+
+    // One PCG solve: x (X_) starts at u^k (U_), ends at u^{k+1}.
+    void pcg(int maxit, double tol, int predicted) {
+        TVD_HIP(launch_init_state(st_, tol, s_));
+        TVD_HIP(hipMemcpyAsync(X_, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        const bool transform = variant_ >= TVD_PREC_X;
+        T* dinv = variant_ == TVD_PREC_DIAG ? Sap_ : nullptr;
+        // r_0 = b - A x_0, ||r_0||^2 partials
+        normal_apply(X_, R_, B_, rr_[0]);
+        int last_rr_n = nb_band_;
+        const double* last_rr = rr_[0];
+        if (transform) {
+            rowpass(0, false, R_, nullptr, 0);
+            colpass(0, true, nb_band_, rr_[0]);
+            rowpass_inv(Z_, R_, rz_[0]);
+            n_rz_ = gx_.blocks;
+        } else {
+            int nb = 0;
+            TVD_HIP(launch_diag_update<T>(int(N_), X_, R_, nullptr, nullptr, dinv, Z_, nullptr, 0, nullptr, 0, rr_[1],
+                                          rz_[0], st_, 0, 0, 1, rr_[0], nb_band_, &nb, s_));
+            n_rz_ = nb;
+            last_rr = rr_[1];
+            last_rr_n = nb;
+        }
+        // polling schedule: first look near the predicted count, then often
+        int next_poll = std::max(2, predicted - 1);
+        for (int it = 1; it <= maxit; ++it) {
+            normal_apply_update(it);
+            if (transform) {
+                rowpass(it, true, R_, rr_[0], 0);
+                last_rr = rr_[0];
+                last_rr_n = gx_.blocks;
+                if (it < maxit) {
+                    colpass(it, true, gx_.blocks, rr_[0]);
+                    rowpass_inv(Z_, R_, rz_[it & 1]);
+                }
+            } else {
+                int nb = 0;
+                TVD_HIP(launch_diag_update<T>(int(N_), X_, R_, Pb_[it & 1], Q_, dinv, Z_, pq_, n_pq_,
+                                              rz_[(it - 1) & 1], n_rz_, rr_[(it + 1) & 1], rz_[it & 1], st_, it, 1,
+                                              1, rr_[it & 1], last_rr_n, &nb, s_));
+                last_rr = rr_[(it + 1) & 1];
+                last_rr_n = nb;
+                n_rz_ = nb;
+            }
+            if (it == next_poll && it < maxit) {
+                TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+                TVD_HIP(hipStreamSynchronize(s_));
+                if (host_st_->done) break;
+                next_poll = it + 2;
+            }
+        }
+        int nfp = 0;
+        TVD_HIP(launch_fpchange<T>(int(N_), X_, U_, fp_, &nfp, s_));
+        TVD_HIP(launch_finalize<T>(st_, last_rr, last_rr_n, fp_, nfp, maxit, s_));
+    }
+
+    void rowpass(int it, bool update, T* r, double* part_out, int /*unused*/) {
+        RowPassArgs<T> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.plan = planX_;
+        a.g = gx_;
+        a.mode = 0;
+        a.do_update = update ? 1 : 0;
+        a.x = X_;
+        a.r = r;
+        a.p = Pb_[it & 1];
+        a.q = Q_;
+        a.pq_part = pq_;
+        a.n_pq = n_pq_;
+        a.rz_part = rz_[(it - 1) & 1];
+        a.n_rz = n_rz_;
+        a.s = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
+        a.dst = T1_;
+        a.part_out = part_out;
+        a.st = st_;
+        a.iter = it;
+        TVD_HIP(launch_rowpass<T>(a, s_));
+    }
+    void colpass(int it, bool check, int n_rr, const double* rr = nullptr) {
+        ColPassArgs<T> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.plan = planY_;
+        a.g = gy_;
+        a.src = T1_;
+        a.dst = T2_;
+        a.muinv = MuInv_;
+        a.check = check ? 1 : 0;
+        a.rr_part = rr;
+        a.n_rr = n_rr;
+        a.st = st_;
+        a.iter = it;
+        TVD_HIP(launch_colpass<T>(a, s_));
+    }
+    void rowpass_inv(T* z, T* r, double* rz_out) {
+        RowPassArgs<T> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.plan = planX_;
+        a.g = gx_;
+        a.mode = 1;
+        a.r = r;
+        a.s = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
+        a.src = T2_;
+        a.dst = z;
+        a.part_out = rz_out;
+        a.st = st_;
+        TVD_HIP(launch_rowpass<T>(a, s_));
+    }
+
+    // -------------------------------------------------------- op entry points
+    void op_blur(const void* x, void* y, bool adjoint) override {
+        TVD_HIP(launch_init_state(st_, 0.0, s_));
+        blur_apply(static_cast<const T*>(x), static_cast<T*>(y), adjoint);
+        TVD_HIP(hipStreamSynchronize(s_));
+    }
+    void op_setup(const void* uk, double alpha, double beta, int variant) override {
+        setup(static_cast<const T*>(uk), alpha, beta, variant);
+        TVD_HIP(hipStreamSynchronize(s_));
+    }
+    void op_normal(const void* x, void* y) override {
+        if (!have_setup_) throw ApiError{TVD_ESTATE, "op_normal before op_setup"};
+        TVD_HIP(launch_init_state(st_, 0.0, s_));
+        normal_apply(static_cast<const T*>(x), static_cast<T*>(y), nullptr, nullptr);
+        TVD_HIP(hipStreamSynchronize(s_));
+    }
+    void op_precond(const void* r, void* z) override {
+        if (!have_setup_) throw ApiError{TVD_ESTATE, "op_precond before op_setup"};
+        precond_apply(static_cast<const T*>(r), static_cast<T*>(z));
+        TVD_HIP(hipStreamSynchronize(s_));
+    }
+    void op_export(int which, void* dst) override {
+        if (which != 3 && !have_setup_) throw ApiError{TVD_ESTATE, "op_export before op_setup"};
+        double* d = static_cast<double*>(dst);
+        const size_t bytes = N_ * sizeof(double);
+        switch (which) {
+            case 0: TVD_HIP(hipMemcpyAsync(d, Kapd_, bytes, hipMemcpyDeviceToDevice, s_)); break;
+            case 1:
+                if (variant_ == TVD_PREC_X || variant_ <= TVD_PREC_DIAG) {
+                    std::vector<double> ones(N_, 1.0);
+                    TVD_HIP(hipMemcpyAsync(d, ones.data(), bytes, hipMemcpyHostToDevice, s_));
+                    TVD_HIP(hipStreamSynchronize(s_));
+                } else {
+                    TVD_HIP(launch_cast_to_double<T>(int(N_), Sap_, d, s_));
+                }
+                break;
+            case 2: TVD_HIP(hipMemcpyAsync(d, Mu_, bytes, hipMemcpyDeviceToDevice, s_)); break;
+            case 3: TVD_HIP(hipMemcpyAsync(d, lamh_, bytes, hipMemcpyDeviceToDevice, s_)); break;
+            case 4: TVD_HIP(hipMemcpyAsync(d, Dd_, bytes, hipMemcpyDeviceToDevice, s_)); break;
+            default: throw ApiError{TVD_EINVAL, "unknown export index"};
+        }
+        TVD_HIP(hipStreamSynchronize(s_));
+    }
+
+   private:
+    static void append(std::vector<double>& dst, const std::vector<double>& src) {
+        dst.insert(dst.end(), src.begin(), src.end());
+    }
+    static GemmProblem gp(int M, int N, int K, int transA, std::initializer_list<GemmTerm> terms, double* C) {
+        GemmProblem p{};
+        p.M = M;
+        p.N = N;
+        p.K = K;
+        p.transA = transA;
+        p.nterms = int(terms.size());
+        int i = 0;
+        for (const GemmTerm& t : terms) p.t[i++] = t;
+        p.C = C;
+        return p;
+    }
+    BandArgs<T> band_base() const {
+        BandArgs<T> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        return a;
+    }
+    void launch(const BandArgs<T>& a, int ty) { TVD_HIP(launch_band<T>(a, ty, s_, nullptr)); }
+    // Tallest band tile (16, else 8) whose LDS fits the device; 0 if none.
+    int pick_ty(const BandArgs<T>& a) const {
+        for (int ty : {16, 8})
+            if (band_lds_bytes(a, ty) + kStaticLds <= max_lds_) return ty;
+        return 0;
+    }
+    static constexpr size_t kStaticLds = 512;  // static reduction scratch of the kernels
+
+    void make_plan(AxisPlan<T>& P, int n) {
+        const AxisTables t = make_axis_tables(n, bc_);
+        P.n = n;
+        P.kind = t.kind;
+        P.L = t.L;
+        P.M = t.M;
+        P.log2M = t.log2M;
+        P.bluestein = t.bluestein;
+        P.tw = reinterpret_cast<const cx<T>*>(geo_.upload<T>(t.tw, s_));
+        P.chirp = t.bluestein ? reinterpret_cast<const cx<T>*>(geo_.upload<T>(t.chirp, s_)) : nullptr;
+        P.bf = t.bluestein ? reinterpret_cast<const cx<T>*>(geo_.upload<T>(t.bf, s_)) : nullptr;
+        P.pre = t.kind == 2 ? reinterpret_cast<const cx<T>*>(geo_.upload<T>(t.pre, s_)) : nullptr;
+        P.post = t.kind == 2 ? reinterpret_cast<const cx<T>*>(geo_.upload<T>(t.post, s_)) : nullptr;
+        P.dst_scale = T(t.dst_scale);
+    }
+    void make_basis(int n, const double*& W, const double*& Pu, const double*& Pul, const double*& Pl) {
+        const std::vector<double> phi = basis_matrix(n, bc_);
+        std::vector<double> w(phi.size()), pu(phi.size(), 0.0), pul(phi.size(), 0.0), pl(phi.size(), 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                const double c = phi[size_t(i) * n + k];
+                w[size_t(i) * n + k] = c * c;
+                if (i < n - 1) {
+                    const double up = phi[size_t(i + 1) * n + k];
+                    pu[size_t(i) * n + k] = up * up;
+                    pul[size_t(i) * n + k] = up * c;
+                    pl[size_t(i) * n + k] = c * c;
+                }
+            }
+        W = geo_.upload<double>(w, s_);
+        Pu = geo_.upload<double>(pu, s_);
+        Pul = geo_.upload<double>(pul, s_);
+        Pl = geo_.upload<double>(pl, s_);
+    }
+
+    int ny_, nx_;
+    size_t N_;
+    hipStream_t s_;
+    size_t max_lds_;
+    DeviceArena geo_;
+    int bc_ = 0, my_ = 0, mx_ = 0, rank_ = 0;
+    bool fused_ = false;
+    int ty_fused_ = 0, ty_h_ = 0, ty_ht_ = 0;
+    const T *Hy_ = nullptr, *Hx_ = nullptr, *HTy_ = nullptr, *HTx_ = nullptr, *Ky_ = nullptr, *Kx_ = nullptr;
+    std::vector<double> lamh_host_;
+    const double *lamh2_ = nullptr, *lamh_ = nullptr;
+    AxisPlan<T> planX_{}, planY_{};
+    LineGeom gx_{}, gy_{};
+    const double *Wy_ = nullptr, *Puy_ = nullptr, *Puly_ = nullptr, *Ply_ = nullptr;
+    const double *Wx_ = nullptr, *Pux_ = nullptr, *Pulx_ = nullptr, *Plx_ = nullptr;
+    T *U_ = nullptr, *X_ = nullptr, *R_ = nullptr, *Pb_[2] = {nullptr, nullptr}, *Q_ = nullptr, *Z_ = nullptr;
+    T *T1_ = nullptr, *T2_ = nullptr, *B_ = nullptr, *Kap_ = nullptr, *Sap_ = nullptr, *MuInv_ = nullptr,
+      *Tmp_ = nullptr;
+    double *Kapd_ = nullptr, *Smu_ = nullptr, *Dd_ = nullptr, *Aop_[3] = {}, *Bop_[3] = {}, *Yg_[3] = {},
+           *Zg_[3] = {}, *Sd_ = nullptr, *LamX_ = nullptr, *LamY_ = nullptr, *LamD_ = nullptr, *Mu_ = nullptr;
+    double *pq_ = nullptr, *rr_[2] = {nullptr, nullptr}, *rz_[2] = {nullptr, nullptr}, *fp_ = nullptr;
+    int nb_band_ = 0, n_pq_ = 0, n_rz_ = 0;
+    PcgState* st_ = nullptr;
+    PcgState* host_st_ = nullptr;
+    GemmProblem *gemm1_ = nullptr, *gemm2_ = nullptr;
+    hipEvent_t ev_a_{}, ev_b_{}, ev_c_{};
+    double alpha_ = 0, beta_ = 0;
+    int variant_ = TVD_PREC_X_D;
+    bool have_setup_ = false;
+};
+
+}  // namespace
+}  // namespace tvd
+
+struct tvdeblur_handle {
+    int ny = 0, nx = 0, prec = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    std::vector<double> psf;
+    int py = 0, px = 0;
+    int bc = 0;
+    bool built = false;
+    std::unique_ptr<tvd::SolverBase> solver;
+};
+
+namespace {
+
+int fail(tvdeblur_t h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    else tvd::g_create_error = msg;
+    return code;
+}
+
+template <typename F>
+int guarded(tvdeblur_t h, F&& f) {
+    try {
+        return f();
+    } catch (const tvd::ApiError& e) {
+        return fail(h, e.code, e.msg);
+    } catch (const tvd::HipError& e) {
+        return fail(h, TVD_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc&) {
+        return fail(h, TVD_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(h, TVD_EDEVICE, "unexpected internal error");
+    }
+}
+
+int check_psf_fits(tvdeblur_t h) {
+    const int my = h->py / 2, mx = h->px / 2;
+    if (h->bc == TVD_BC_ANTIREFLECTIVE && (my > h->ny - 1 || mx > h->nx - 1))
+        return fail(h, TVD_ESIZE, "anti-reflective BCs need PSF half-width <= n-1");
+    if (h->bc == TVD_BC_REFLECTIVE && (my > h->ny || mx > h->nx))
+        return fail(h, TVD_ESIZE, "reflective BCs need PSF half-width <= n");
+    return TVD_OK;
+}
+
+int ensure_built(tvdeblur_t h) {
+    if (h->psf.empty()) return fail(h, TVD_ESTATE, "PSF not set");
+    if (h->bc == 0) return fail(h, TVD_ESTATE, "boundary condition not set");
+    int rc = check_psf_fits(h);
+    if (rc) return rc;
+    if (!h->built) {
+        h->solver->build(h->psf, h->py, h->px, h->bc);
+        h->built = true;
+    }
+    return TVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvdeblur_create(tvdeblur_t* out, int ny, int nx, int precision, void* hip_stream) {
+    if (!out) return fail(nullptr, TVD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (precision != TVD_F64 && precision != TVD_F32_MIXED) return fail(nullptr, TVD_EINVAL, "bad precision");
+    if (ny < 3 || nx < 3) return fail(nullptr, TVD_ESIZE, "images must be at least 3 x 3");
+    tvdeblur_t h = new (std::nothrow) tvdeblur_handle();
+    if (!h) return fail(nullptr, TVD_ENOMEM, "host allocation failed");
+    h->ny = ny;
+    h->nx = nx;
+    h->prec = precision;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    int rc = guarded(nullptr, [&]() {
+        TVD_HIP(hipGetDevice(&h->device));
+        int lds = 0;
+        TVD_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+        if (precision == TVD_F64) h->solver.reset(new tvd::Solver<double>(ny, nx, h->stream, size_t(lds)));
+        else h->solver.reset(new tvd::Solver<float>(ny, nx, h->stream, size_t(lds)));
+        return TVD_OK;
+    });
+    if (rc != TVD_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return TVD_OK;
+}
+
+int tvdeblur_set_psf(tvdeblur_t h, const double* psf_host, int py, int px) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    std::string err;
+    const int rc = tvd::validate_psf(psf_host, py, px, err);
+    if (rc == -1) return fail(h, TVD_EINVAL, err);
+    if (rc == -2) return fail(h, TVD_ENOTSYM, err);
+    if (rc == -3) return fail(h, TVD_ENORM, err);
+    h->psf.assign(psf_host, psf_host + size_t(py) * px);
+    h->py = py;
+    h->px = px;
+    h->built = false;
+    if (h->bc) return check_psf_fits(h);
+    return TVD_OK;
+}
+
+int tvdeblur_set_bc(tvdeblur_t h, int bc) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (bc != TVD_BC_REFLECTIVE && bc != TVD_BC_ANTIREFLECTIVE) return fail(h, TVD_EINVAL, "bad boundary condition");
+    h->bc = bc;
+    h->built = false;
+    if (!h->psf.empty()) return check_psf_fits(h);
+    return TVD_OK;
+}
+
+int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_params* p, tvd_stats* stats) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (!v_dev || !u_dev || !p) return fail(h, TVD_EINVAL, "NULL argument");
+    if (v_dev == u_dev) return fail(h, TVD_EINVAL, "v and u must not alias");
+    if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || p->alpha < 0 || !(p->beta > 0))
+        return fail(h, TVD_EINVAL, "alpha must be >= 0 and beta > 0, both finite");
+    if (p->max_outer < 1 || p->max_outer > TVD_MAX_OUTER) return fail(h, TVD_EINVAL, "max_outer out of range");
+    if (p->max_inner < 1 || !(p->inner_tol >= 0) || !(p->fp_tol >= 0))
+        return fail(h, TVD_EINVAL, "bad inner_tol / max_inner / fp_tol");
+    if (p->precond < TVD_PREC_NONE || p->precond > TVD_PREC_X_D) return fail(h, TVD_EINVAL, "bad preconditioner");
+    if (p->replay_host)
+        for (int k = 0; k < p->max_outer; ++k)
+            if (p->replay_host[k] < 0) return fail(h, TVD_EINVAL, "negative replay count");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        tvd_stats local;
+        h->solver->solve(v_dev, u_dev, *p, stats ? *stats : local);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_destroy(tvdeblur_t h) {
+    if (!h) return TVD_OK;
+    guarded(h, [&]() {
+        h->solver.reset();
+        return TVD_OK;
+    });
+    delete h;
+    return TVD_OK;
+}
+
+const char* tvdeblur_last_error(tvdeblur_t h) { return h ? h->err.c_str() : tvd::g_create_error.c_str(); }
+
+int tvdeblur_op_blur(tvdeblur_t h, const void* x_dev, void* y_dev) {
+    if (!h || !x_dev || !y_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_blur(x_dev, y_dev, false);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_op_blur_adjoint(tvdeblur_t h, const void* x_dev, void* y_dev) {
+    if (!h || !x_dev || !y_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_blur(x_dev, y_dev, true);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_op_setup(tvdeblur_t h, const void* uk_dev, double alpha, double beta, int precond) {
+    if (!h || !uk_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    if (!std::isfinite(alpha) || alpha < 0 || !std::isfinite(beta) || !(beta > 0))
+        return fail(h, TVD_EINVAL, "alpha must be >= 0 and beta > 0, both finite");
+    if (precond < TVD_PREC_NONE || precond > TVD_PREC_X_D) return fail(h, TVD_EINVAL, "bad preconditioner");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_setup(uk_dev, alpha, beta, precond);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_op_normal(tvdeblur_t h, const void* x_dev, void* y_dev) {
+    if (!h || !x_dev || !y_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_normal(x_dev, y_dev);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_op_precond(tvdeblur_t h, const void* r_dev, void* z_dev) {
+    if (!h || !r_dev || !z_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    if (r_dev == z_dev) return fail(h, TVD_EINVAL, "r and z must not alias");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_precond(r_dev, z_dev);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_op_export(tvdeblur_t h, int which, void* dst_dev) {
+    if (!h || !dst_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_export(which, dst_dev);
+        return TVD_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,203 @@
+// Internal interfaces of libtvdeblur: device-side argument blocks shared by
+// the host driver (tvd_capi.cpp) and the kernels (tvd_kernels.hip), and the
+// host-side precomputation routines (tvd_plan.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace tvd {
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+// PCG control block, one per solve, in device memory.  Written only by
+// block 0 of a kernel; read by later kernels on the same stream.
+struct PcgState {
+    double r0norm;     // ||r_0||
+    double tol;        // inner tolerance
+    double relres;     // ||r_i|| / ||r_0|| at the last convergence test
+    double fp_change;  // ||x - u|| / ||x||, filled by the step finaliser
+    int done;          // 0 running, 1 converged, 2 breakdown
+    int iters;         // iterations completed when done != 0
+    int pad[2];
+};
+
+// Transform plan for one axis: 1D DST-I on the interior (anti-reflective)
+// or DCT-II / DCT-III (reflective), computed two image lines at a time as
+// one complex DFT of length L (Stockham radix-2 when L is a power of two,
+// Bluestein through a power-of-two M otherwise).
+template <typename T>
+struct AxisPlan {
+    int n;          // line length
+    int kind;       // 1 = DST-I interior (AR), 2 = DCT-II/III (reflective)
+    int L, M, log2M, bluestein;
+    const cx<T>* tw;     // M/2 twiddles exp(-2 pi i t / M)
+    const cx<T>* chirp;  // L entries exp(-i pi t^2 / L)      (Bluestein)
+    const cx<T>* bf;     // M entries FFT_M(conj chirp, wrapped) / M (Bluestein)
+    const cx<T>* pre;    // n entries: DCT-III input weights w_k exp(+i pi k/(2n))
+    const cx<T>* post;   // n entries: DCT-II output weights w_k exp(-i pi k/(2n)) / 2
+    T dst_scale;         // 1/sqrt(2(n-1))
+};
+
+// Launch geometry of a line pass.
+struct LineGeom {
+    int units;   // line pairs
+    int upb;     // units per block
+    int tpu;     // threads per unit
+    int blocks;
+    size_t lds;  // dynamic LDS bytes
+};
+
+// Banded Kronecker operator  Y = sum_r (By_r (x) Bx_r) X  (+ alpha L(S) X,
+// optional p-update of the input, residual form and FP64 dot partials).
+template <typename T>
+struct BandArgs {
+    int ny, nx;
+    int wy, wx, nterms;
+    const T* By;           // [nterms][ny][2wy+1]
+    const T* Bx;           // [nterms][nx][2wx+1]
+    const T* X;            // input, or p_old when Z != nullptr
+    const T* Z;            // p-update: X_eff = Z + beta X
+    T* Xnew;               // receives X_eff (own tile) when Z != nullptr
+    const double* rz_new;  // beta = sum(rz_new)/sum(rz_old); rz_old == nullptr -> beta = 0
+    const double* rz_old;
+    int n_rz;
+    const T* kap;          // stencil diffusivity (nullptr: no stencil)
+    double alpha;
+    const T* S;            // stencil input; nullptr -> the (updated) band input
+    const T* Bvec;         // residual form Y = Bvec - result when non-null
+    T* Y;
+    double* dot_part;      // per-block partials
+    int dotmode;           // 0 none, 1 <stencil input, result>, 2 <Y, Y>
+    const PcgState* st;    // exit when st->done (nullable)
+    int tile_y;            // tile height (8 or 16), chosen by the launcher
+};
+
+template <typename T>
+struct RowPassArgs {
+    int ny, nx;
+    AxisPlan<T> plan;       // along rows (length nx)
+    LineGeom g;
+    int mode;               // 0 forward (s o r -> T1), 1 inverse (T2 -> z = s o ., <r,z>)
+    int do_update;          // mode 0: x += a p, r -= a q first; a = sum(rz)/sum(pq)
+    T* x;
+    T* r;
+    const T* p;
+    const T* q;
+    const double* pq_part;
+    int n_pq;
+    const double* rz_part;
+    int n_rz;
+    const T* s;             // scaling (nullptr = 1)
+    const T* src;
+    T* dst;
+    double* part_out;       // mode 0: ||r||^2 partials, mode 1: <r,z> partials
+    PcgState* st;
+    int iter;
+};
+
+template <typename T>
+struct ColPassArgs {
+    int ny, nx;
+    AxisPlan<T> plan;       // along columns (length ny)
+    LineGeom g;
+    const T* src;
+    T* dst;
+    const T* muinv;
+    int check;              // convergence test from rr partials before work
+    const double* rr_part;
+    int n_rr;
+    PcgState* st;
+    int iter;
+};
+
+// FP64 GEMM problem C = sum_t coef_t op(A_t) B_t (row-major).
+struct GemmTerm {
+    const double* A;
+    const double* B;
+    double coef;
+};
+struct GemmProblem {
+    int M, N, K;
+    int transA;
+    int nterms;
+    GemmTerm t[3];
+    double* C;
+};
+
+// ---- kernel launchers (tvd_kernels.hip) ----
+// Launch with tile height ty (8 or 16); band_lds_bytes gives the dynamic
+// LDS the launch needs, band_blocks the grid size (= number of partials).
+template <typename T>
+hipError_t launch_band(const BandArgs<T>& a, int ty, hipStream_t s, int* nblocks_out);
+int band_blocks(int ny, int nx, int ty);
+template <typename T>
+size_t band_lds_bytes(const BandArgs<T>& a, int ty);
+template <typename T>
+hipError_t launch_rowpass(const RowPassArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_colpass(const ColPassArgs<T>& a, hipStream_t s);
+template <typename T>
+LineGeom line_geom(int lines, int M);
+
+template <typename T>
+hipError_t launch_diag_update(int n, T* x, T* r, const T* p, const T* q, const T* dinv, T* z,
+                              const double* pq_part, int n_pq, const double* rz_part, int n_rz,
+                              double* rr_out, double* rz_out, PcgState* st, int iter, int do_update,
+                              int check, const double* rr_in, int n_rr_in, int* nblocks, hipStream_t s);
+
+template <typename T>
+hipError_t launch_kappa(int ny, int nx, const T* u, double alpha, double beta, int variant,
+                        T* kap, double* kapd, T* s_apply, double* s_mu, double* Dd, hipStream_t s);
+hipError_t launch_gemm_operands(int ny, int nx, const double* kapd, const double* s_mu, double* A1,
+                                double* A2, double* A3, double* B1, double* B2, double* B3,
+                                hipStream_t s);
+hipError_t launch_gemm(const GemmProblem* probs_dev, int nprob, int maxM, int maxN, hipStream_t s);
+template <typename T>
+hipError_t launch_mu(int n, const double* lamh2, const double* lamx, const double* lamy,
+                     const double* lamd, int use_lamd, double alpha, double* mu, T* muinv,
+                     hipStream_t s);
+template <typename T>
+hipError_t launch_fpchange(int n, const T* x, const T* u, double* part, int* nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_finalize(PcgState* st, const double* rr_part, int n_rr, const double* fp_part,
+                           int n_fp, int max_iter, hipStream_t s);
+template <typename T>
+hipError_t launch_cast_to_double(int n, const T* src, double* dst, hipStream_t s);
+hipError_t launch_init_state(PcgState* st, double tol, hipStream_t s);
+
+// ---- host precomputation (tvd_plan.cpp) ----
+struct PsfFactors {
+    int my, mx, rank;
+    std::vector<std::vector<double>> gy, gx;  // rank terms; h ~ sum gy_r gx_r^T
+};
+int validate_psf(const double* h, int py, int px, std::string& err);
+PsfFactors factor_psf(const double* h, int py, int px);
+
+// Dense 1D blur matrix (n x n, row-major) of the 1D filter g (length 2m+1,
+// centre at m) under the boundary condition bc (1 reflective, 2 AR).
+std::vector<double> blur_matrix_1d(const std::vector<double>& g, int n, int bc);
+// Band of a dense n x n matrix: out[i*(2w+1) + d + w] = A[i][i+d] (0 outside).
+std::vector<double> band_of(const std::vector<double>& A, int n, int w);
+std::vector<double> transpose(const std::vector<double>& A, int n);
+std::vector<double> matmul_tn(const std::vector<double>& A, const std::vector<double>& B, int n);
+
+// Basis matrix Phi[i*n + k] = phi_k(i) of the transform of the BC.
+std::vector<double> basis_matrix(int n, int bc);
+// lambda_H[k*nx + l] = h^(theta_k, theta_l) on the BC grid.
+std::vector<double> symbol_eigenvalues(const double* h, int py, int px, int ny, int nx, int bc);
+
+struct AxisTables {
+    int n, kind, L, M, log2M, bluestein;
+    std::vector<double> tw, chirp, bf, pre, post;  // interleaved re, im
+    double dst_scale;
+};
+AxisTables make_axis_tables(int n, int bc);
+
+}  // namespace tvd

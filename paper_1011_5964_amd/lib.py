@@ -1,0 +1,210 @@
+"""ctypes binding of libtvdeblur.so (include/tvdeblur.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Images are torch tensors on the HIP device (float64 for the
+'f64' precision, float32 for 'f32_mixed'); work is queued on torch's current
+stream of that device.  The binding raises if the library is not built --
+there is no CPU fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtvdeblur.so")
+
+TVD_OK = 0
+ERRORS = {-1: "TVD_EINVAL", -2: "TVD_ENOTSYM", -3: "TVD_ENORM", -4: "TVD_ESIZE", -5: "TVD_ESTATE",
+          -6: "TVD_EDEVICE", -7: "TVD_EBREAKDOWN", -8: "TVD_ENOMEM"}
+PRECISION = {"f64": 0, "f32_mixed": 1}
+BC = {"reflective": 1, "antireflective": 2}
+PRECOND = {"none": 0, "diag": 1, "x": 2, "d_x": 3, "x_d": 4}
+EXPORT = {"kappa": 0, "s": 1, "mu": 2, "lambda_h": 3, "d": 4}
+MAX_OUTER = 256
+
+# Every symbol declared in include/tvdeblur.h.
+EXPORTED_SYMBOLS = (
+    "tvdeblur_create", "tvdeblur_set_psf", "tvdeblur_set_bc", "tvdeblur_solve", "tvdeblur_destroy",
+    "tvdeblur_last_error", "tvdeblur_op_blur", "tvdeblur_op_blur_adjoint", "tvdeblur_op_setup",
+    "tvdeblur_op_normal", "tvdeblur_op_precond", "tvdeblur_op_export",
+)
+
+
+class TvdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("fp_tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_inner", ctypes.c_int),
+                ("precond", ctypes.c_int), ("u0_dev", ctypes.c_void_p), ("replay_host", ctypes.POINTER(ctypes.c_int)),
+                ("iterates_dev", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("outer_steps", ctypes.c_int), ("inner_iters", ctypes.c_int * MAX_OUTER),
+                ("relres", ctypes.c_double * MAX_OUTER), ("fp_change", ctypes.c_double * MAX_OUTER),
+                ("all_converged", ctypes.c_int), ("breakdown", ctypes.c_int),
+                ("total_inner_iters", ctypes.c_longlong), ("time_total_s", ctypes.c_double),
+                ("time_setup_s", ctypes.c_double), ("time_inner_s", ctypes.c_double)]
+
+    def to_dict(self):
+        k = self.outer_steps
+        return {"outer_steps": k, "inner_iters": list(self.inner_iters[:k]), "relres": list(self.relres[:k]),
+                "fp_change": list(self.fp_change[:k]), "all_converged": bool(self.all_converged),
+                "breakdown": bool(self.breakdown), "total_inner_iters": int(self.total_inner_iters),
+                "time_total_s": self.time_total_s, "time_setup_s": self.time_setup_s,
+                "time_inner_s": self.time_inner_s}
+
+
+_lib = None
+
+
+def load():
+    """Load libtvdeblur.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1011_5964_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "tvdeblur_create": [ctypes.POINTER(vp), i, i, i, vp],
+        "tvdeblur_set_psf": [vp, ctypes.POINTER(d), i, i],
+        "tvdeblur_set_bc": [vp, i],
+        "tvdeblur_solve": [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Stats)],
+        "tvdeblur_destroy": [vp],
+        "tvdeblur_op_blur": [vp, vp, vp],
+        "tvdeblur_op_blur_adjoint": [vp, vp, vp],
+        "tvdeblur_op_setup": [vp, vp, d, d, i],
+        "tvdeblur_op_normal": [vp, vp, vp],
+        "tvdeblur_op_precond": [vp, vp, vp],
+        "tvdeblur_op_export": [vp, i, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = i
+    lib.tvdeblur_last_error.argtypes = [vp]
+    lib.tvdeblur_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class TVDeblur:
+    """One handle: fixed image shape, precision and stream."""
+
+    def __init__(self, ny, nx, precision="f32_mixed", stream=None):
+        import torch
+        self.lib = load()
+        self.ny, self.nx = int(ny), int(nx)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.device = stream.device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_create(ctypes.byref(h), self.ny, self.nx, PRECISION[precision],
+                                          ctypes.c_void_p(stream.cuda_stream))
+        if rc != TVD_OK:
+            raise TvdError(rc, self.lib.tvdeblur_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != TVD_OK:
+            raise TvdError(rc, self.lib.tvdeblur_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tvdeblur_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _img(self, t, name):
+        if t.dtype != self.dtype or tuple(t.shape) != (self.ny, self.nx) or not t.is_contiguous() \
+                or t.device != self.device:
+            raise ValueError(f"{name} must be a contiguous {self.dtype} ({self.ny}, {self.nx}) tensor on {self.device}")
+        return t
+
+    def set_psf(self, psf):
+        h = np.ascontiguousarray(psf, dtype=np.float64)
+        self._check(self.lib.tvdeblur_set_psf(self.h, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              h.shape[0], h.shape[1]))
+
+    def set_bc(self, bc):
+        self._check(self.lib.tvdeblur_set_bc(self.h, BC[bc]))
+
+    def solve(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="x_d", fp_tol=0.0,
+              u0=None, replay=None, iterates=None, out=None):
+        import torch
+        self._img(v, "v")
+        u = out if out is not None else torch.empty_like(v)
+        p = Params()
+        p.alpha, p.beta, p.max_outer = float(alpha), float(beta), int(max_outer)
+        p.fp_tol, p.inner_tol, p.max_inner = float(fp_tol), float(inner_tol), int(max_inner)
+        p.precond = PRECOND[precond]
+        p.u0_dev = None if u0 is None else self._img(u0, "u0").data_ptr()
+        keep = None
+        if replay is not None:
+            keep = (ctypes.c_int * len(replay))(*[int(x) for x in replay])
+            p.replay_host = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int))
+        if iterates is not None:
+            if iterates.dtype != self.dtype or iterates.numel() < (max_outer + 1) * self.ny * self.nx:
+                raise ValueError("iterates buffer too small")
+            p.iterates_dev = iterates.data_ptr()
+        st = Stats()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_solve(self.h, _ptr(v), _ptr(u), ctypes.byref(p), ctypes.byref(st))
+        self._check(rc)
+        return u, st.to_dict()
+
+    # single operators
+    def _op(self, fn, x, name):
+        import torch
+        self._img(x, name)
+        y = torch.empty_like(x)
+        with torch.cuda.device(self.device):
+            self._check(fn(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def blur(self, x):
+        return self._op(self.lib.tvdeblur_op_blur, x, "x")
+
+    def blur_adjoint(self, x):
+        return self._op(self.lib.tvdeblur_op_blur_adjoint, x, "x")
+
+    def setup(self, uk, alpha, beta, precond="x_d"):
+        import torch
+        self._img(uk, "uk")
+        with torch.cuda.device(self.device):
+            self._check(self.lib.tvdeblur_op_setup(self.h, _ptr(uk), float(alpha), float(beta), PRECOND[precond]))
+
+    def normal(self, x):
+        return self._op(self.lib.tvdeblur_op_normal, x, "x")
+
+    def precond(self, r):
+        return self._op(self.lib.tvdeblur_op_precond, r, "r")
+
+    def export(self, which):
+        import torch
+        out = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            self._check(self.lib.tvdeblur_op_export(self.h, EXPORT[which], _ptr(out)))
+        return out

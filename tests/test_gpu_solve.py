@@ -1,0 +1,191 @@
+"""GPU parity of the whole fixed-point / PCG method against the FP64 oracle,
+through the C-ABI, plus edge cases and error paths.
+
+Bars (relative 2-norm error of the restored image against the oracle's):
+FP64 <= 1e-10, FP32-mixed <= 1e-5.  Where the GPU's own stopping decisions
+could differ from the oracle's at a borderline residual, the GPU is also
+run in replay mode with the ORACLE's per-step iteration counts.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1011_5964_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+AR, R = "antireflective", "reflective"
+BAR = {"f64": 1e-10, "f32_mixed": 1e-5}
+
+
+def dev(a, prec):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu_solve(p, prec, variant="x_d", replay=None, n_outer=None, **kw):
+    from paper_1011_5964_amd.lib import TVDeblur
+    ny, nx = p.v.shape
+    h = TVDeblur(ny, nx, prec)
+    h.set_psf(p.psf)
+    h.set_bc(p.bc)
+    u, st = h.solve(dev(p.v, prec), p.alpha, p.beta, n_outer or p.n_outer, p.inner_tol, p.max_inner,
+                    variant, replay=replay, **kw)
+    return host(u), st
+
+
+def oracle_solve(p, variant="x_d", v=None, n_outer=None):
+    return O.fp_solve(p.v if v is None else v, p.psf, p.bc, p.alpha, p.beta, n_outer or p.n_outer,
+                      p.inner_tol, p.max_inner, variant)
+
+
+def check_parity(p, prec, variant="x_d", n_outer=None):
+    vq = host(dev(p.v, prec))                     # input as the GPU holds it
+    uo, so = oracle_solve(p, variant, v=vq, n_outer=n_outer)
+    ug, sg = gpu_solve(p, prec, variant, n_outer=n_outer)
+    print(f"oracle iters {so['inner_iters']}\ngpu    iters {sg['inner_iters']}", flush=True)
+    if sg["inner_iters"] == so["inner_iters"]:
+        err = rel2(ug, uo)
+        print(f"rel err {err:.3e}", flush=True)
+        if err <= BAR[prec]:
+            return err, so, sg
+    ur, sr = gpu_solve(p, prec, variant, replay=so["inner_iters"], n_outer=n_outer)
+    assert sr["inner_iters"] == so["inner_iters"]
+    err = rel2(ur, uo)
+    print(f"replay rel err {err:.3e}", flush=True)
+    assert err <= BAR[prec]
+    # the free-running GPU solve stops within one iteration of the oracle per step
+    assert all(abs(a - b) <= 1 for a, b in zip(sg["inner_iters"], so["inner_iters"]))
+    return err, so, sg
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+def test_c1_anti_reflective(prec):
+    """64^2, 8 shapes, 9x9 Gaussian s=1.5, AR, X_D, alpha 1e-3, beta 0.1, 10 steps."""
+    print(f"case c1 {prec}", flush=True)
+    check_parity(synth.config("c1"), prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("variant", ["none", "diag", "x", "d_x", "x_d"])
+def test_variants_small_ragged(bc, variant, prec):
+    """Every preconditioner on a ragged 45 x 38 image (several tiles plus a
+    tail) with a non-separable PSF for the reflective case."""
+    print(f"case variants {bc} {variant} {prec}", flush=True)
+    p = synth.small_problem(n=38, ny=45, psf_size=7, sigma=1.3, bc=bc, n_outer=3, alpha=2e-3, beta=0.1)
+    if bc == R:
+        p.psf = synth.disk_psf(3)
+    check_parity(p, prec, variant)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+def test_c2_both_bcs(prec):
+    """256^2, 32 shapes, 15x15 Gaussian s=2.5, alpha 5e-4, beta 0.05 -- 6 of
+    the 20 fixed-point steps (the oracle's time budget), both BCs."""
+    for name in ("c2_ar", "c2_r"):
+        print(f"case {name} {prec}", flush=True)
+        check_parity(synth.config(name), prec, n_outer=6)
+
+
+@pytest.mark.slow
+def test_m512_fp32_mixed_full():
+    """The benchmark workload: 512^2, 21x21 Gaussian s=3, AR, X_D, 15 steps,
+    FP32-mixed, against the FP64 oracle."""
+    print("case m512 f32_mixed", flush=True)
+    err, so, sg = check_parity(synth.config("m512"), "f32_mixed")
+    print(f"m512 rel err {err:.3e} iters {sum(sg['inner_iters'])}", flush=True)
+
+
+def test_identity_psf_alpha_zero_returns_v():
+    p = synth.small_problem(n=20)
+    p.psf = np.ones((1, 1))
+    p.alpha = 0.0
+    for prec in ("f64", "f32_mixed"):
+        u, st = gpu_solve(p, prec, n_outer=2)
+        np.testing.assert_array_equal(u, host(dev(p.v, prec)))
+        assert st["inner_iters"] == [0, 0]
+
+
+def test_constant_image_is_fixed_point():
+    p = synth.small_problem(n=24)
+    p.v = np.full((24, 24), 0.3)
+    u, st = gpu_solve(p, "f64", n_outer=2)
+    np.testing.assert_allclose(u, 0.3, atol=1e-13)
+
+
+def test_minimal_image_and_largest_psf():
+    """3 x 3 image with a 3 x 3 PSF; 9 x 9 image with the largest AR PSF
+    (half-width n-1 = 8, 17 x 17)."""
+    for n, size in ((3, 3), (9, 17)):
+        p = synth.small_problem(n=n, psf_size=5, sigma=1.0, n_outer=2)
+        p.psf = synth.gaussian_psf(size, 2.0)
+        print(f"case tiny n={n} psf={size}", flush=True)
+        check_parity(p, "f64", n_outer=2)
+
+
+def test_error_paths():
+    from paper_1011_5964_amd.lib import TVDeblur, TvdError
+    h = TVDeblur(16, 16, "f64")
+    v = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(TvdError) as e:
+        h.solve(v, 1e-3, 0.1, 2)
+    assert e.value.name == "TVD_ESTATE"
+    bad = synth.gaussian_psf(5, 1.0)
+    bad[0, 1] += 1e-3
+    bad /= bad.sum()
+    with pytest.raises(TvdError) as e:
+        h.set_psf(bad)
+    assert e.value.name == "TVD_ENOTSYM"
+    with pytest.raises(TvdError) as e:
+        h.set_psf(2 * synth.gaussian_psf(5, 1.0))
+    assert e.value.name == "TVD_ENORM"
+    h.set_bc("antireflective")
+    with pytest.raises(TvdError) as e:
+        h.set_psf(synth.gaussian_psf(33, 4.0))
+    assert e.value.name == "TVD_ESIZE"
+    h.set_psf(synth.gaussian_psf(5, 1.0))
+    with pytest.raises(TvdError) as e:
+        h.solve(v, -1.0, 0.1, 2)
+    assert e.value.name == "TVD_EINVAL"
+    # NaN data makes the PCG curvature NaN: reported as breakdown, no crash
+    vn = v.clone()
+    vn[3, 4] = float("nan")
+    with pytest.raises(TvdError) as e:
+        h.solve(vn, 1e-3, 0.1, 2)
+    assert e.value.name == "TVD_EBREAKDOWN"
+
+
+def test_iterates_checkpoint_and_warm_start():
+    p = synth.small_problem(n=32, n_outer=4)
+    u, st = gpu_solve(p, "f64")
+    its = torch.empty((p.n_outer + 1, 32, 32), dtype=torch.float64, device="cuda")
+    u2, st2 = gpu_solve(p, "f64", iterates=its)
+    np.testing.assert_array_equal(u, u2)
+    np.testing.assert_array_equal(host(its[0]), p.v)
+    np.testing.assert_array_equal(host(its[-1]), u)
+    # resuming from the checkpoint u^2 for 2 steps reproduces u^4
+    from paper_1011_5964_amd.lib import TVDeblur
+    h = TVDeblur(32, 32, "f64")
+    h.set_psf(p.psf)
+    h.set_bc(p.bc)
+    u3, _ = h.solve(dev(p.v, "f64"), p.alpha, p.beta, 2, p.inner_tol, p.max_inner, u0=its[2].contiguous())
+    np.testing.assert_allclose(host(u3), u, rtol=0, atol=1e-14)
+
+
+def test_run_to_run_determinism():
+    p = synth.config("c1")
+    a, sa = gpu_solve(p, "f32_mixed")
+    b, sb = gpu_solve(p, "f32_mixed")
+    np.testing.assert_array_equal(a, b)
+    assert sa["inner_iters"] == sb["inner_iters"]
