@@ -61,10 +61,12 @@ typedef struct tvdeblur_handle* tvdeblur_t;
 /* precision of a handle */
 #define TVD_F64        0     /* all vectors and arithmetic in IEEE double */
 #define TVD_F32_MIXED  1     /* float vectors, convolution, stencil and
-                                transforms; every inner product, the CG
-                                scalars, the stopping test, the fixed-point
-                                change and the preconditioner eigenvalue
-                                setup in double */
+                                transforms inside PCG; every inner product,
+                                the CG scalars, the stopping test, the
+                                fixed-point change, the preconditioner
+                                eigenvalue setup, b = H^T v and the residual
+                                b - A u^k that starts each fixed-point step
+                                (iterative refinement) in double */
 
 /* boundary condition of the blur H (Section 2) */
 #define TVD_BC_REFLECTIVE      1
@@ -165,6 +167,26 @@ int tvdeblur_op_precond(tvdeblur_t h, const void* r_dev, void* z_dev);
  * doubles: 0 = kappa, 1 = scaling s (D^{-1/2}, or 1), 2 = eigenvalues mu,
  * 3 = lambda_H (PSF symbol on the BC grid), 4 = D. */
 int tvdeblur_op_export(tvdeblur_t h, int which, void* dst_dev);
+
+/* ---- kernel timing (HIP events on the handle's stream) ---- */
+
+#define TVD_KTIME_KINDS 8
+typedef struct {
+    int    n_kinds;                         /* entries filled */
+    char   name[TVD_KTIME_KINDS][24];       /* kernel class */
+    long long launches[TVD_KTIME_KINDS];    /* launches timed */
+    double total_ms[TVD_KTIME_KINDS];       /* summed event-to-event time */
+} tvd_kernel_times;
+
+/* enable != 0: from now on every kernel launch of tvdeblur_solve is
+ * bracketed by a pair of HIP events on the handle's stream and its duration
+ * accumulated per kernel class (band operator, forward row transform, column
+ * transform, inverse row transform, residual, setup, other); the counters
+ * are reset.  enable == 0 stops recording.  Costs one event pair per launch. */
+int tvdeblur_set_profiling(tvdeblur_t h, int enable);
+
+/* Copy the accumulated per-class counts and times into *out (host). */
+int tvdeblur_get_kernel_times(tvdeblur_t h, tvd_kernel_times* out);
 
 #ifdef __cplusplus
 }

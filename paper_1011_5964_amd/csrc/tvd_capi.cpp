@@ -77,6 +77,85 @@ class SolverBase {
     virtual void op_normal(const void* x, void* y) = 0;
     virtual void op_precond(const void* r, void* z) = 0;
     virtual void op_export(int which, void* dst) = 0;
+    virtual void set_profiling(bool on) = 0;
+    virtual void get_times(tvd_kernel_times* out) = 0;
+};
+
+// Per-class kernel timing with pairs of HIP events around launches.
+class KernelTimer {
+   public:
+    enum Kind { kBand = 0, kRowFwd, kCol, kRowInv, kResidual, kSetup, kOther, kKinds };
+    ~KernelTimer() {
+        for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+    }
+    void enable(bool on) {
+        on_ = on;
+        for (int k = 0; k < kKinds; ++k) {
+            count_[k] = 0;
+            ms_[k] = 0.0;
+        }
+        pending_.clear();
+        used_ = 0;
+    }
+    bool on() const { return on_; }
+    // returns the event to record before a launch (nullptr when off)
+    void begin(Kind k, hipStream_t s) {
+        if (!on_) return;
+        cur_ = k;
+        e0_ = get();
+        (void)hipEventRecord(e0_, s);
+    }
+    void end(hipStream_t s) {
+        if (!on_) return;
+        hipEvent_t e1 = get();
+        (void)hipEventRecord(e1, s);
+        pending_.push_back({cur_, e0_, e1});
+    }
+    // after a stream synchronisation: harvest all pending pairs
+    void harvest() {
+        for (const auto& p : pending_) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                ms_[p.kind] += ms;
+                count_[p.kind] += 1;
+            }
+        }
+        pending_.clear();
+        used_ = 0;
+    }
+    void fill(tvd_kernel_times* out) const {
+        static const char* names[kKinds] = {"band_normal", "row_forward", "column", "row_inverse",
+                                            "residual", "setup", "other"};
+        std::memset(out, 0, sizeof(*out));
+        out->n_kinds = kKinds;
+        for (int k = 0; k < kKinds; ++k) {
+            std::strncpy(out->name[k], names[k], sizeof(out->name[k]) - 1);
+            out->launches[k] = count_[k];
+            out->total_ms[k] = ms_[k];
+        }
+    }
+
+   private:
+    struct Pair {
+        int kind;
+        hipEvent_t a, b;
+    };
+    hipEvent_t get() {
+        if (used_ == pool_.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) throw ApiError{TVD_EDEVICE, "hipEventCreate failed"};
+            pool_.push_back(e);
+        }
+        return pool_[used_++];
+    }
+    bool on_ = false;
+    int cur_ = 0;
+    hipEvent_t e0_{};
+    std::vector<hipEvent_t> pool_;
+    size_t used_ = 0;
+    std::vector<Pair> pending_;
+    long long count_[kKinds] = {};
+    double ms_[kKinds] = {};
 };
 
 template <typename T>
@@ -121,17 +200,29 @@ class Solver final : public SolverBase {
         Hx_ = geo_.upload<T>(hx, s_);
         HTy_ = geo_.upload<T>(hty, s_);
         HTx_ = geo_.upload<T>(htx, s_);
+        HyD_ = geo_.upload<double>(hy, s_);
+        HxD_ = geo_.upload<double>(hx, s_);
+        HTyD_ = geo_.upload<double>(hty, s_);
+        HTxD_ = geo_.upload<double>(htx, s_);
         fused_ = false;
         if (rank_ == 1) {
             Ky_ = geo_.upload<T>(ky, s_);
             Kx_ = geo_.upload<T>(kx, s_);
+            KyD_ = geo_.upload<double>(ky, s_);
+            KxD_ = geo_.upload<double>(kx, s_);
             BandArgs<T> probe = band_base();
             probe.wy = 2 * my_;
             probe.wx = 2 * mx_;
             probe.nterms = 1;
             probe.kap = reinterpret_cast<const T*>(1);
             ty_fused_ = pick_ty(probe);
-            fused_ = ty_fused_ > 0;
+            BandArgsT<T, T, double, T> probe_hp{};
+            probe_hp.wy = 2 * my_;
+            probe_hp.wx = 2 * mx_;
+            probe_hp.nterms = 1;
+            probe_hp.kap = reinterpret_cast<const double*>(1);
+            ty_res_ = pick_ty(probe_hp);
+            fused_ = ty_fused_ > 0 && ty_res_ > 0;
         }
         {
             BandArgs<T> probe = band_base();
@@ -142,7 +233,16 @@ class Solver final : public SolverBase {
             probe.kap = reinterpret_cast<const T*>(1);
             probe.S = reinterpret_cast<const T*>(1);
             ty_ht_ = pick_ty(probe);
-            if (ty_h_ == 0 || ty_ht_ == 0) throw ApiError{TVD_ESIZE, "PSF too large for the device's LDS tile"};
+            BandArgsT<double, T, double, T> probe_hp{};
+            probe_hp.wy = my_;
+            probe_hp.wx = mx_;
+            probe_hp.nterms = rank_;
+            ty_h_hp_ = pick_ty(probe_hp);
+            probe_hp.kap = reinterpret_cast<const double*>(1);
+            probe_hp.S = reinterpret_cast<const T*>(1);
+            ty_ht_hp_ = pick_ty(probe_hp);
+            if (ty_h_ == 0 || ty_ht_ == 0 || ty_h_hp_ == 0 || ty_ht_hp_ == 0)
+                throw ApiError{TVD_ESIZE, "PSF too large for the device's LDS tile"};
         }
         // symbol eigenvalues
         lamh_host_ = symbol_eigenvalues(psf.data(), py, px, ny_, nx_, bc);
@@ -180,7 +280,8 @@ class Solver final : public SolverBase {
         Z_ = A(N_);
         T1_ = A(N_);
         T2_ = A(N_);
-        B_ = A(N_);
+        BD_ = D(N_);
+        TmpD_ = D(N_);
         Kap_ = A(N_);
         Sap_ = A(N_);
         MuInv_ = A(N_);
@@ -198,7 +299,8 @@ class Solver final : public SolverBase {
         LamD_ = D(N_);
         Mu_ = D(N_);
         nb_band_ = band_blocks(ny_, nx_, fused_ ? ty_fused_ : ty_ht_);
-        const int cap = std::max({nb_band_, gx_.blocks, gy_.blocks, 1024, 1024});
+        nb_res_ = band_blocks(ny_, nx_, fused_ ? ty_res_ : ty_ht_hp_);
+        const int cap = std::max({nb_band_, nb_res_, gx_.blocks, gy_.blocks, 1024});
         pq_ = D(cap);
         rr_[0] = D(cap);
         rr_[1] = D(cap);
@@ -275,6 +377,81 @@ class Solver final : public SolverBase {
         }
     }
 
+    // b = H^T v with FP64 coefficients and accumulation (stored in FP64).
+    void rhs_hp(const T* v) {
+        BandArgsT<T, T, double, double> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.wy = my_;
+        a.wx = mx_;
+        a.nterms = rank_;
+        a.By = HTyD_;
+        a.Bx = HTxD_;
+        a.X = v;
+        a.Y = BD_;
+        TVD_HIP(launch_band(a, pick_ty(a), s_, nullptr));
+    }
+
+    // Iterative-refinement residual r = b - A x (FP64 coefficients,
+    // diffusivity and accumulation; r rounded to the working precision),
+    // with ||r||^2 partials.  One per fixed-point step.
+    void residual_hp(const T* x, T* r, double* rr_out) {
+        timer_.begin(KernelTimer::kResidual, s_);
+        residual_hp_launch(x, r, rr_out);
+        timer_.end(s_);
+    }
+    void residual_hp_launch(const T* x, T* r, double* rr_out) {
+        if (fused_) {
+            BandArgsT<T, T, double, T> a{};
+            a.ny = ny_;
+            a.nx = nx_;
+            a.wy = 2 * my_;
+            a.wx = 2 * mx_;
+            a.nterms = 1;
+            a.By = KyD_;
+            a.Bx = KxD_;
+            a.X = x;
+            a.kap = Kapd_;
+            a.alpha = alpha_;
+            a.Bvec = BD_;
+            a.Y = r;
+            a.dot_part = rr_out;
+            a.dotmode = 2;
+            a.st = st_;
+            TVD_HIP(launch_band(a, ty_res_, s_, nullptr));
+        } else {
+            BandArgsT<T, T, double, double> h{};
+            h.ny = ny_;
+            h.nx = nx_;
+            h.wy = my_;
+            h.wx = mx_;
+            h.nterms = rank_;
+            h.By = HyD_;
+            h.Bx = HxD_;
+            h.X = x;
+            h.Y = TmpD_;
+            TVD_HIP(launch_band(h, pick_ty(h), s_, nullptr));
+            BandArgsT<double, T, double, T> a{};
+            a.ny = ny_;
+            a.nx = nx_;
+            a.wy = my_;
+            a.wx = mx_;
+            a.nterms = rank_;
+            a.By = HTyD_;
+            a.Bx = HTxD_;
+            a.X = TmpD_;
+            a.kap = Kapd_;
+            a.alpha = alpha_;
+            a.S = x;
+            a.Bvec = BD_;
+            a.Y = r;
+            a.dot_part = rr_out;
+            a.dotmode = 2;
+            a.st = st_;
+            TVD_HIP(launch_band(a, ty_ht_hp_, s_, nullptr));
+        }
+    }
+
     // PCG direction update fused with q = A p and <p, q> partials.
     void normal_apply_update(int it) {
         const T* pold = Pb_[(it + 1) & 1];
@@ -328,6 +505,11 @@ class Solver final : public SolverBase {
 
     // Per-step setup from u^k: kappa, D, s, mu.
     void setup(const T* uk, double alpha, double beta, int variant) {
+        timer_.begin(KernelTimer::kSetup, s_);
+        setup_launch(uk, alpha, beta, variant);
+        timer_.end(s_);
+    }
+    void setup_launch(const T* uk, double alpha, double beta, int variant) {
         alpha_ = alpha;
         beta_ = beta;
         variant_ = variant;
@@ -366,8 +548,8 @@ class Solver final : public SolverBase {
         std::memset(&st, 0, sizeof(st));
         st.all_converged = 1;
         T* iters_out = static_cast<T*>(p.iterates_dev);
-        // b = H^T v, u^0
-        blur_apply(v, B_, true);
+        // b = H^T v (FP64), u^0
+        rhs_hp(v);
         TVD_HIP(hipMemcpyAsync(U_, p.u0_dev ? p.u0_dev : vv, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
         float ms_setup = 0, ms_inner = 0;
         int prev_iters = 8;
@@ -383,6 +565,7 @@ class Solver final : public SolverBase {
             TVD_HIP(hipEventRecord(ev_c_, s_));
             TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
             TVD_HIP(hipStreamSynchronize(s_));
+            timer_.harvest();
             float a = 0, b = 0;
             TVD_HIP(hipEventElapsedTime(&a, ev_a_, ev_b_));
             TVD_HIP(hipEventElapsedTime(&b, ev_b_, ev_c_));
@@ -421,19 +604,19 @@ class Solver final : public SolverBase {
         TVD_HIP(hipMemcpyAsync(X_, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
         const bool transform = variant_ >= TVD_PREC_X;
         T* dinv = variant_ == TVD_PREC_DIAG ? Sap_ : nullptr;
-        // r_0 = b - A x_0, ||r_0||^2 partials
-        normal_apply(X_, R_, B_, rr_[0]);
-        int last_rr_n = nb_band_;
+        // r_0 = b - A x_0 in FP64 arithmetic, ||r_0||^2 partials
+        residual_hp(X_, R_, rr_[0]);
+        int last_rr_n = nb_res_;
         const double* last_rr = rr_[0];
         if (transform) {
             rowpass(0, false, R_, nullptr, 0);
-            colpass(0, true, nb_band_, rr_[0]);
+            colpass(0, true, nb_res_, rr_[0]);
             rowpass_inv(Z_, R_, rz_[0]);
             n_rz_ = gx_.blocks;
         } else {
             int nb = 0;
             TVD_HIP(launch_diag_update<T>(int(N_), X_, R_, nullptr, nullptr, dinv, Z_, nullptr, 0, nullptr, 0, rr_[1],
-                                          rz_[0], st_, 0, 0, 1, rr_[0], nb_band_, &nb, s_));
+                                          rz_[0], st_, 0, 0, 1, rr_[0], nb_res_, &nb, s_));
             n_rz_ = nb;
             last_rr = rr_[1];
             last_rr_n = nb;
@@ -462,6 +645,7 @@ class Solver final : public SolverBase {
             if (it == next_poll && it < maxit) {
                 TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
                 TVD_HIP(hipStreamSynchronize(s_));
+                timer_.harvest();
                 if (host_st_->done) break;
                 next_poll = it + 2;
             }
@@ -492,7 +676,9 @@ class Solver final : public SolverBase {
         a.part_out = part_out;
         a.st = st_;
         a.iter = it;
+        timer_.begin(KernelTimer::kRowFwd, s_);
         TVD_HIP(launch_rowpass<T>(a, s_));
+        timer_.end(s_);
     }
     void colpass(int it, bool check, int n_rr, const double* rr = nullptr) {
         ColPassArgs<T> a{};
@@ -508,7 +694,9 @@ class Solver final : public SolverBase {
         a.n_rr = n_rr;
         a.st = st_;
         a.iter = it;
+        timer_.begin(KernelTimer::kCol, s_);
         TVD_HIP(launch_colpass<T>(a, s_));
+        timer_.end(s_);
     }
     void rowpass_inv(T* z, T* r, double* rz_out) {
         RowPassArgs<T> a{};
@@ -523,7 +711,9 @@ class Solver final : public SolverBase {
         a.dst = z;
         a.part_out = rz_out;
         a.st = st_;
+        timer_.begin(KernelTimer::kRowInv, s_);
         TVD_HIP(launch_rowpass<T>(a, s_));
+        timer_.end(s_);
     }
 
     // -------------------------------------------------------- op entry points
@@ -570,7 +760,11 @@ class Solver final : public SolverBase {
         TVD_HIP(hipStreamSynchronize(s_));
     }
 
+    void set_profiling(bool on) override { timer_.enable(on); }
+    void get_times(tvd_kernel_times* out) override { timer_.fill(out); }
+
    private:
+    KernelTimer timer_;
     static void append(std::vector<double>& dst, const std::vector<double>& src) {
         dst.insert(dst.end(), src.begin(), src.end());
     }
@@ -592,9 +786,14 @@ class Solver final : public SolverBase {
         a.nx = nx_;
         return a;
     }
-    void launch(const BandArgs<T>& a, int ty) { TVD_HIP(launch_band<T>(a, ty, s_, nullptr)); }
+    void launch(const BandArgs<T>& a, int ty) {
+        timer_.begin(a.kap ? KernelTimer::kBand : KernelTimer::kOther, s_);
+        TVD_HIP(launch_band<T>(a, ty, s_, nullptr));
+        timer_.end(s_);
+    }
     // Tallest band tile (16, else 8) whose LDS fits the device; 0 if none.
-    int pick_ty(const BandArgs<T>& a) const {
+    template <typename A>
+    int pick_ty(const A& a) const {
         for (int ty : {16, 8})
             if (band_lds_bytes(a, ty) + kStaticLds <= max_lds_) return ty;
         return 0;
@@ -645,6 +844,10 @@ class Solver final : public SolverBase {
     bool fused_ = false;
     int ty_fused_ = 0, ty_h_ = 0, ty_ht_ = 0;
     const T *Hy_ = nullptr, *Hx_ = nullptr, *HTy_ = nullptr, *HTx_ = nullptr, *Ky_ = nullptr, *Kx_ = nullptr;
+    const double *HyD_ = nullptr, *HxD_ = nullptr, *HTyD_ = nullptr, *HTxD_ = nullptr, *KyD_ = nullptr,
+                 *KxD_ = nullptr;
+    int ty_res_ = 0, ty_h_hp_ = 0, ty_ht_hp_ = 0, nb_res_ = 0;
+    double *BD_ = nullptr, *TmpD_ = nullptr;
     std::vector<double> lamh_host_;
     const double *lamh2_ = nullptr, *lamh_ = nullptr;
     AxisPlan<T> planX_{}, planY_{};
@@ -652,7 +855,7 @@ class Solver final : public SolverBase {
     const double *Wy_ = nullptr, *Puy_ = nullptr, *Puly_ = nullptr, *Ply_ = nullptr;
     const double *Wx_ = nullptr, *Pux_ = nullptr, *Pulx_ = nullptr, *Plx_ = nullptr;
     T *U_ = nullptr, *X_ = nullptr, *R_ = nullptr, *Pb_[2] = {nullptr, nullptr}, *Q_ = nullptr, *Z_ = nullptr;
-    T *T1_ = nullptr, *T2_ = nullptr, *B_ = nullptr, *Kap_ = nullptr, *Sap_ = nullptr, *MuInv_ = nullptr,
+    T *T1_ = nullptr, *T2_ = nullptr, *Kap_ = nullptr, *Sap_ = nullptr, *MuInv_ = nullptr,
       *Tmp_ = nullptr;
     double *Kapd_ = nullptr, *Smu_ = nullptr, *Dd_ = nullptr, *Aop_[3] = {}, *Bop_[3] = {}, *Yg_[3] = {},
            *Zg_[3] = {}, *Sd_ = nullptr, *LamX_ = nullptr, *LamY_ = nullptr, *LamD_ = nullptr, *Mu_ = nullptr;
@@ -865,6 +1068,22 @@ int tvdeblur_op_precond(tvdeblur_t h, const void* r_dev, void* z_dev) {
         int rc = ensure_built(h);
         if (rc) return rc;
         h->solver->op_precond(r_dev, z_dev);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_set_profiling(tvdeblur_t h, int enable) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    return guarded(h, [&]() {
+        h->solver->set_profiling(enable != 0);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_get_kernel_times(tvdeblur_t h, tvd_kernel_times* out) {
+    if (!h || !out) return fail(h, TVD_EINVAL, "NULL argument");
+    return guarded(h, [&]() {
+        h->solver->get_times(out);
         return TVD_OK;
     });
 }

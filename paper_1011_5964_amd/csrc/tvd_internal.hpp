@@ -56,28 +56,33 @@ struct LineGeom {
 
 // Banded Kronecker operator  Y = sum_r (By_r (x) Bx_r) X  (+ alpha L(S) X,
 // optional p-update of the input, residual form and FP64 dot partials).
-template <typename T>
-struct BandArgs {
+// TX: band input (and p-update) storage, TS: separate stencil input storage,
+// TA: band coefficients, diffusivity, residual right-hand side and the
+// accumulation type, TY: output storage.
+template <typename TX, typename TS, typename TA, typename TY>
+struct BandArgsT {
     int ny, nx;
     int wy, wx, nterms;
-    const T* By;           // [nterms][ny][2wy+1]
-    const T* Bx;           // [nterms][nx][2wx+1]
-    const T* X;            // input, or p_old when Z != nullptr
-    const T* Z;            // p-update: X_eff = Z + beta X
-    T* Xnew;               // receives X_eff (own tile) when Z != nullptr
+    const TA* By;          // [nterms][ny][2wy+1]
+    const TA* Bx;          // [nterms][nx][2wx+1]
+    const TX* X;           // input, or p_old when Z != nullptr
+    const TX* Z;           // p-update: X_eff = Z + beta X
+    TX* Xnew;              // receives X_eff (own tile) when Z != nullptr
     const double* rz_new;  // beta = sum(rz_new)/sum(rz_old); rz_old == nullptr -> beta = 0
     const double* rz_old;
     int n_rz;
-    const T* kap;          // stencil diffusivity (nullptr: no stencil)
+    const TA* kap;         // stencil diffusivity (nullptr: no stencil)
     double alpha;
-    const T* S;            // stencil input; nullptr -> the (updated) band input
-    const T* Bvec;         // residual form Y = Bvec - result when non-null
-    T* Y;
+    const TS* S;           // stencil input; nullptr -> the (updated) band input
+    const TA* Bvec;        // residual form Y = Bvec - result when non-null
+    TY* Y;
     double* dot_part;      // per-block partials
     int dotmode;           // 0 none, 1 <stencil input, result>, 2 <Y, Y>
     const PcgState* st;    // exit when st->done (nullable)
     int tile_y;            // tile height (8 or 16), chosen by the launcher
 };
+template <typename T>
+using BandArgs = BandArgsT<T, T, T, T>;
 
 template <typename T>
 struct RowPassArgs {
@@ -134,11 +139,11 @@ struct GemmProblem {
 // ---- kernel launchers (tvd_kernels.hip) ----
 // Launch with tile height ty (8 or 16); band_lds_bytes gives the dynamic
 // LDS the launch needs, band_blocks the grid size (= number of partials).
-template <typename T>
-hipError_t launch_band(const BandArgs<T>& a, int ty, hipStream_t s, int* nblocks_out);
+template <typename TX, typename TS, typename TA, typename TY>
+hipError_t launch_band(const BandArgsT<TX, TS, TA, TY>& a, int ty, hipStream_t s, int* nblocks_out);
 int band_blocks(int ny, int nx, int ty);
-template <typename T>
-size_t band_lds_bytes(const BandArgs<T>& a, int ty);
+template <typename TX, typename TS, typename TA, typename TY>
+size_t band_lds_bytes(const BandArgsT<TX, TS, TA, TY>& a, int ty);
 template <typename T>
 hipError_t launch_rowpass(const RowPassArgs<T>& a, hipStream_t s);
 template <typename T>

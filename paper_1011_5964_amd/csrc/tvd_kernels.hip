@@ -69,8 +69,8 @@ __device__ double sum_partials(const double* p, int n, double* red) {
 // The boundary condition of the blur is folded into the band coefficients,
 // so the kernel only sees zeros outside the image.
 // ------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBandThreads) k_band(BandArgs<T> a) {
+template <typename TX, typename TS, typename T, typename TOut>
+__global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[17];
     if (a.st && a.st->done) return;
@@ -114,11 +114,12 @@ __global__ void __launch_bounds__(kBandThreads) k_band(BandArgs<T> a) {
         if (gi >= 0 && gi < ny && gj >= 0 && gj < nx) {
             const size_t g = size_t(gi) * nx + gj;
             if (upd) {
-                v = a.Z[g];
-                if (use_old) v += beta * a.X[g];
-                if (r >= hy && r < hy + TY && c >= hx && c < hx + kBandTX) a.Xnew[g] = v;
+                TX w = a.Z[g];
+                if (use_old) w += TX(beta) * a.X[g];
+                if (r >= hy && r < hy + TY && c >= hx && c < hx + kBandTX) a.Xnew[g] = w;
+                v = T(w);
             } else {
-                v = a.X[g];
+                v = T(a.X[g]);
             }
         }
         P[k] = v;
@@ -143,7 +144,7 @@ __global__ void __launch_bounds__(kBandThreads) k_band(BandArgs<T> a) {
         for (int k = tid; k < (TY + 2) * SW; k += kBandThreads) {
             const int r = k / SW, c = k - r * SW;
             const int gi = i0 - 1 + r, gj = j0 - 1 + c;
-            Sl[k] = (gi >= 0 && gi < ny && gj >= 0 && gj < nx) ? a.S[size_t(gi) * nx + gj] : T(0);
+            Sl[k] = (gi >= 0 && gi < ny && gj >= 0 && gj < nx) ? T(a.S[size_t(gi) * nx + gj]) : T(0);
         }
     }
     __syncthreads();
@@ -216,9 +217,10 @@ __global__ void __launch_bounds__(kBandThreads) k_band(BandArgs<T> a) {
             cen = P[(hy + ti) * PW + hx + tx];
         }
         if (a.Bvec) res = a.Bvec[g] - res;
-        a.Y[g] = res;
-        if (a.dotmode == 1) dot += double(cen) * double(res);
-        else if (a.dotmode == 2) dot += double(res) * double(res);
+        const TOut out = TOut(res);
+        a.Y[g] = out;
+        if (a.dotmode == 1) dot += double(cen) * double(out);
+        else if (a.dotmode == 2) dot += double(out) * double(out);
     }
     if (a.dotmode) {
         const double s = block_sum(dot, red);
@@ -792,8 +794,8 @@ int band_blocks(int ny, int nx, int ty) {
     return ((nx + kBandTX - 1) / kBandTX) * ((ny + ty - 1) / ty);
 }
 
-template <typename T>
-size_t band_lds_bytes(const BandArgs<T>& a, int ty) {
+template <typename TX, typename TS, typename T, typename TY>
+size_t band_lds_bytes(const BandArgsT<TX, TS, T, TY>& a, int ty) {
     const bool sten_tile = a.kap != nullptr && a.S == nullptr;
     const int hy = std::max(a.wy, sten_tile ? 1 : 0), hx = std::max(a.wx, sten_tile ? 1 : 0);
     size_t elems = size_t(ty + 2 * hy) * (kBandTX + 2 * hx) + size_t(ty + 2 * a.wy) * kBandTX +
@@ -802,18 +804,18 @@ size_t band_lds_bytes(const BandArgs<T>& a, int ty) {
     return elems * sizeof(T);
 }
 
-template <typename T>
-hipError_t launch_band(const BandArgs<T>& a0, int ty, hipStream_t s, int* nblocks_out) {
+template <typename TX, typename TS, typename T, typename TY>
+hipError_t launch_band(const BandArgsT<TX, TS, T, TY>& a0, int ty, hipStream_t s, int* nblocks_out) {
     if (ty != 8 && ty != 16) return hipErrorInvalidValue;
-    BandArgs<T> a = a0;
+    BandArgsT<TX, TS, T, TY> a = a0;
     a.tile_y = ty;
     const size_t lds = band_lds_bytes(a, ty);
     dim3 grid((a.nx + kBandTX - 1) / kBandTX, (a.ny + ty - 1) / ty);
     if (nblocks_out) *nblocks_out = grid.x * grid.y;
     if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band<T>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band<TX, TS, T, TY>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    hipLaunchKernelGGL(k_band<T>, grid, dim3(kBandThreads), lds, s, a);
+    hipLaunchKernelGGL((k_band<TX, TS, T, TY>), grid, dim3(kBandThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -922,8 +924,8 @@ hipError_t launch_cast_to_double(int n, const T* src, double* dst, hipStream_t s
 }
 
 #define TVD_INSTANTIATE(T)                                                                                    \
-    template hipError_t launch_band<T>(const BandArgs<T>&, int, hipStream_t, int*);                           \
-    template size_t band_lds_bytes<T>(const BandArgs<T>&, int);                                               \
+    template hipError_t launch_band<T, T, T, T>(const BandArgs<T>&, int, hipStream_t, int*);                  \
+    template size_t band_lds_bytes<T, T, T, T>(const BandArgs<T>&, int);                                      \
     template LineGeom line_geom<T>(int, int);                                                                 \
     template hipError_t launch_rowpass<T>(const RowPassArgs<T>&, hipStream_t);                                \
     template hipError_t launch_colpass<T>(const ColPassArgs<T>&, hipStream_t);                                \
@@ -941,5 +943,15 @@ hipError_t launch_cast_to_double(int n, const T* src, double* dst, hipStream_t s
 
 TVD_INSTANTIATE(float)
 TVD_INSTANTIATE(double)
+
+// Mixed-precision band operators of the FP32 path: FP64 coefficients and
+// accumulation for the per-step residual b - A u^k and for b = H^T v.
+#define TVD_INSTANTIATE_BAND(TX, TS, TA, TY)                                                                  \
+    template hipError_t launch_band<TX, TS, TA, TY>(const BandArgsT<TX, TS, TA, TY>&, int, hipStream_t, int*); \
+    template size_t band_lds_bytes<TX, TS, TA, TY>(const BandArgsT<TX, TS, TA, TY>&, int);
+
+TVD_INSTANTIATE_BAND(float, float, double, float)
+TVD_INSTANTIATE_BAND(float, float, double, double)
+TVD_INSTANTIATE_BAND(double, float, double, float)
 
 }  // namespace tvd

@@ -28,7 +28,8 @@ MAX_OUTER = 256
 EXPORTED_SYMBOLS = (
     "tvdeblur_create", "tvdeblur_set_psf", "tvdeblur_set_bc", "tvdeblur_solve", "tvdeblur_destroy",
     "tvdeblur_last_error", "tvdeblur_op_blur", "tvdeblur_op_blur_adjoint", "tvdeblur_op_setup",
-    "tvdeblur_op_normal", "tvdeblur_op_precond", "tvdeblur_op_export",
+    "tvdeblur_op_normal", "tvdeblur_op_precond", "tvdeblur_op_export", "tvdeblur_set_profiling",
+    "tvdeblur_get_kernel_times",
 )
 
 
@@ -62,6 +63,11 @@ class Stats(ctypes.Structure):
                 "time_inner_s": self.time_inner_s}
 
 
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("n_kinds", ctypes.c_int), ("name", (ctypes.c_char * 24) * 8),
+                ("launches", ctypes.c_longlong * 8), ("total_ms", ctypes.c_double * 8)]
+
+
 _lib = None
 
 
@@ -86,6 +92,8 @@ def load():
         "tvdeblur_op_normal": [vp, vp, vp],
         "tvdeblur_op_precond": [vp, vp, vp],
         "tvdeblur_op_export": [vp, i, vp],
+        "tvdeblur_set_profiling": [vp, i],
+        "tvdeblur_get_kernel_times": [vp, ctypes.POINTER(KernelTimes)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -174,6 +182,15 @@ class TVDeblur:
             rc = self.lib.tvdeblur_solve(self.h, _ptr(v), _ptr(u), ctypes.byref(p), ctypes.byref(st))
         self._check(rc)
         return u, st.to_dict()
+
+    def set_profiling(self, enable):
+        self._check(self.lib.tvdeblur_set_profiling(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        kt = KernelTimes()
+        self._check(self.lib.tvdeblur_get_kernel_times(self.h, ctypes.byref(kt)))
+        return {kt.name[k].value.decode(): {"launches": int(kt.launches[k]), "total_ms": float(kt.total_ms[k])}
+                for k in range(kt.n_kinds)}
 
     # single operators
     def _op(self, fn, x, name):
