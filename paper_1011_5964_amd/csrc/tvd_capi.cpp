@@ -244,6 +244,21 @@ class Solver final : public SolverBase {
             if (ty_h_ == 0 || ty_ht_ == 0 || ty_h_hp_ == 0 || ty_ht_hp_ == 0)
                 throw ApiError{TVD_ESIZE, "PSF too large for the device's LDS tile"};
         }
+        // Toeplitz-compressed K_x for the x-pass fused into the inverse row
+        // transform (rank-1 PSFs; the column half runs in k_ypass)
+        xpass_ = false;
+        if (fused_ && 2 * my_ <= 32) {
+            const ToeplitzBand tb = compress_band(kx, nx_, 2 * mx_);
+            std::vector<double> d = tb.data;
+            const size_t per16 = 16 / sizeof(T);
+            while (d.size() % per16) d.push_back(0.0);
+            xband_ = geo_.upload<T>(d, s_);
+            xband_len_ = int(d.size());
+            kw_ = tb.w;
+            klo_ = tb.lo;
+            khi_ = tb.hi;
+            xpass_ = true;
+        }
         // symbol eigenvalues
         lamh_host_ = symbol_eigenvalues(psf.data(), py, px, ny_, nx_, bc);
         std::vector<double> l2(lamh_host_.size());
@@ -258,6 +273,24 @@ class Solver final : public SolverBase {
         gy_ = line_geom<T>(nx_, planY_.M);  // column pass: lines are columns
         if (gx_.lds + kStaticLds > max_lds_ || gy_.lds + kStaticLds > max_lds_)
             throw ApiError{TVD_ESIZE, "transform length too large for the device's LDS"};
+        // FFT tables go to LDS next to the buffers when they fit
+        if (gx_.tpu == 0 || gy_.tpu == 0) throw ApiError{TVD_ESIZE, "image side too long for the line transforms"};
+        auto place_tables = [&](AxisPlan<T>& P, LineGeom& g) {
+            const size_t tb = lds_table_bytes<T>(P.blob_len);
+            if (g.lds + tb + kStaticLds <= max_lds_) {
+                P.tables_in_lds = 1;
+                g.lds += tb;
+            }
+        };
+        place_tables(planX_, gx_);
+        place_tables(planY_, gy_);
+        gxi_ = gx_;
+        if (xpass_) {
+            const size_t xb = ((size_t(xband_len_) * sizeof(T) + 1023) / 1024) * 1024;
+            const size_t ylds = (size_t(16 + 4 * my_) * 64 + size_t(18) * 66) * sizeof(T);
+            if (gx_.lds + xb + kStaticLds <= max_lds_ && ylds + kStaticLds <= max_lds_) gxi_.lds += xb;
+            else xpass_ = false;
+        }
         // basis matrices for the eigenvalue setup
         make_basis(ny_, Wy_, Puy_, Puly_, Ply_);
         if (ny_ == nx_) {
@@ -276,6 +309,9 @@ class Solver final : public SolverBase {
         R_ = A(N_);
         Pb_[0] = A(N_);
         Pb_[1] = A(N_);
+        Tb_[0] = A(N_);
+        Tb_[1] = A(N_);
+        W_ = A(N_);
         Q_ = A(N_);
         Z_ = A(N_);
         T1_ = A(N_);
@@ -300,7 +336,7 @@ class Solver final : public SolverBase {
         Mu_ = D(N_);
         nb_band_ = band_blocks(ny_, nx_, fused_ ? ty_fused_ : ty_ht_);
         nb_res_ = band_blocks(ny_, nx_, fused_ ? ty_res_ : ty_ht_hp_);
-        const int cap = std::max({nb_band_, nb_res_, gx_.blocks, gy_.blocks, 1024});
+        const int cap = std::max({nb_band_, nb_res_, gx_.blocks, gy_.blocks, ypass_blocks(ny_, nx_), 1024});
         pq_ = D(cap);
         rr_[0] = D(cap);
         rr_[1] = D(cap);
@@ -450,6 +486,35 @@ class Solver final : public SolverBase {
             a.st = st_;
             TVD_HIP(launch_band(a, ty_ht_hp_, s_, nullptr));
         }
+    }
+
+    // PCG direction update fused with q = A p, column half (the row half
+    // w = (I (x) K_x) z ran inside the inverse row transform).
+    void ypass_update(int it) {
+        YPassArgs<T> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.w = 2 * my_;
+        a.Ky = Ky_;
+        a.wv = W_;
+        a.tmp_old = Tb_[(it + 1) & 1];
+        a.tmp_new = Tb_[it & 1];
+        a.z = Z_;
+        a.p_old = Pb_[(it + 1) & 1];
+        a.p_new = Pb_[it & 1];
+        a.kap = Kap_;
+        a.alpha = alpha_;
+        a.rz_new = rz_[(it - 1) & 1];
+        a.rz_old = it >= 2 ? rz_[it & 1] : nullptr;
+        a.n_rz = n_rz_;
+        a.q = Q_;
+        a.pq_part = pq_;
+        a.st = st_;
+        int nb = 0;
+        timer_.begin(KernelTimer::kBand, s_);
+        TVD_HIP(launch_ypass<T>(a, s_, &nb));
+        timer_.end(s_);
+        n_pq_ = nb;
     }
 
     // PCG direction update fused with q = A p and <p, q> partials.
@@ -608,10 +673,11 @@ class Solver final : public SolverBase {
         residual_hp(X_, R_, rr_[0]);
         int last_rr_n = nb_res_;
         const double* last_rr = rr_[0];
+        const bool xp = transform && xpass_;
         if (transform) {
             rowpass(0, false, R_, nullptr, 0);
             colpass(0, true, nb_res_, rr_[0]);
-            rowpass_inv(Z_, R_, rz_[0]);
+            rowpass_inv(Z_, R_, rz_[0], xp);
             n_rz_ = gx_.blocks;
         } else {
             int nb = 0;
@@ -624,14 +690,15 @@ class Solver final : public SolverBase {
         // polling schedule: first look near the predicted count, then often
         int next_poll = std::max(2, predicted - 1);
         for (int it = 1; it <= maxit; ++it) {
-            normal_apply_update(it);
+            if (xp) ypass_update(it);
+            else normal_apply_update(it);
             if (transform) {
                 rowpass(it, true, R_, rr_[0], 0);
                 last_rr = rr_[0];
                 last_rr_n = gx_.blocks;
                 if (it < maxit) {
                     colpass(it, true, gx_.blocks, rr_[0]);
-                    rowpass_inv(Z_, R_, rz_[it & 1]);
+                    rowpass_inv(Z_, R_, rz_[it & 1], xp);
                 }
             } else {
                 int nb = 0;
@@ -698,13 +765,21 @@ class Solver final : public SolverBase {
         TVD_HIP(launch_colpass<T>(a, s_));
         timer_.end(s_);
     }
-    void rowpass_inv(T* z, T* r, double* rz_out) {
+    void rowpass_inv(T* z, T* r, double* rz_out, bool xpass = false) {
         RowPassArgs<T> a{};
         a.ny = ny_;
         a.nx = nx_;
         a.plan = planX_;
-        a.g = gx_;
+        a.g = xpass ? gxi_ : gx_;
         a.mode = 1;
+        if (xpass) {
+            a.wout = W_;
+            a.xband = xband_;
+            a.xband_len = xband_len_;
+            a.kw = kw_;
+            a.klo = klo_;
+            a.khi = khi_;
+        }
         a.r = r;
         a.s = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
         a.src = T2_;
@@ -725,17 +800,20 @@ class Solver final : public SolverBase {
     void op_setup(const void* uk, double alpha, double beta, int variant) override {
         setup(static_cast<const T*>(uk), alpha, beta, variant);
         TVD_HIP(hipStreamSynchronize(s_));
+        timer_.harvest();
     }
     void op_normal(const void* x, void* y) override {
         if (!have_setup_) throw ApiError{TVD_ESTATE, "op_normal before op_setup"};
         TVD_HIP(launch_init_state(st_, 0.0, s_));
         normal_apply(static_cast<const T*>(x), static_cast<T*>(y), nullptr, nullptr);
         TVD_HIP(hipStreamSynchronize(s_));
+        timer_.harvest();
     }
     void op_precond(const void* r, void* z) override {
         if (!have_setup_) throw ApiError{TVD_ESTATE, "op_precond before op_setup"};
         precond_apply(static_cast<const T*>(r), static_cast<T*>(z));
         TVD_HIP(hipStreamSynchronize(s_));
+        timer_.harvest();
     }
     void op_export(int which, void* dst) override {
         if (which != 3 && !have_setup_) throw ApiError{TVD_ESTATE, "op_export before op_setup"};
@@ -814,6 +892,13 @@ class Solver final : public SolverBase {
         P.pre = t.kind == 2 ? reinterpret_cast<const cx<T>*>(geo_.upload<T>(t.pre, s_)) : nullptr;
         P.post = t.kind == 2 ? reinterpret_cast<const cx<T>*>(geo_.upload<T>(t.post, s_)) : nullptr;
         P.dst_scale = T(t.dst_scale);
+        P.blob = reinterpret_cast<const cx<T>*>(geo_.upload<T>(t.blob, s_));
+        P.blob_len = t.blob_len;
+        P.off_chirp = t.off_chirp;
+        P.off_bf = t.off_bf;
+        P.off_pre = t.off_pre;
+        P.off_post = t.off_post;
+        P.tables_in_lds = 0;  // decided with the launch geometry
     }
     void make_basis(int n, const double*& W, const double*& Pu, const double*& Pul, const double*& Pl) {
         const std::vector<double> phi = basis_matrix(n, bc_);
@@ -847,6 +932,11 @@ class Solver final : public SolverBase {
     const double *HyD_ = nullptr, *HxD_ = nullptr, *HTyD_ = nullptr, *HTxD_ = nullptr, *KyD_ = nullptr,
                  *KxD_ = nullptr;
     int ty_res_ = 0, ty_h_hp_ = 0, ty_ht_hp_ = 0, nb_res_ = 0;
+    bool xpass_ = false;
+    const T* xband_ = nullptr;
+    int xband_len_ = 0, kw_ = 0, klo_ = 0, khi_ = 0;
+    LineGeom gxi_{};
+    T *Tb_[2] = {nullptr, nullptr}, *W_ = nullptr;
     double *BD_ = nullptr, *TmpD_ = nullptr;
     std::vector<double> lamh_host_;
     const double *lamh2_ = nullptr, *lamh_ = nullptr;

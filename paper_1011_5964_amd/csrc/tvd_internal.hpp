@@ -37,12 +37,19 @@ struct AxisPlan {
     int n;          // line length
     int kind;       // 1 = DST-I interior (AR), 2 = DCT-II/III (reflective)
     int L, M, log2M, bluestein;
-    const cx<T>* tw;     // M/2 twiddles exp(-2 pi i t / M)
+    const cx<T>* tw;     // M twiddles exp(-2 pi i t / M)
     const cx<T>* chirp;  // L entries exp(-i pi t^2 / L)      (Bluestein)
     const cx<T>* bf;     // M entries FFT_M(conj chirp, wrapped) / M (Bluestein)
     const cx<T>* pre;    // n entries: DCT-III input weights w_k exp(+i pi k/(2n))
     const cx<T>* post;   // n entries: DCT-II output weights w_k exp(-i pi k/(2n)) / 2
     T dst_scale;         // 1/sqrt(2(n-1))
+    // All tables above, contiguous in one device blob (tw | chirp | bf | pre |
+    // post, each padded to an even count) so a block can copy them into LDS
+    // with 16-byte loads; offsets in complex entries.
+    const cx<T>* blob;
+    int blob_len;        // even
+    int off_chirp, off_bf, off_pre, off_post;
+    int tables_in_lds;   // copy the blob into LDS (if it fits next to the FFT buffers)
 };
 
 // Launch geometry of a line pass.
@@ -105,6 +112,35 @@ struct RowPassArgs {
     double* part_out;       // mode 0: ||r||^2 partials, mode 1: <r,z> partials
     PcgState* st;
     int iter;
+    // mode 1 only: also w = (I (x) K_x) z along the rows held in LDS.
+    // K_x is Toeplitz on rows [klo, khi); xband = [Toeplitz row | rows < klo
+    // | rows >= khi], each 2*kw+1 wide, copied to LDS (xband_len reals).
+    T* wout;                // nullptr: no x-pass
+    const T* xband;
+    int kw, klo, khi, xband_len;
+};
+
+// Column half of the fused normal operator for the PCG direction update:
+// tmp_new = w + beta tmp_old, p_new = z + beta p_old (own tile written),
+// q = (K_y (x) I) tmp_new + alpha L(u^k) p_new, <p_new, q> partials.
+template <typename T>
+struct YPassArgs {
+    int ny, nx, w;
+    const T* Ky;            // [ny][2w+1]
+    const T* wv;            // (I (x) K_x) z of this iteration
+    const T* tmp_old;
+    T* tmp_new;
+    const T* z;
+    const T* p_old;
+    T* p_new;
+    const T* kap;
+    double alpha;
+    const double* rz_new;   // beta = sum(rz_new)/sum(rz_old); rz_old == nullptr -> beta = 0
+    const double* rz_old;
+    int n_rz;
+    T* q;
+    double* pq_part;
+    const PcgState* st;
 };
 
 template <typename T>
@@ -147,9 +183,15 @@ size_t band_lds_bytes(const BandArgsT<TX, TS, TA, TY>& a, int ty);
 template <typename T>
 hipError_t launch_rowpass(const RowPassArgs<T>& a, hipStream_t s);
 template <typename T>
+hipError_t launch_ypass(const YPassArgs<T>& a, hipStream_t s, int* nblocks);
+int ypass_blocks(int ny, int nx);
+template <typename T>
 hipError_t launch_colpass(const ColPassArgs<T>& a, hipStream_t s);
 template <typename T>
 LineGeom line_geom(int lines, int M);
+// LDS bytes reserved for a plan's table blob of blob_len complex entries.
+template <typename T>
+size_t lds_table_bytes(int blob_len);
 
 template <typename T>
 hipError_t launch_diag_update(int n, T* x, T* r, const T* p, const T* q, const T* dinv, T* z,
@@ -191,6 +233,13 @@ std::vector<double> blur_matrix_1d(const std::vector<double>& g, int n, int bc);
 // Band of a dense n x n matrix: out[i*(2w+1) + d + w] = A[i][i+d] (0 outside).
 std::vector<double> band_of(const std::vector<double>& A, int n, int w);
 std::vector<double> transpose(const std::vector<double>& A, int n);
+// Band rows [lo, hi) all equal one Toeplitz row; data = [that row | rows < lo
+// | rows >= hi], each 2w+1 wide (lo = hi = n when no row repeats).
+struct ToeplitzBand {
+    int w, lo, hi;
+    std::vector<double> data;
+};
+ToeplitzBand compress_band(const std::vector<double>& band, int n, int w);
 std::vector<double> matmul_tn(const std::vector<double>& A, const std::vector<double>& B, int n);
 
 // Basis matrix Phi[i*n + k] = phi_k(i) of the transform of the BC.
@@ -202,6 +251,9 @@ struct AxisTables {
     int n, kind, L, M, log2M, bluestein;
     std::vector<double> tw, chirp, bf, pre, post;  // interleaved re, im
     double dst_scale;
+    // tw | chirp | bf | pre | post, each padded to an even number of entries
+    std::vector<double> blob;
+    int off_chirp, off_bf, off_pre, off_post, blob_len;
 };
 AxisTables make_axis_tables(int n, int bc);
 

@@ -39,7 +39,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum of v over the block; every thread gets the result.  red: >= 17 doubles.
-__device__ double block_sum(double v, double* red) {
+__device__ __forceinline__ double block_sum(double v, double* red) {
     v = wave_sum(v);
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
@@ -57,7 +57,7 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // Deterministic sum of n per-block partials, computed redundantly per block.
-__device__ double sum_partials(const double* p, int n, double* red) {
+__device__ __forceinline__ double sum_partials(const double* p, int n, double* red) {
     double s = 0.0;
     for (int k = threadIdx.x; k < n; k += blockDim.x) s += p[k];
     return block_sum(s, red);
@@ -69,6 +69,26 @@ __device__ double sum_partials(const double* p, int n, double* red) {
 // The boundary condition of the blur is folded into the band coefficients,
 // so the kernel only sees zeros outside the image.
 // ------------------------------------------------------------------------
+// Stage `count` elements into LDS with kStageBatch independent global loads in
+// flight per thread (load(k) must not read memory written by store()).
+constexpr int kStageBatch = 8;
+template <typename V, typename Load, typename Store>
+__device__ __forceinline__ void stage_lds(int count, int tid, int nthreads, Load load, Store store) {
+    for (int base = tid; base < count; base += nthreads * kStageBatch) {
+        V v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int k = base + u * nthreads;
+            if (k < count) v[u] = load(k);
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int k = base + u * nthreads;
+            if (k < count) store(k, v[u]);
+        }
+    }
+}
+
 template <typename TX, typename TS, typename T, typename TOut>
 __global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -94,7 +114,7 @@ __global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut
     T* tmp = P + PH * PW;
     T* bxl = tmp + TH * kBandTX;                       // [nterms][TX][bx_w]
     T* byl = bxl + a.nterms * kBandTX * bx_w;           // [nterms][TY][by_w]
-    T* Sl = byl + a.nterms * TY * by_w;            // [(TY+2)][(TX+2)] if separate stencil input
+    T* Sl = byl + a.nterms * TY * by_w;                 // [(TY+2)][(TX+2)] if separate stencil input
 
     // p-update coefficient from the <r,z> partials of the last two iterations
     T beta = T(0);
@@ -106,74 +126,120 @@ __global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut
         beta = T(rn / ro);
     }
 
-    // stage input tile (zeros outside the image)
-    for (int k = tid; k < PH * PW; k += kBandThreads) {
-        const int r = k / PW, c = k - r * PW;
-        const int gi = i0 - hy + r, gj = j0 - hx + c;
-        T v = T(0);
-        if (gi >= 0 && gi < ny && gj >= 0 && gj < nx) {
-            const size_t g = size_t(gi) * nx + gj;
-            if (upd) {
-                TX w = a.Z[g];
-                if (use_old) w += TX(beta) * a.X[g];
-                if (r >= hy && r < hy + TY && c >= hx && c < hx + kBandTX) a.Xnew[g] = w;
-                v = T(w);
-            } else {
-                v = T(a.X[g]);
-            }
-        }
-        P[k] = v;
+    // stage the input tile (zeros outside the image), p = z + beta p_old on the fly
+    {
+        const TX* __restrict__ Zp = a.Z;
+        const TX* __restrict__ Xp = a.X;
+        const TX tb = TX(beta);
+        stage_lds<T>(PH * PW, tid, kBandThreads,
+            [&](int k) -> T {
+                const int r = k / PW, c = k - r * PW;
+                const int gi = i0 - hy + r, gj = j0 - hx + c;
+                if (gi < 0 || gi >= ny || gj < 0 || gj >= nx) return T(0);
+                const size_t g = size_t(gi) * nx + gj;
+                if (!upd) return T(Xp[g]);
+                TX w = Zp[g];
+                if (use_old) w += tb * Xp[g];
+                return T(w);
+            },
+            [&](int k, T v) { P[k] = v; });
     }
-    for (int k = tid; k < a.nterms * kBandTX * bx_w; k += kBandThreads) {
-        const int r = k / (kBandTX * bx_w);
-        const int rem = k - r * kBandTX * bx_w;
-        const int c = rem / bx_w, d = rem - c * bx_w;
-        const int gj = j0 + c;
-        bxl[k] = (gj < nx) ? a.Bx[(size_t(r) * nx + gj) * bx_w + d] : T(0);
-    }
-    for (int k = tid; k < a.nterms * TY * by_w; k += kBandThreads) {
-        const int r = k / (TY * by_w);
-        const int rem = k - r * TY * by_w;
-        const int c = rem / by_w, d = rem - c * by_w;
-        const int gi = i0 + c;
-        byl[k] = (gi < ny) ? a.By[(size_t(r) * ny + gi) * by_w + d] : T(0);
+    {
+        const T* __restrict__ Bx = a.Bx;
+        stage_lds<T>(a.nterms * kBandTX * bx_w, tid, kBandThreads,
+            [&](int k) -> T {
+                const int r = k / (kBandTX * bx_w);
+                const int rem = k - r * kBandTX * bx_w;
+                const int c = rem / bx_w, d = rem - c * bx_w;
+                const int gj = j0 + c;
+                return (gj < nx) ? Bx[(size_t(r) * nx + gj) * bx_w + d] : T(0);
+            },
+            [&](int k, T v) { bxl[k] = v; });
+        const T* __restrict__ By = a.By;
+        stage_lds<T>(a.nterms * TY * by_w, tid, kBandThreads,
+            [&](int k) -> T {
+                const int r = k / (TY * by_w);
+                const int rem = k - r * TY * by_w;
+                const int c = rem / by_w, d = rem - c * by_w;
+                const int gi = i0 + c;
+                return (gi < ny) ? By[(size_t(r) * ny + gi) * by_w + d] : T(0);
+            },
+            [&](int k, T v) { byl[k] = v; });
     }
     const bool sten_sep = stencil && a.S != nullptr;
     if (sten_sep) {
         const int SW = kBandTX + 2;
-        for (int k = tid; k < (TY + 2) * SW; k += kBandThreads) {
-            const int r = k / SW, c = k - r * SW;
-            const int gi = i0 - 1 + r, gj = j0 - 1 + c;
-            Sl[k] = (gi >= 0 && gi < ny && gj >= 0 && gj < nx) ? T(a.S[size_t(gi) * nx + gj]) : T(0);
-        }
+        const TS* __restrict__ Sp = a.S;
+        stage_lds<T>((TY + 2) * SW, tid, kBandThreads,
+            [&](int k) -> T {
+                const int r = k / SW, c = k - r * SW;
+                const int gi = i0 - 1 + r, gj = j0 - 1 + c;
+                return (gi >= 0 && gi < ny && gj >= 0 && gj < nx) ? T(Sp[size_t(gi) * nx + gj]) : T(0);
+            },
+            [&](int k, T v) { Sl[k] = v; });
     }
     __syncthreads();
+    if (upd) {  // publish the updated direction of this tile (from LDS)
+        for (int r = ty; r < TY; r += 4) {
+            const int gi = i0 + r, gj = j0 + tx;
+            if (gi < ny && gj < nx) a.Xnew[size_t(gi) * nx + gj] = TX(P[(hy + r) * PW + hx + tx]);
+        }
+    }
 
     T acc[kBandTYMax / 4];
 #pragma unroll
     for (int k = 0; k < kBandTYMax / 4; ++k) acc[k] = T(0);
     const int nacc = TY / 4;
 
+    // rows of tmp handled by this thread-row: a contiguous block, 8 at a time,
+    // so each band coefficient read from LDS serves 8 multiply-adds
+    const int rpt = (TH + 3) / 4;
+    const int rlo = ty * rpt, rhi = min(TH, rlo + rpt);
+    constexpr int kRB = 8;
     for (int term = 0; term < a.nterms; ++term) {
-        // row pass: tmp[lr][tx] = sum_d bx[tx][d] P[lr + hy - wy][hx + tx + d - wx]
         const T* bxr = bxl + (term * kBandTX + tx) * bx_w;
-        for (int lr = ty; lr < TH; lr += 4) {
-            const T* prow = P + (lr + hy - a.wy) * PW + (hx - a.wx) + tx;
-            T s = T(0);
-            for (int d = 0; d < bx_w; ++d) s += bxr[d] * prow[d];
-            tmp[lr * kBandTX + tx] = s;
+        for (int r0 = rlo; r0 < rhi; r0 += kRB) {
+            T sacc[kRB];
+#pragma unroll
+            for (int u = 0; u < kRB; ++u) sacc[u] = T(0);
+            const T* pbase = P + (r0 + hy - a.wy) * PW + (hx - a.wx) + tx;
+            const int nr = min(kRB, rhi - r0);
+            if (nr == kRB) {
+                for (int d = 0; d < bx_w; ++d) {
+                    const T c = bxr[d];
+#pragma unroll
+                    for (int u = 0; u < kRB; ++u) sacc[u] += c * pbase[u * PW + d];
+                }
+            } else {
+                for (int d = 0; d < bx_w; ++d) {
+                    const T c = bxr[d];
+#pragma unroll
+                    for (int u = 0; u < kRB; ++u)
+                        if (u < nr) sacc[u] += c * pbase[u * PW + d];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRB; ++u)
+                if (u < nr) tmp[(r0 + u) * kBandTX + tx] = sacc[u];
         }
         __syncthreads();
-        // column pass
+        // column pass: wave-uniform coefficients, 4 independent partial sums
 #pragma unroll
         for (int k = 0; k < kBandTYMax / 4; ++k) {
             if (k >= nacc) break;
             const int ti = ty + 4 * k;
             const T* byr = byl + (term * TY + ti) * by_w;
             const T* tcol = tmp + ti * kBandTX + tx;
-            T s = T(0);
-            for (int d = 0; d < by_w; ++d) s += byr[d] * tcol[d * kBandTX];
-            acc[k] += s;
+            T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+            int d = 0;
+            for (; d + 4 <= by_w; d += 4) {
+                s0 += byr[d] * tcol[d * kBandTX];
+                s1 += byr[d + 1] * tcol[(d + 1) * kBandTX];
+                s2 += byr[d + 2] * tcol[(d + 2) * kBandTX];
+                s3 += byr[d + 3] * tcol[(d + 3) * kBandTX];
+            }
+            for (; d < by_w; ++d) s0 += byr[d] * tcol[d * kBandTX];
+            acc[k] += (s0 + s1) + (s2 + s3);
         }
         __syncthreads();
     }
@@ -232,27 +298,97 @@ __global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut
 // Line transforms in LDS: two real lines packed as one complex sequence.
 // ------------------------------------------------------------------------
 
-// Stockham radix-2 FFT (forward, exp(-2 pi i/M)) of the unit's sequence,
-// ping-ponging between x and y; returns the buffer holding the result.
+// LDS slot of sequence element i: one pad entry every 8 elements keeps the
+// stride-8 writes of the first radix-8 stages free of bank conflicts.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int padded_len(int M) { return M + (M >> 3); }
+
+// LDS entries reserved for a table blob of `len` complex entries: whole
+// 1 KB wave chunks of the direct global-to-LDS copy.
 template <typename T>
-__device__ cx<T>* fft_pow2(cx<T>* x, cx<T>* y, int M, int log2M, const cx<T>* __restrict__ tw,
-                           int lt, int tpu) {
-    const int half = M >> 1;
-    int s = 1;
-    for (int st = 0; st < log2M; ++st) {
-        for (int b = lt; b < half; b += tpu) {
-            const int p = b >> st, q = b & (s - 1);
-            const cx<T> u = x[b], v = x[b + half];
-            const cx<T> w = tw[p * s];
-            const cx<T> d = {u.x - v.x, u.y - v.y};
-            y[q + 2 * s * p] = {u.x + v.x, u.y + v.y};
-            y[q + s * (2 * p + 1)] = cmul(d, w);
-        }
+__host__ __device__ constexpr int lds_table_len(int len) {
+    return len == 0 ? 0 : ((len * int(sizeof(cx<T>)) + 1023) / 1024) * (1024 / int(sizeof(cx<T>)));
+}
+
+// In-register DFTs out[k] = sum_r a[r] exp(-2 pi i r k / R), R = 2, 4, 8.
+template <typename T>
+__device__ __forceinline__ void dft2(cx<T>& a0, cx<T>& a1) {
+    const cx<T> t = a0;
+    a0 = {t.x + a1.x, t.y + a1.y};
+    a1 = {t.x - a1.x, t.y - a1.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; }  // times -i
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>* b) {
+    cx<T> c0 = b[0], c1 = b[2], c2 = b[1], c3 = b[3];
+    dft2(c0, c1);  // b0 +- b2
+    dft2(c2, c3);  // b1 +- b3
+    c3 = mul_mi(c3);
+    b[0] = {c0.x + c2.x, c0.y + c2.y};
+    b[2] = {c0.x - c2.x, c0.y - c2.y};
+    b[1] = {c1.x + c3.x, c1.y + c3.y};
+    b[3] = {c1.x - c3.x, c1.y - c3.y};
+}
+template <typename T>
+__device__ __forceinline__ void dft8(cx<T>* a) {
+    const T h = T(0.70710678118654752440084436210484903);
+    cx<T> e[4] = {a[0], a[2], a[4], a[6]};
+    cx<T> o[4] = {a[1], a[3], a[5], a[7]};
+    dft4(e);
+    dft4(o);
+    // o[k] *= exp(-2 pi i k / 8)
+    o[1] = {h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};
+    o[2] = mul_mi(o[2]);
+    o[3] = {h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = {e[k].x + o[k].x, e[k].y + o[k].y};
+        a[k + 4] = {e[k].x - o[k].x, e[k].y - o[k].y};
+    }
+}
+
+// One Stockham decimation-in-frequency stage of radix R: for the current
+// sub-transform length n = M / s, element q + s(p + r m) (m = n/R) feeds
+// output q + s(R p + k) with the twiddle exp(-2 pi i p k / n) = tw[p k s].
+template <typename T, int R>
+__device__ __forceinline__ void stockham_stage(const cx<T>* x, cx<T>* y, int M, int log2s,
+                                               const cx<T>* __restrict__ tw, int lt, int tpu) {
+    const int s = 1 << log2s;
+    const int nb = M / R;
+    for (int b = lt; b < nb; b += tpu) {
+        const int p = b >> log2s, q = b & (s - 1);
+        cx<T> a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = x[pidx(b + r * nb)];
+        if constexpr (R == 8) dft8(a);
+        else if constexpr (R == 4) dft4(a);
+        else dft2(a[0], a[1]);
+        const int base = q + s * R * p;
+        y[pidx(base)] = a[0];
+#pragma unroll
+        for (int k = 1; k < R; ++k) y[pidx(base + s * k)] = cmul(a[k], tw[p * k * s]);
+    }
+}
+
+// Mixed-radix Stockham FFT (forward, exp(-2 pi i/M)) of the unit's sequence,
+// radix-8 stages then one radix-4 or radix-2 stage; ping-pongs between x and
+// y and returns the buffer holding the result.
+template <typename T>
+__device__ __forceinline__ cx<T>* fft_pow2(cx<T>* x, cx<T>* y, int M, int log2M, const cx<T>* __restrict__ tw, int lt,
+                           int tpu) {
+    int log2s = 0;
+    while (log2s < log2M) {
+        const int rem = log2M - log2s;
+        const int lr = rem >= 3 ? 3 : rem;
+        if (lr == 3) stockham_stage<T, 8>(x, y, M, log2s, tw, lt, tpu);
+        else if (lr == 2) stockham_stage<T, 4>(x, y, M, log2s, tw, lt, tpu);
+        else stockham_stage<T, 2>(x, y, M, log2s, tw, lt, tpu);
         __syncthreads();
         cx<T>* t = x;
         x = y;
         y = t;
-        s <<= 1;
+        log2s += lr;
     }
     return x;
 }
@@ -261,30 +397,30 @@ __device__ cx<T>* fft_pow2(cx<T>* x, cx<T>* y, int M, int log2M, const cx<T>* __
 // chirp-multiplied and zero padded to M).  Returns the result buffer; the
 // caller reads X_k through dft_get().
 template <typename T>
-__device__ cx<T>* dft_run(cx<T>* b0, cx<T>* b1, const AxisPlan<T>& P, int lt, int tpu) {
+__device__ __forceinline__ cx<T>* dft_run(cx<T>* b0, cx<T>* b1, const AxisPlan<T>& P, int lt, int tpu) {
     cx<T>* r = fft_pow2(b0, b1, P.M, P.log2M, P.tw, lt, tpu);
     if (!P.bluestein) return r;
     cx<T>* o = (r == b0) ? b1 : b0;
-    for (int k = lt; k < P.M; k += tpu) r[k] = cconj(cmul(r[k], P.bf[k]));
+    for (int k = lt; k < P.M; k += tpu) r[pidx(k)] = cconj(cmul(r[pidx(k)], P.bf[k]));
     __syncthreads();
     return fft_pow2(r, o, P.M, P.log2M, P.tw, lt, tpu);
 }
 
 template <typename T>
 __device__ __forceinline__ cx<T> dft_get(const cx<T>* r, int k, const AxisPlan<T>& P) {
-    if (!P.bluestein) return r[k];
-    return cmul(P.chirp[k], cconj(r[k]));
+    if (!P.bluestein) return r[pidx(k)];
+    return cmul(P.chirp[k], cconj(r[pidx(k)]));
 }
 
 template <typename T>
 __device__ __forceinline__ void dft_put(cx<T>* b, int t, cx<T> v, const AxisPlan<T>& P) {
-    b[t] = P.bluestein ? cmul(v, P.chirp[t]) : v;
+    b[pidx(t)] = P.bluestein ? cmul(v, P.chirp[t]) : v;
 }
 
 template <typename T>
 __device__ __forceinline__ void dft_pad(cx<T>* b, const AxisPlan<T>& P, int lt, int tpu) {
     if (P.bluestein)
-        for (int t = P.L + lt; t < P.M; t += tpu) b[t] = {T(0), T(0)};
+        for (int t = P.L + lt; t < P.M; t += tpu) b[pidx(t)] = {T(0), T(0)};
 }
 
 // Assemble the forward transform input for position t of the two lines
@@ -347,29 +483,123 @@ __device__ __forceinline__ bool passthrough(int t, const AxisPlan<T>& P) {
     return P.kind == 1 && (t == 0 || t == P.n - 1);
 }
 
+// ---- line-pass plumbing: one batched round trip of global loads ----------
+
+// Asynchronous copy of the plan's table blob into LDS with the direct
+// global-to-LDS load (each lane moves 16 bytes to wave_base + 16 * lane);
+// nothing passes through registers.  The LDS region is padded to whole
+// 64-chunk waves (lds_table_len), the last wave re-reads the final chunk to
+// stay inside the source.  Completion: vmcnt(0) + barrier (lds_copy_wait).
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+__device__ __forceinline__ void lds_copy_async(const void* src, void* lds, int n16) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int4* s = reinterpret_cast<const int4*>(src);
+    int4* d = reinterpret_cast<int4*>(lds);
+    for (int base = wave * 64; base < n16; base += nw * 64) {
+        const int k = min(base + lane, n16 - 1);
+        __builtin_amdgcn_global_load_lds((glb_void_t*)(s + k), (lds_void_t*)(d + base), 16, 0, 0);
+    }
+}
+__device__ __forceinline__ void lds_copy_wait() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Plan whose table pointers refer to the LDS copy (or stay global).
+template <typename T, bool kTabLds>
+__device__ __forceinline__ AxisPlan<T> lds_plan(const AxisPlan<T>& G, cx<T>* tab) {
+    AxisPlan<T> P = G;
+    if constexpr (kTabLds) {
+        P.tw = tab;
+        P.chirp = tab + G.off_chirp;
+        P.bf = tab + G.off_bf;
+        P.pre = tab + G.off_pre;
+        P.post = tab + G.off_post;
+    }
+    return P;
+}
+
+// Up to 4 per-thread partial loads summed in registers (n <= 4 * nthreads
+// handled in the batch; longer lists fall back to a loop).
+__device__ __forceinline__ double partial_issue(const double* p, int n, int tid, int nthr) {
+    if (p == nullptr) return 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = tid + u * nthr;
+        if (k < n) s += p[k];
+    }
+    for (int k = tid + 4 * nthr; k < n; k += nthr) s += p[k];
+    return s;
+}
+
+constexpr int kLinePos = 2;  // positions per thread per line (n <= 2 * tpu)
+
 // Row pass.  mode 0: (optional x,r update) then T1 = Qx (s o r) row-wise.
 //            mode 1: z = s o (Qx^T T2) row-wise, <r, z> partials.
-template <typename T>
+template <typename T, bool kTabLds>
 __global__ void k_rowpass(RowPassArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[17];
-    if (a.st->done) return;
-    const AxisPlan<T>& P = a.plan;
     const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
     const int ul = tid / a.g.tpu, lt = tid - ul * a.g.tpu;
     const int unit = blockIdx.x * a.g.upb + ul;
     const int nx = a.nx, ny = a.ny;
-    cx<T>* b0 = reinterpret_cast<cx<T>*>(smem_raw) + size_t(ul) * 2 * P.M;
-    cx<T>* b1 = b0 + P.M;
+    const int tpu = a.g.tpu;
+    cx<T>* tab = reinterpret_cast<cx<T>*>(smem_raw);
+    const int tab_len = kTabLds ? a.plan.blob_len : 0;
+    const int Mp = padded_len(a.plan.M);
+    cx<T>* b0 = tab + lds_table_len<T>(tab_len) + size_t(ul) * 2 * Mp;
+    cx<T>* b1 = b0 + Mp;
+    T* xb_lds = reinterpret_cast<T*>(tab + lds_table_len<T>(tab_len) + size_t(a.g.upb) * 2 * Mp);
     const int ia = 2 * unit, ib = 2 * unit + 1;
     const bool va = ia < ny, vb = ib < ny;
+    const size_t ga = size_t(ia) * nx, gb = size_t(ib) * nx;
+    const bool upd = a.mode == 0 && a.do_update;
+
+    // ---- one batch of global loads ----
+    const int n16 = tab_len * int(sizeof(cx<T>)) / 16;
+    if (kTabLds) lds_copy_async(a.plan.blob, tab, n16);
+    if (a.mode == 1 && a.wout) lds_copy_async(a.xband, xb_lds, a.xband_len * int(sizeof(T)) / 16);
+    const int done = a.st->done;
+    const double pq = upd ? partial_issue(a.pq_part, a.n_pq, tid, nthr) : 0.0;
+    const double rzp = upd ? partial_issue(a.rz_part, a.n_rz, tid, nthr) : 0.0;
+    T ra[kLinePos], rb[kLinePos], xa[kLinePos], xb[kLinePos], pa[kLinePos], pb[kLinePos], qa[kLinePos],
+        qb[kLinePos], sa[kLinePos], sb[kLinePos];
+    const T* src = a.mode == 0 ? a.r : a.src;
+#pragma unroll
+    for (int c = 0; c < kLinePos; ++c) {
+        const int t = lt + c * tpu;
+        const bool in = t < nx;
+        ra[c] = (in && va) ? src[ga + t] : T(0);
+        rb[c] = (in && vb) ? src[gb + t] : T(0);
+        sa[c] = (in && va && a.s) ? a.s[ga + t] : T(1);
+        sb[c] = (in && vb && a.s) ? a.s[gb + t] : T(1);
+        if (upd) {
+            xa[c] = (in && va) ? a.x[ga + t] : T(0);
+            xb[c] = (in && vb) ? a.x[gb + t] : T(0);
+            pa[c] = (in && va) ? a.p[ga + t] : T(0);
+            pb[c] = (in && vb) ? a.p[gb + t] : T(0);
+            qa[c] = (in && va) ? a.q[ga + t] : T(0);
+            qb[c] = (in && vb) ? a.q[gb + t] : T(0);
+        }
+        if (a.mode == 1) {  // r for the <r, z> dot
+            xa[c] = (in && va) ? a.r[ga + t] : T(0);
+            xb[c] = (in && vb) ? a.r[gb + t] : T(0);
+        }
+    }
+    lds_copy_wait();
+    if (done) return;
+    const AxisPlan<T> P = lds_plan<T, kTabLds>(a.plan, tab);
 
     double part = 0.0;
     if (a.mode == 0) {
         T step = T(0);
-        if (a.do_update) {
-            const double g = sum_partials(a.pq_part, a.n_pq, red);
-            const double rz = sum_partials(a.rz_part, a.n_rz, red);
+        if (upd) {
+            const double g = block_sum(pq, red);
+            const double rz = block_sum(rzp, red);
             if (!(g > 0.0)) {  // curvature <= 0 (or NaN): stop, keep x_{i-1}
                 if (blockIdx.x == 0 && tid == 0) {
                     a.st->done = 2;
@@ -379,104 +609,165 @@ __global__ void k_rowpass(RowPassArgs<T> a) {
             }
             step = T(rz / g);
         }
-        for (int t = lt; t < nx; t += a.g.tpu) {
-            T ra = T(0), rb = T(0);
-            if (va) {
-                const size_t g = size_t(ia) * nx + t;
-                ra = a.r[g];
-                if (a.do_update) {
-                    a.x[g] += step * a.p[g];
-                    ra -= step * a.q[g];
-                    a.r[g] = ra;
-                    part += double(ra) * double(ra);
-                }
-                if (a.s) ra *= a.s[g];
-            }
-            if (vb) {
-                const size_t g = size_t(ib) * nx + t;
-                rb = a.r[g];
-                if (a.do_update) {
-                    a.x[g] += step * a.p[g];
-                    rb -= step * a.q[g];
-                    a.r[g] = rb;
-                    part += double(rb) * double(rb);
-                }
-                if (a.s) rb *= a.s[g];
-            }
-            if (passthrough(t, P)) {
-                if (va) a.dst[size_t(ia) * nx + t] = ra;
-                if (vb) a.dst[size_t(ib) * nx + t] = rb;
-            }
-            put_forward(b0, t, cx<T>{ra, rb}, P);
-        }
-        dft_pad(b0, P, lt, a.g.tpu);
-        __syncthreads();
-        cx<T>* res = dft_run(b0, b1, P, lt, a.g.tpu);
-        for (int k = lt; k < nx; k += a.g.tpu) {
-            if (passthrough(k, P)) continue;
-            const cx<T> o = get_forward(res, k, P);
-            if (va) a.dst[size_t(ia) * nx + k] = o.x;
-            if (vb) a.dst[size_t(ib) * nx + k] = o.y;
-        }
-        if (a.do_update) {
-            const double s = block_sum(part, red);
-            if (tid == 0) a.part_out[blockIdx.x] = s;
-        }
-    } else {
-        for (int k = lt; k < nx; k += a.g.tpu) {
-            const T ya = va ? a.src[size_t(ia) * nx + k] : T(0);
-            const T yb = vb ? a.src[size_t(ib) * nx + k] : T(0);
-            if (passthrough(k, P)) {
+#pragma unroll
+        for (int c = 0; c < kLinePos; ++c) {
+            const int t = lt + c * tpu;
+            if (t >= nx) continue;
+            T va_ = ra[c], vb_ = rb[c];
+            if (upd) {
+                va_ -= step * qa[c];
+                vb_ -= step * qb[c];
                 if (va) {
-                    const size_t g = size_t(ia) * nx + k;
-                    const T z = a.s ? a.s[g] * ya : ya;
-                    a.dst[g] = z;
-                    part += double(a.r[g]) * double(z);
+                    a.x[ga + t] = xa[c] + step * pa[c];
+                    a.r[ga + t] = va_;
+                    part += double(va_) * double(va_);
                 }
                 if (vb) {
-                    const size_t g = size_t(ib) * nx + k;
-                    const T z = a.s ? a.s[g] * yb : yb;
-                    a.dst[g] = z;
-                    part += double(a.r[g]) * double(z);
+                    a.x[gb + t] = xb[c] + step * pb[c];
+                    a.r[gb + t] = vb_;
+                    part += double(vb_) * double(vb_);
                 }
             }
-            put_inverse(b0, k, cx<T>{ya, yb}, P);
+            va_ *= sa[c];
+            vb_ *= sb[c];
+            if (passthrough(t, P)) {
+                if (va) a.dst[ga + t] = va_;
+                if (vb) a.dst[gb + t] = vb_;
+            }
+            put_forward(b0, t, cx<T>{va_, vb_}, P);
         }
-        dft_pad(b0, P, lt, a.g.tpu);
+        dft_pad(b0, P, lt, tpu);
         __syncthreads();
-        cx<T>* res = dft_run(b0, b1, P, lt, a.g.tpu);
-        for (int t = lt; t < nx; t += a.g.tpu) {
-            if (passthrough(t, P)) continue;
-            const cx<T> o = get_inverse(res, t, P);
-            if (va) {
-                const size_t g = size_t(ia) * nx + t;
-                const T z = a.s ? a.s[g] * o.x : o.x;
-                a.dst[g] = z;
-                part += double(a.r[g]) * double(z);
+        cx<T>* res = dft_run(b0, b1, P, lt, tpu);
+        for (int k = lt; k < nx; k += tpu) {
+            if (passthrough(k, P)) continue;
+            const cx<T> o = get_forward(res, k, P);
+            if (va) a.dst[ga + k] = o.x;
+            if (vb) a.dst[gb + k] = o.y;
+        }
+        if (upd) {
+            const double sm = block_sum(part, red);
+            if (tid == 0) a.part_out[blockIdx.x] = sm;
+        }
+    } else {
+        T zpa[kLinePos], zpb[kLinePos];
+#pragma unroll
+        for (int c = 0; c < kLinePos; ++c) {
+            const int k = lt + c * tpu;
+            zpa[c] = zpb[c] = T(0);
+            if (k >= nx) continue;
+            if (passthrough(k, P)) {
+                const T za = sa[c] * ra[c], zb = sb[c] * rb[c];
+                zpa[c] = za;
+                zpb[c] = zb;
+                if (va) {
+                    a.dst[ga + k] = za;
+                    part += double(xa[c]) * double(za);
+                }
+                if (vb) {
+                    a.dst[gb + k] = zb;
+                    part += double(xb[c]) * double(zb);
+                }
             }
-            if (vb) {
-                const size_t g = size_t(ib) * nx + t;
-                const T z = a.s ? a.s[g] * o.y : o.y;
-                a.dst[g] = z;
-                part += double(a.r[g]) * double(z);
+            put_inverse(b0, k, cx<T>{ra[c], rb[c]}, P);
+        }
+        dft_pad(b0, P, lt, tpu);
+        __syncthreads();
+        cx<T>* res = dft_run(b0, b1, P, lt, tpu);
+        cx<T>* zc = (res == b0) ? b1 : b0;  // free buffer: z of both lines for the x-pass
+#pragma unroll
+        for (int c = 0; c < kLinePos; ++c) {
+            const int t = lt + c * tpu;
+            if (t >= nx) continue;
+            T za = zpa[c], zb = zpb[c];
+            if (!passthrough(t, P)) {
+                const cx<T> o = get_inverse(res, t, P);
+                za = sa[c] * o.x;
+                zb = sb[c] * o.y;
+                if (va) {
+                    a.dst[ga + t] = za;
+                    part += double(xa[c]) * double(za);
+                }
+                if (vb) {
+                    a.dst[gb + t] = zb;
+                    part += double(xb[c]) * double(zb);
+                }
+            }
+            if (a.wout) zc[t] = cx<T>{za, zb};
+        }
+        if (a.wout) {
+            // w = (I (x) K_x) z on both lines: Toeplitz row in the interior,
+            // stored rows near the edges; taps outside the line have zero
+            // coefficients (indices clamped only to stay inside the buffer).
+            const int bw = 2 * a.kw + 1;
+            __syncthreads();
+            lds_copy_wait();
+#pragma unroll
+            for (int c = 0; c < kLinePos; ++c) {
+                const int t = lt + c * tpu;
+                if (t >= nx) continue;
+                const int rr = t < a.klo ? 1 + t : (t >= a.khi ? 1 + a.klo + (t - a.khi) : 0);
+                const T* coef = xb_lds + rr * bw;
+                T sa_ = T(0), sb_ = T(0);
+                for (int d = 0; d < bw; ++d) {
+                    const int idx = min(max(t + d - a.kw, 0), nx - 1);
+                    const cx<T> zv = zc[idx];
+                    sa_ += coef[d] * zv.x;
+                    sb_ += coef[d] * zv.y;
+                }
+                if (va) a.wout[ga + t] = sa_;
+                if (vb) a.wout[gb + t] = sb_;
             }
         }
-        const double s = block_sum(part, red);
-        if (tid == 0) a.part_out[blockIdx.x] = s;
+        const double sm = block_sum(part, red);
+        if (tid == 0) a.part_out[blockIdx.x] = sm;
     }
 }
 
 // Column pass: convergence test, forward column transform, divide by mu,
 // inverse column transform.
-template <typename T>
+template <typename T, bool kTabLds>
 __global__ void k_colpass(ColPassArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[17];
-    if (a.st->done) return;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int ul = tid / a.g.tpu, lt = tid - ul * a.g.tpu;
+    const int unit = blockIdx.x * a.g.upb + ul;
+    const int nx = a.nx, ny = a.ny;
+    const int tpu = a.g.tpu;
+    cx<T>* tab = reinterpret_cast<cx<T>*>(smem_raw);
+    const int tab_len = kTabLds ? a.plan.blob_len : 0;
+    const int Mp = padded_len(a.plan.M);
+    cx<T>* b0 = tab + lds_table_len<T>(tab_len) + size_t(ul) * 2 * Mp;
+    cx<T>* b1 = b0 + Mp;
+    const int ja = 2 * unit, jb = 2 * unit + 1;
+    const bool va = ja < nx, vb = jb < nx;
+
+    // ---- one batch of global loads ----
+    const int n16 = tab_len * int(sizeof(cx<T>)) / 16;
+    if (kTabLds) lds_copy_async(a.plan.blob, tab, n16);
+    const int done = a.st->done;
+    const double r0 = a.st->r0norm;
+    const double tol = a.st->tol;
+    const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, nthr) : 0.0;
+    T xa[kLinePos], xb[kLinePos], ma[kLinePos], mb[kLinePos];
+#pragma unroll
+    for (int c = 0; c < kLinePos; ++c) {
+        const int t = lt + c * tpu;
+        const bool in = t < ny;
+        const size_t g = size_t(t) * nx;
+        xa[c] = (in && va) ? a.src[g + ja] : T(0);
+        xb[c] = (in && vb) ? a.src[g + jb] : T(0);
+        ma[c] = (in && va) ? a.muinv[g + ja] : T(0);
+        mb[c] = (in && vb) ? a.muinv[g + jb] : T(0);
+    }
+    lds_copy_wait();
+    if (done) return;
     if (a.check) {
-        const double rn = sqrt(sum_partials(a.rr_part, a.n_rr, red));
+        const double rn = sqrt(block_sum(rrp, red));
         if (a.iter == 0) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (blockIdx.x == 0 && tid == 0) {
                 a.st->r0norm = rn;
                 a.st->relres = rn > 0.0 ? 1.0 : 0.0;
                 if (rn == 0.0) {
@@ -486,10 +777,9 @@ __global__ void k_colpass(ColPassArgs<T> a) {
             }
             if (rn == 0.0) return;
         } else {
-            const double r0 = a.st->r0norm;
-            if (blockIdx.x == 0 && threadIdx.x == 0) a.st->relres = rn / r0;
-            if (rn < a.st->tol * r0) {
-                if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (blockIdx.x == 0 && tid == 0) a.st->relres = rn / r0;
+            if (rn < tol * r0) {
+                if (blockIdx.x == 0 && tid == 0) {
                     a.st->done = 1;
                     a.st->iters = a.iter;
                 }
@@ -497,47 +787,144 @@ __global__ void k_colpass(ColPassArgs<T> a) {
             }
         }
     }
-    const AxisPlan<T>& P = a.plan;
-    const int tid = threadIdx.x;
-    const int ul = tid / a.g.tpu, lt = tid - ul * a.g.tpu;
-    const int unit = blockIdx.x * a.g.upb + ul;
-    const int nx = a.nx, ny = a.ny;
-    cx<T>* b0 = reinterpret_cast<cx<T>*>(smem_raw) + size_t(ul) * 2 * P.M;
-    cx<T>* b1 = b0 + P.M;
-    const int ja = 2 * unit, jb = 2 * unit + 1;
-    const bool va = ja < nx, vb = jb < nx;
-
-    for (int t = lt; t < ny; t += a.g.tpu) {
-        const T xa = va ? a.src[size_t(t) * nx + ja] : T(0);
-        const T xb = vb ? a.src[size_t(t) * nx + jb] : T(0);
+    const AxisPlan<T> P = lds_plan<T, kTabLds>(a.plan, tab);
+#pragma unroll
+    for (int c = 0; c < kLinePos; ++c) {
+        const int t = lt + c * tpu;
+        if (t >= ny) continue;
         if (passthrough(t, P)) {
-            if (va) a.dst[size_t(t) * nx + ja] = xa * a.muinv[size_t(t) * nx + ja];
-            if (vb) a.dst[size_t(t) * nx + jb] = xb * a.muinv[size_t(t) * nx + jb];
+            if (va) a.dst[size_t(t) * nx + ja] = xa[c] * ma[c];
+            if (vb) a.dst[size_t(t) * nx + jb] = xb[c] * mb[c];
         }
-        put_forward(b0, t, cx<T>{xa, xb}, P);
+        put_forward(b0, t, cx<T>{xa[c], xb[c]}, P);
     }
-    dft_pad(b0, P, lt, a.g.tpu);
+    dft_pad(b0, P, lt, tpu);
     __syncthreads();
-    cx<T>* res = dft_run(b0, b1, P, lt, a.g.tpu);
+    cx<T>* res = dft_run(b0, b1, P, lt, tpu);
     cx<T>* nb = (res == b0) ? b1 : b0;
-    for (int k = lt; k < ny; k += a.g.tpu) {
-        cx<T> c = {T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < kLinePos; ++c) {
+        const int k = lt + c * tpu;
+        if (k >= ny) continue;
+        cx<T> v = {T(0), T(0)};
         if (!passthrough(k, P)) {
-            c = get_forward(res, k, P);
-            c.x *= va ? a.muinv[size_t(k) * nx + ja] : T(0);
-            c.y *= vb ? a.muinv[size_t(k) * nx + jb] : T(0);
+            v = get_forward(res, k, P);
+            v.x *= ma[c];
+            v.y *= mb[c];
         }
-        put_inverse(nb, k, c, P);
+        put_inverse(nb, k, v, P);
     }
-    dft_pad(nb, P, lt, a.g.tpu);
+    dft_pad(nb, P, lt, tpu);
     __syncthreads();
-    cx<T>* res2 = dft_run(nb, res, P, lt, a.g.tpu);
-    for (int t = lt; t < ny; t += a.g.tpu) {
-        if (passthrough(t, P)) continue;
+    cx<T>* res2 = dft_run(nb, res, P, lt, tpu);
+#pragma unroll
+    for (int c = 0; c < kLinePos; ++c) {
+        const int t = lt + c * tpu;
+        if (t >= ny || passthrough(t, P)) continue;
         const cx<T> o = get_inverse(res2, t, P);
         if (va) a.dst[size_t(t) * nx + ja] = o.x;
         if (vb) a.dst[size_t(t) * nx + jb] = o.y;
     }
+}
+
+// Column half of the fused normal operator (see YPassArgs), 64 x 16 outputs
+// per block, one output per thread, all inputs in one batch of loads.
+constexpr int kYTX = 64, kYTY = 16, kYThreads = kYTX * kYTY;
+template <typename T>
+__global__ void __launch_bounds__(kYThreads) k_ypass(YPassArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[17];
+    const int tid = threadIdx.x, tx = tid & (kYTX - 1), ty = tid / kYTX;
+    const int tyu = __builtin_amdgcn_readfirstlane(ty);
+    const int i0 = blockIdx.y * kYTY, j0 = blockIdx.x * kYTX;
+    const int ny = a.ny, nx = a.nx, w = a.w;
+    const int TH = kYTY + 2 * w;
+    constexpr int PW = kYTX + 2;
+    T* tt = reinterpret_cast<T*>(smem_raw);  // [TH][kYTX]  tmp_new
+    T* pt = tt + TH * kYTX;                  // [kYTY + 2][PW] p_new
+    const bool use_old = a.rz_old != nullptr;
+
+    // ---- one batch of global loads ----
+    const int done = a.st ? a.st->done : 0;
+    const double rzn = use_old ? partial_issue(a.rz_new, a.n_rz, tid, kYThreads) : 0.0;
+    const double rzo = use_old ? partial_issue(a.rz_old, a.n_rz, tid, kYThreads) : 0.0;
+    constexpr int kTS = 5;  // (16 + 2*32) * 64 / 1024
+    T wv[kTS], to[kTS];
+#pragma unroll
+    for (int k = 0; k < kTS; ++k) {
+        const int e = tid + k * kYThreads;
+        const int r = e / kYTX, c = e - r * kYTX;
+        const int gi = i0 - w + r, gj = j0 + c;
+        const bool in = e < TH * kYTX && gi >= 0 && gi < ny && gj < nx;
+        const size_t g = in ? size_t(gi) * nx + gj : 0;
+        wv[k] = in ? a.wv[g] : T(0);
+        to[k] = (in && use_old) ? a.tmp_old[g] : T(0);
+    }
+    constexpr int kPS = 2;  // (16 + 2) * 66 = 1188 <= 2 * 1024
+    T zv[kPS], po[kPS];
+#pragma unroll
+    for (int k = 0; k < kPS; ++k) {
+        const int e = tid + k * kYThreads;
+        const int r = e / PW, c = e - r * PW;
+        const int gi = i0 - 1 + r, gj = j0 - 1 + c;
+        const bool in = e < (kYTY + 2) * PW && gi >= 0 && gi < ny && gj >= 0 && gj < nx;
+        const size_t g = in ? size_t(gi) * nx + gj : 0;
+        zv[k] = in ? a.z[g] : T(0);
+        po[k] = (in && use_old) ? a.p_old[g] : T(0);
+    }
+    const int gi = i0 + ty, gj = j0 + tx;
+    const bool own = gi < ny && gj < nx;
+    const size_t g = own ? size_t(gi) * nx + gj : 0;
+    const T kc = own ? a.kap[g] : T(0);
+    const T ku = (own && gi > 0) ? a.kap[g - nx] : T(0);
+    const T kl = (own && gj > 0) ? a.kap[g - 1] : T(0);
+    if (done) return;
+
+    T beta = T(0);
+    if (use_old) {
+        const double n_ = block_sum(rzn, red);
+        const double o_ = block_sum(rzo, red);
+        beta = T(n_ / o_);
+    }
+#pragma unroll
+    for (int k = 0; k < kTS; ++k) {
+        const int e = tid + k * kYThreads;
+        if (e < TH * kYTX) tt[e] = wv[k] + beta * to[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kPS; ++k) {
+        const int e = tid + k * kYThreads;
+        if (e < (kYTY + 2) * PW) pt[e] = zv[k] + beta * po[k];
+    }
+    __syncthreads();
+
+    double dot = 0.0;
+    if (own) {
+        const T* prow = pt + (ty + 1) * PW + tx + 1;
+        const T pc = prow[0];
+        a.tmp_new[g] = tt[(ty + w) * kYTX + tx];
+        a.p_new[g] = pc;
+        const int row = min(i0 + tyu, ny - 1);  // wave-uniform band row
+        const T* kyr = a.Ky + size_t(row) * (2 * w + 1);
+        const T* tcol = tt + ty * kYTX + tx;
+        T s0 = T(0), s1 = T(0);
+        int d = 0;
+        for (; d + 2 <= 2 * w + 1; d += 2) {
+            s0 += kyr[d] * tcol[d * kYTX];
+            s1 += kyr[d + 1] * tcol[(d + 1) * kYTX];
+        }
+        if (d < 2 * w + 1) s0 += kyr[d] * tcol[d * kYTX];
+        T lp = T(0);
+        if (gi > 0) lp += ku * (pc - prow[-PW]);
+        if (gi < ny - 1) lp += kc * (pc - prow[PW]);
+        if (gj > 0) lp += kl * (pc - prow[-1]);
+        if (gj < nx - 1) lp += kc * (pc - prow[1]);
+        const T qv = (s0 + s1) + T(a.alpha) * lp;
+        a.q[g] = qv;
+        dot = double(pc) * double(qv);
+    }
+    const double sm = block_sum(dot, red);
+    if (tid == 0) a.pq_part[blockIdx.y * gridDim.x + blockIdx.x] = sm;
 }
 
 // Diagonal / identity preconditioner iteration tail (no transform):
@@ -823,10 +1210,13 @@ template <typename T>
 LineGeom line_geom(int lines, int M) {
     LineGeom g;
     g.units = (lines + 1) / 2;
+    // line length n < M/2 + 1 and each thread holds at most kLinePos positions
     g.tpu = std::min(256, std::max(64, M / 8));
-    const size_t per_unit = size_t(2) * M * sizeof(cx<T>);
-    int upb = 256 / g.tpu;
-    while (upb > 1 && per_unit * upb > 64 * 1024) upb >>= 1;
+    while (g.tpu * kLinePos < M / 2 + 2 && g.tpu < 1024) g.tpu *= 2;
+    if (g.tpu * kLinePos < M / 2 + 2) g.tpu = 0;  // line too long for one block
+    const size_t per_unit = size_t(2) * padded_len(M) * sizeof(cx<T>);
+    int upb = std::max(1, 256 / g.tpu);
+    while (upb > 1 && per_unit * upb > 80 * 1024) upb >>= 1;
     g.upb = std::min(upb, g.units);
     g.blocks = (g.units + g.upb - 1) / g.upb;
     g.lds = per_unit * g.upb;
@@ -834,20 +1224,39 @@ LineGeom line_geom(int lines, int M) {
 }
 
 template <typename T>
+size_t lds_table_bytes(int blob_len) {
+    return size_t(lds_table_len<T>(blob_len)) * sizeof(cx<T>);
+}
+
+template <typename T>
 hipError_t launch_rowpass(const RowPassArgs<T>& a, hipStream_t s) {
+    auto k = a.plan.tables_in_lds ? &k_rowpass<T, true> : &k_rowpass<T, false>;
     if (a.g.lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rowpass<T>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(a.g.lds));
-    hipLaunchKernelGGL(k_rowpass<T>, dim3(a.g.blocks), dim3(a.g.upb * a.g.tpu), a.g.lds, s, a);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(a.g.lds));
+    hipLaunchKernelGGL(k, dim3(a.g.blocks), dim3(a.g.upb * a.g.tpu), a.g.lds, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_colpass(const ColPassArgs<T>& a, hipStream_t s) {
+    auto k = a.plan.tables_in_lds ? &k_colpass<T, true> : &k_colpass<T, false>;
     if (a.g.lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colpass<T>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(a.g.lds));
-    hipLaunchKernelGGL(k_colpass<T>, dim3(a.g.blocks), dim3(a.g.upb * a.g.tpu), a.g.lds, s, a);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(a.g.lds));
+    hipLaunchKernelGGL(k, dim3(a.g.blocks), dim3(a.g.upb * a.g.tpu), a.g.lds, s, a);
+    return hipGetLastError();
+}
+
+int ypass_blocks(int ny, int nx) { return ((nx + kYTX - 1) / kYTX) * ((ny + kYTY - 1) / kYTY); }
+
+template <typename T>
+hipError_t launch_ypass(const YPassArgs<T>& a, hipStream_t s, int* nblocks) {
+    if (a.w > 32) return hipErrorInvalidValue;  // tile slots sized for half-width <= 32
+    const size_t lds = (size_t(kYTY + 2 * a.w) * kYTX + size_t(kYTY + 2) * (kYTX + 2)) * sizeof(T);
+    dim3 grid((a.nx + kYTX - 1) / kYTX, (a.ny + kYTY - 1) / kYTY);
+    if (nblocks) *nblocks = grid.x * grid.y;
+    hipLaunchKernelGGL(k_ypass<T>, grid, dim3(kYThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -927,7 +1336,9 @@ hipError_t launch_cast_to_double(int n, const T* src, double* dst, hipStream_t s
     template hipError_t launch_band<T, T, T, T>(const BandArgs<T>&, int, hipStream_t, int*);                  \
     template size_t band_lds_bytes<T, T, T, T>(const BandArgs<T>&, int);                                      \
     template LineGeom line_geom<T>(int, int);                                                                 \
+    template size_t lds_table_bytes<T>(int);                                                                  \
     template hipError_t launch_rowpass<T>(const RowPassArgs<T>&, hipStream_t);                                \
+    template hipError_t launch_ypass<T>(const YPassArgs<T>&, hipStream_t, int*);                              \
     template hipError_t launch_colpass<T>(const ColPassArgs<T>&, hipStream_t);                                \
     template hipError_t launch_diag_update<T>(int, T*, T*, const T*, const T*, const T*, T*, const double*,   \
                                               int, const double*, int, double*, double*, PcgState*, int, int, \

@@ -230,6 +230,29 @@ std::vector<double> band_of(const std::vector<double>& A, int n, int w) {
     return out;
 }
 
+ToeplitzBand compress_band(const std::vector<double>& band, int n, int w) {
+    const int bw = 2 * w + 1;
+    ToeplitzBand t;
+    t.w = w;
+    const int mid = n / 2;
+    auto same = [&](int i) {
+        for (int d = 0; d < bw; ++d)
+            if (band[size_t(i) * bw + d] != band[size_t(mid) * bw + d]) return false;
+        return true;
+    };
+    int lo = mid, hi = mid + 1;
+    while (lo > 0 && same(lo - 1)) --lo;
+    while (hi < n && same(hi)) ++hi;
+    // Equality includes the zero taps that fall outside the image, so using
+    // the Toeplitz row for every row in [lo, hi) is exact.
+    t.lo = lo;
+    t.hi = hi;
+    t.data.assign(band.begin() + size_t(mid) * bw, band.begin() + size_t(mid + 1) * bw);
+    t.data.insert(t.data.end(), band.begin(), band.begin() + size_t(lo) * bw);
+    t.data.insert(t.data.end(), band.begin() + size_t(hi) * bw, band.end());
+    return t;
+}
+
 std::vector<double> transpose(const std::vector<double>& A, int n) {
     std::vector<double> T(size_t(n) * n);
     for (int i = 0; i < n; ++i)
@@ -329,8 +352,8 @@ AxisTables make_axis_tables(int n, int bc) {
     }
     t.log2M = 0;
     while ((1 << t.log2M) < t.M) ++t.log2M;
-    t.tw.resize(size_t(t.M));  // M/2 complex
-    for (int k = 0; k < t.M / 2; ++k) {
+    t.tw.resize(2 * size_t(t.M));  // M complex
+    for (int k = 0; k < t.M; ++k) {
         t.tw[2 * k] = cos_pi_frac(2LL * k, t.M);
         t.tw[2 * k + 1] = -sin_pi_frac(2LL * k, t.M);
     }
@@ -366,6 +389,19 @@ AxisTables make_axis_tables(int n, int bc) {
         }
     }
     t.dst_scale = 1.0 / std::sqrt(2.0 * (n - 1));
+    // one blob: every section padded to an even number of complex entries
+    auto add = [&](const std::vector<double>& v) {
+        const int off = int(t.blob.size() / 2);
+        t.blob.insert(t.blob.end(), v.begin(), v.end());
+        if ((v.size() / 2) % 2) t.blob.insert(t.blob.end(), {0.0, 0.0});
+        return off;
+    };
+    add(t.tw);
+    t.off_chirp = add(t.chirp);
+    t.off_bf = add(t.bf);
+    t.off_pre = add(t.pre);
+    t.off_post = add(t.post);
+    t.blob_len = int(t.blob.size() / 2);
     return t;
 }
 
