@@ -136,6 +136,24 @@ int tvdeblur_set_bc(tvdeblur_t h, int bc);
 int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev,
                    const tvd_params* p, tvd_stats* stats);
 
+/* Differentiation form: reverse-mode derivative of the K fixed-point steps of
+ * eq. (fp), u^{k+1} = (H^T H + alpha L(u^k))^{-1} H^T v with u^0 = v.
+ * iterates_dev holds u^0..u^K as written by tvdeblur_solve (iterates_dev of
+ * its params; K = its stats.outer_steps), ubar_dev = dl/du^K.  Writes
+ * vbar_dev = dl/dv (device, the image type of the handle) and *abar_host =
+ * dl/dalpha, *bbar_host = dl/dbeta.  Step k recomputes kappa(u^k) and the
+ * preconditioner from the checkpoint and solves the adjoint system
+ * A_k lambda = ubar^{k+1} with the same PCG and preconditioner (A_k is
+ * symmetric), from lambda = 0, with p->inner_tol / max_inner / precond;
+ * alpha and beta must equal the forward call's.  The result is the
+ * derivative of the exact fixed-point map, so gradient checks use a tight
+ * inner_tol in both calls.  stats (nullable) reports the adjoint PCG
+ * iterations per step (index K-1-k for step k).
+ * Errors: as tvdeblur_solve. */
+int tvdeblur_solve_adjoint(tvdeblur_t h, const void* iterates_dev, int K, const void* ubar_dev,
+                           void* vbar_dev, double* abar_host, double* bbar_host,
+                           const tvd_params* p, tvd_stats* stats);
+
 /* Release the handle and its device workspace. NULL is accepted. */
 int tvdeblur_destroy(tvdeblur_t h);
 

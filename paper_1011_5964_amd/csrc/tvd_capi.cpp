@@ -72,6 +72,8 @@ class SolverBase {
     virtual ~SolverBase() = default;
     virtual void build(const std::vector<double>& psf, int py, int px, int bc) = 0;
     virtual void solve(const void* v, void* u, const tvd_params& p, tvd_stats& st) = 0;
+    virtual void solve_adjoint(const void* iterates, int K, const void* ubar, void* vbar, double* abar,
+                               double* bbar, const tvd_params& p, tvd_stats& st) = 0;
     virtual void op_blur(const void* x, void* y, bool adjoint) = 0;
     virtual void op_setup(const void* uk, double alpha, double beta, int variant) = 0;
     virtual void op_normal(const void* x, void* y) = 0;
@@ -269,8 +271,8 @@ class Solver final : public SolverBase {
         make_plan(planX_, nx_);
         if (ny_ == nx_) planY_ = planX_;
         else make_plan(planY_, ny_);
-        gx_ = line_geom<T>(ny_, planX_.M);  // row pass: lines are rows (ny of them)
-        gy_ = line_geom<T>(nx_, planY_.M);  // column pass: lines are columns
+        gx_ = line_geom<T>(ny_, nx_, planX_.M);  // row pass: ny lines of length nx
+        gy_ = line_geom<T>(nx_, ny_, planY_.M);  // column pass: nx lines of length ny
         if (gx_.lds + kStaticLds > max_lds_ || gy_.lds + kStaticLds > max_lds_)
             throw ApiError{TVD_ESIZE, "transform length too large for the device's LDS"};
         // FFT tables go to LDS next to the buffers when they fit
@@ -663,6 +665,79 @@ class Solver final : public SolverBase {
         if (st.breakdown) throw ApiError{TVD_EBREAKDOWN, "PCG breakdown: p^T A p <= 0"};
     }
 
+    // Reverse sweep over the checkpointed iterates (differentiation form).
+    void solve_adjoint(const void* itv, int K, const void* ubarv, void* vbarv, double* abar, double* bbar,
+                       const tvd_params& p, tvd_stats& st) override {
+        const auto t0 = std::chrono::steady_clock::now();
+        const T* its = static_cast<const T*>(itv);
+        std::memset(&st, 0, sizeof(st));
+        st.all_converged = 1;
+        if (!UbarD_) {
+            UbarD_ = static_cast<double*>(geo_.alloc(N_ * sizeof(double)));
+            VbarD_ = static_cast<double*>(geo_.alloc(N_ * sizeof(double)));
+            Gd_ = static_cast<double*>(geo_.alloc(N_ * sizeof(double)));
+            adj_part_ = static_cast<double*>(geo_.alloc(2 * 1024 * sizeof(double)));
+        }
+        TVD_HIP(launch_cast_to_double<T>(int(N_), static_cast<const T*>(ubarv), UbarD_, s_));
+        TVD_HIP(hipMemsetAsync(VbarD_, 0, N_ * sizeof(double), s_));
+        double sum_ke = 0.0, sum_k3e = 0.0;
+        std::vector<double> part(2 * 1024);
+        float ms_setup = 0, ms_inner = 0;
+        for (int k = K - 1; k >= 0; --k) {
+            const T* uk = its + size_t(k) * N_;
+            const T* uk1 = its + size_t(k + 1) * N_;
+            TVD_HIP(hipEventRecord(ev_a_, s_));
+            setup(uk, p.alpha, p.beta, p.precond);
+            TVD_HIP(hipEventRecord(ev_b_, s_));
+            // lambda = A_k^{-1} ubar from lambda = 0 (right-hand side in FP64)
+            TVD_HIP(hipMemcpyAsync(BD_, UbarD_, N_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+            TVD_HIP(hipMemsetAsync(U_, 0, N_ * sizeof(T), s_));
+            pcg(p.max_inner, p.inner_tol, 8);
+            TVD_HIP(hipEventRecord(ev_c_, s_));
+            // vbar += H lambda, scalar partials, g = kappa^3 e, ubar = alpha D^T(g o D u^k)
+            blur_apply(X_, Tmp_, false);
+            int nb = 0;
+            TVD_HIP(launch_adj_accum<T>(ny_, nx_, X_, Tmp_, uk1, Kapd_, VbarD_, Gd_, adj_part_, &nb, s_));
+            TVD_HIP(launch_adj_ubar<T>(ny_, nx_, Gd_, uk, p.alpha, UbarD_, s_));
+            TVD_HIP(hipMemcpyAsync(part.data(), adj_part_, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, s_));
+            TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+            TVD_HIP(hipStreamSynchronize(s_));
+            timer_.harvest();
+            float a = 0, b = 0;
+            TVD_HIP(hipEventElapsedTime(&a, ev_a_, ev_b_));
+            TVD_HIP(hipEventElapsedTime(&b, ev_b_, ev_c_));
+            ms_setup += a;
+            ms_inner += b;
+            for (int q = 0; q < nb; ++q) {
+                sum_ke += part[2 * q];
+                sum_k3e += part[2 * q + 1];
+            }
+            const int idx = K - 1 - k;
+            st.inner_iters[idx] = host_st_->iters;
+            st.relres[idx] = host_st_->relres;
+            st.total_inner_iters += host_st_->iters;
+            st.outer_steps = idx + 1;
+            if (host_st_->done != 1 && host_st_->iters >= p.max_inner) st.all_converged = 0;
+            if (host_st_->done == 2) {
+                st.breakdown = 1;
+                throw ApiError{TVD_EBREAKDOWN, "adjoint PCG breakdown: p^T A p <= 0"};
+            }
+        }
+        // u^0 = v: vbar += ubar^0
+        TVD_HIP(hipMemcpyAsync(TmpD_, UbarD_, N_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+        TVD_HIP(launch_add_vec(VbarD_, TmpD_));
+        TVD_HIP(launch_cast_from_double<T>(int(N_), VbarD_, static_cast<T*>(vbarv), s_));
+        TVD_HIP(hipStreamSynchronize(s_));
+        *abar = -sum_ke;
+        *bbar = p.alpha * p.beta * sum_k3e;
+        st.time_setup_s = ms_setup * 1e-3;
+        st.time_inner_s = ms_inner * 1e-3;
+        st.time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    hipError_t launch_add_vec(double* dst, const double* src) {
+        return launch_add_to_double<double>(int(N_), src, dst, s_);
+    }
+
     // One PCG solve: x (X_) starts at u^k (U_), ends at u^{k+1}.
     void pcg(int maxit, double tol, int predicted) {
         TVD_HIP(launch_init_state(st_, tol, s_));
@@ -938,6 +1013,7 @@ class Solver final : public SolverBase {
     LineGeom gxi_{};
     T *Tb_[2] = {nullptr, nullptr}, *W_ = nullptr;
     double *BD_ = nullptr, *TmpD_ = nullptr;
+    double *UbarD_ = nullptr, *VbarD_ = nullptr, *Gd_ = nullptr, *adj_part_ = nullptr;
     std::vector<double> lamh_host_;
     const double *lamh2_ = nullptr, *lamh_ = nullptr;
     AxisPlan<T> planX_{}, planY_{};
@@ -1092,6 +1168,26 @@ int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_param
         if (rc) return rc;
         tvd_stats local;
         h->solver->solve(v_dev, u_dev, *p, stats ? *stats : local);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_solve_adjoint(tvdeblur_t h, const void* iterates_dev, int K, const void* ubar_dev, void* vbar_dev,
+                           double* abar_host, double* bbar_host, const tvd_params* p, tvd_stats* stats) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (!iterates_dev || !ubar_dev || !vbar_dev || !abar_host || !bbar_host || !p)
+        return fail(h, TVD_EINVAL, "NULL argument");
+    if (K < 1 || K > TVD_MAX_OUTER) return fail(h, TVD_EINVAL, "K out of range");
+    if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || p->alpha < 0 || !(p->beta > 0))
+        return fail(h, TVD_EINVAL, "alpha must be >= 0 and beta > 0, both finite");
+    if (p->max_inner < 1 || !(p->inner_tol >= 0)) return fail(h, TVD_EINVAL, "bad inner_tol / max_inner");
+    if (p->precond < TVD_PREC_NONE || p->precond > TVD_PREC_X_D) return fail(h, TVD_EINVAL, "bad preconditioner");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        tvd_stats local;
+        h->solver->solve_adjoint(iterates_dev, K, ubar_dev, vbar_dev, abar_host, bbar_host, *p,
+                                 stats ? *stats : local);
         return TVD_OK;
     });
 }

@@ -188,7 +188,7 @@ int ypass_blocks(int ny, int nx);
 template <typename T>
 hipError_t launch_colpass(const ColPassArgs<T>& a, hipStream_t s);
 template <typename T>
-LineGeom line_geom(int lines, int M);
+LineGeom line_geom(int lines, int n, int M);
 // LDS bytes reserved for a plan's table blob of blob_len complex entries.
 template <typename T>
 size_t lds_table_bytes(int blob_len);
@@ -218,6 +218,17 @@ hipError_t launch_finalize(PcgState* st, const double* rr_part, int n_rr, const 
 template <typename T>
 hipError_t launch_cast_to_double(int n, const T* src, double* dst, hipStream_t s);
 hipError_t launch_init_state(PcgState* st, double tol, hipStream_t s);
+// Adjoint step pieces (differentiation form).
+template <typename T>
+hipError_t launch_adj_accum(int ny, int nx, const T* lam, const T* hlam, const T* uk1, const double* kapd,
+                            double* vbar, double* g, double* part, int* nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_ubar(int ny, int nx, const double* g, const T* uk, double alpha, double* ubar,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_cast_from_double(int n, const double* src, T* dst, hipStream_t s);
+template <typename T>
+hipError_t launch_add_to_double(int n, const T* src, double* dst, hipStream_t s);
 
 // ---- host precomputation (tvd_plan.cpp) ----
 struct PsfFactors {

@@ -1046,11 +1046,12 @@ __global__ void k_gemm_operands(int ny, int nx, const double* __restrict__ kap, 
     B3[g] = (j < nx - 1) ? k * sc * sc : 0.0;
 }
 
-// C = sum_t coef_t op(A_t) B_t, FP64, 64x64 tiles, 4x4 outputs per thread.
+// C = sum_t coef_t op(A_t) B_t, FP64, 64x64 tiles, 4x4 outputs per thread;
+// the next K tile is fetched into registers while the current one is used.
 constexpr int kGT = 64, kGK = 16;
 __global__ void __launch_bounds__(256) k_gemm(const GemmProblem* probs) {
-    __shared__ double As[kGK][kGT + 1];
-    __shared__ double Bs[kGK][kGT + 1];
+    __shared__ double As[2][kGK][kGT + 1];
+    __shared__ double Bs[2][kGK][kGT + 1];
     const GemmProblem& pb = probs[blockIdx.z];
     const int M = pb.M, N = pb.N, K = pb.K;
     if (int(blockIdx.y) * kGT >= M || int(blockIdx.x) * kGT >= N) return;
@@ -1062,42 +1063,60 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmProblem* probs) {
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int term = 0; term < pb.nterms; ++term) {
+    const int ktiles = (K + kGK - 1) / kGK;
+    const int total = pb.nterms * ktiles;
+    double ra[4], rb[4];
+    auto fetch = [&](int step) {
+        const int term = step / ktiles, k0 = (step - term * ktiles) * kGK;
         const double* A = pb.t[term].A;
         const double* B = pb.t[term].B;
         const double cf = pb.t[term].coef;
-        for (int k0 = 0; k0 < K; k0 += kGK) {
-            for (int e = tid; e < kGK * kGT; e += 256) {
-                int kk, mm;
-                double v = 0.0;
-                if (pb.transA) {  // A stored K x M: op(A)[m][k] = A[k][m]
-                    kk = e / kGT;
-                    mm = e % kGT;
-                    if (k0 + kk < K && m0 + mm < M) v = A[size_t(k0 + kk) * M + m0 + mm];
-                } else {          // A stored M x K
-                    mm = e / kGK;
-                    kk = e % kGK;
-                    if (k0 + kk < K && m0 + mm < M) v = A[size_t(m0 + mm) * K + k0 + kk];
-                }
-                As[kk][mm] = cf * v;
-                const int bk = e / kGT, bn = e % kGT;
-                Bs[bk][bn] = (k0 + bk < K && n0 + bn < N) ? B[size_t(k0 + bk) * N + n0 + bn] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + u * 256;
+            int kk, mm;
+            if (pb.transA) {
+                kk = e / kGT;
+                mm = e % kGT;
+                ra[u] = (k0 + kk < K && m0 + mm < M) ? cf * A[size_t(k0 + kk) * M + m0 + mm] : 0.0;
+            } else {
+                mm = e / kGK;
+                kk = e % kGK;
+                ra[u] = (k0 + kk < K && m0 + mm < M) ? cf * A[size_t(m0 + mm) * K + k0 + kk] : 0.0;
             }
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < kGK; ++kk) {
-                double av[4], bv[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) av[a] = As[kk][tm + 16 * a];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tn + 16 * b];
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
-            }
-            __syncthreads();
+            const int bk = e / kGT, bn = e % kGT;
+            rb[u] = (k0 + bk < K && n0 + bn < N) ? B[size_t(k0 + bk) * N + n0 + bn] : 0.0;
         }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + u * 256;
+            if (pb.transA) As[buf][e / kGT][e % kGT] = ra[u];
+            else As[buf][e % kGK][e / kGK] = ra[u];
+            Bs[buf][e / kGT][e % kGT] = rb[u];
+        }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int step = 0; step < total; ++step) {
+        const int buf = step & 1;
+        if (step + 1 < total) fetch(step + 1);
+#pragma unroll
+        for (int kk = 0; kk < kGK; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][tm + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk][tn + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        }
+        if (step + 1 < total) stash(buf ^ 1);
+        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -1166,6 +1185,65 @@ __global__ void k_init_state(PcgState* st, double tol) {
     st->iters = 0;
 }
 
+// Adjoint step: vbar += H lambda; e = D_x lam o D_x u^{k+1} + D_y lam o
+// D_y u^{k+1}; g = kappa^3 e; partials of sum kappa e and sum kappa^3 e.
+template <typename T>
+__global__ void k_adj_accum(int ny, int nx, const T* __restrict__ lam, const T* __restrict__ hlam,
+                            const T* __restrict__ u1, const double* __restrict__ kap, double* vbar, double* g,
+                            double* part) {
+    __shared__ double red[17];
+    double s1 = 0.0, s3 = 0.0;
+    const int n = ny * nx;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int i = k / nx, j = k - i * nx;
+        const double lc = lam[k], uc = u1[k];
+        double e = 0.0;
+        if (i < ny - 1) e += (double(lam[k + nx]) - lc) * (double(u1[k + nx]) - uc);
+        if (j < nx - 1) e += (double(lam[k + 1]) - lc) * (double(u1[k + 1]) - uc);
+        const double kc = kap[k];
+        const double k3e = kc * kc * kc * e;
+        s1 += kc * e;
+        s3 += k3e;
+        g[k] = k3e;
+        vbar[k] += double(hlam[k]);
+    }
+    const double a = block_sum(s1, red);
+    const double b = block_sum(s3, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// ubar^k = alpha [D_x^T (g o D_x u^k) + D_y^T (g o D_y u^k)].
+template <typename T>
+__global__ void k_adj_ubar(int ny, int nx, const double* __restrict__ g, const T* __restrict__ u, double alpha,
+                           double* ubar) {
+    const int n = ny * nx;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int i = k / nx, j = k - i * nx;
+        const double uc = u[k];
+        double s = 0.0;
+        if (i > 0) s += g[k - nx] * (uc - double(u[k - nx]));
+        if (i < ny - 1) s -= g[k] * (double(u[k + nx]) - uc);
+        if (j > 0) s += g[k - 1] * (uc - double(u[k - 1]));
+        if (j < nx - 1) s -= g[k] * (double(u[k + 1]) - uc);
+        ubar[k] = alpha * s;
+    }
+}
+
+template <typename T>
+__global__ void k_cast_from_double(int n, const double* src, T* dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = T(src[k]);
+}
+
+template <typename T>
+__global__ void k_add_to_double(int n, const T* src, double* dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] += double(src[k]);
+}
+
 template <typename T>
 __global__ void k_cast_double(int n, const T* src, double* dst) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1207,13 +1285,15 @@ hipError_t launch_band(const BandArgsT<TX, TS, T, TY>& a0, int ty, hipStream_t s
 }
 
 template <typename T>
-LineGeom line_geom(int lines, int M) {
+LineGeom line_geom(int lines, int n, int M) {
     LineGeom g;
     g.units = (lines + 1) / 2;
-    // line length n < M/2 + 1 and each thread holds at most kLinePos positions
+    // one radix-8 butterfly per thread per stage, and each thread holds at
+    // most kLinePos positions of a line of length n
+    // (one position per thread where possible: shorter serial load/store phases)
     g.tpu = std::min(256, std::max(64, M / 8));
-    while (g.tpu * kLinePos < M / 2 + 2 && g.tpu < 1024) g.tpu *= 2;
-    if (g.tpu * kLinePos < M / 2 + 2) g.tpu = 0;  // line too long for one block
+    while (g.tpu < n && g.tpu < 1024) g.tpu *= 2;
+    if (g.tpu * kLinePos < n) g.tpu = 0;  // line too long for one block
     const size_t per_unit = size_t(2) * padded_len(M) * sizeof(cx<T>);
     int upb = std::max(1, 256 / g.tpu);
     while (upb > 1 && per_unit * upb > 80 * 1024) upb >>= 1;
@@ -1332,10 +1412,43 @@ hipError_t launch_cast_to_double(int n, const T* src, double* dst, hipStream_t s
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_adj_accum(int ny, int nx, const T* lam, const T* hlam, const T* uk1, const double* kapd,
+                            double* vbar, double* g, double* part, int* nblocks, hipStream_t s) {
+    const int nb = elem_blocks(ny * nx, 256, 1024);
+    *nblocks = nb;
+    hipLaunchKernelGGL(k_adj_accum<T>, dim3(nb), dim3(256), 0, s, ny, nx, lam, hlam, uk1, kapd, vbar, g, part);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_ubar(int ny, int nx, const double* g, const T* uk, double alpha, double* ubar, hipStream_t s) {
+    const int nb = elem_blocks(ny * nx, 256, 2048);
+    hipLaunchKernelGGL(k_adj_ubar<T>, dim3(nb), dim3(256), 0, s, ny, nx, g, uk, alpha, ubar);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cast_from_double(int n, const double* src, T* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast_from_double<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_add_to_double(int n, const T* src, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_to_double<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
 #define TVD_INSTANTIATE(T)                                                                                    \
+    template hipError_t launch_adj_accum<T>(int, int, const T*, const T*, const T*, const double*, double*,   \
+                                            double*, double*, int*, hipStream_t);                             \
+    template hipError_t launch_adj_ubar<T>(int, int, const double*, const T*, double, double*, hipStream_t);  \
+    template hipError_t launch_cast_from_double<T>(int, const double*, T*, hipStream_t);                      \
+    template hipError_t launch_add_to_double<T>(int, const T*, double*, hipStream_t);                         \
     template hipError_t launch_band<T, T, T, T>(const BandArgs<T>&, int, hipStream_t, int*);                  \
     template size_t band_lds_bytes<T, T, T, T>(const BandArgs<T>&, int);                                      \
-    template LineGeom line_geom<T>(int, int);                                                                 \
+    template LineGeom line_geom<T>(int, int, int);                                                            \
     template size_t lds_table_bytes<T>(int);                                                                  \
     template hipError_t launch_rowpass<T>(const RowPassArgs<T>&, hipStream_t);                                \
     template hipError_t launch_ypass<T>(const YPassArgs<T>&, hipStream_t, int*);                              \

@@ -29,7 +29,7 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_create", "tvdeblur_set_psf", "tvdeblur_set_bc", "tvdeblur_solve", "tvdeblur_destroy",
     "tvdeblur_last_error", "tvdeblur_op_blur", "tvdeblur_op_blur_adjoint", "tvdeblur_op_setup",
     "tvdeblur_op_normal", "tvdeblur_op_precond", "tvdeblur_op_export", "tvdeblur_set_profiling",
-    "tvdeblur_get_kernel_times",
+    "tvdeblur_get_kernel_times", "tvdeblur_solve_adjoint",
 )
 
 
@@ -94,6 +94,8 @@ def load():
         "tvdeblur_op_export": [vp, i, vp],
         "tvdeblur_set_profiling": [vp, i],
         "tvdeblur_get_kernel_times": [vp, ctypes.POINTER(KernelTimes)],
+        "tvdeblur_solve_adjoint": [vp, vp, i, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d),
+                                   ctypes.POINTER(Params), ctypes.POINTER(Stats)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -182,6 +184,28 @@ class TVDeblur:
             rc = self.lib.tvdeblur_solve(self.h, _ptr(v), _ptr(u), ctypes.byref(p), ctypes.byref(st))
         self._check(rc)
         return u, st.to_dict()
+
+    def solve_adjoint(self, iterates, K, ubar, alpha, beta, inner_tol=1e-6, max_inner=100, precond="x_d"):
+        """Gradients (vbar, alphabar, betabar, stats) of a loss with dl/du^K =
+        ubar, through the K fixed-point steps whose iterates u^0..u^K are in
+        `iterates` (as filled by solve(..., iterates=...))."""
+        import torch
+        self._img(ubar, "ubar")
+        if iterates.dtype != self.dtype or not iterates.is_contiguous() or \
+                iterates.numel() < (K + 1) * self.ny * self.nx:
+            raise ValueError("iterates must hold K+1 contiguous images of the handle's type")
+        vbar = torch.empty_like(ubar)
+        p = Params()
+        p.alpha, p.beta, p.max_outer = float(alpha), float(beta), int(K)
+        p.inner_tol, p.max_inner, p.precond = float(inner_tol), int(max_inner), PRECOND[precond]
+        ab, bb = ctypes.c_double(), ctypes.c_double()
+        st = Stats()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_solve_adjoint(self.h, ctypes.c_void_p(iterates.data_ptr()), int(K), _ptr(ubar),
+                                                 _ptr(vbar), ctypes.byref(ab), ctypes.byref(bb), ctypes.byref(p),
+                                                 ctypes.byref(st))
+        self._check(rc)
+        return vbar, ab.value, bb.value, st.to_dict()
 
     def set_profiling(self, enable):
         self._check(self.lib.tvdeblur_set_profiling(self.h, 1 if enable else 0))
