@@ -206,6 +206,93 @@ int tvdeblur_set_profiling(tvdeblur_t h, int enable);
 /* Copy the accumulated per-class counts and times into *out (host). */
 int tvdeblur_get_kernel_times(tvdeblur_t h, tvd_kernel_times* out);
 
+/* ---- batching form: many independent images, one launch per PCG stage ----
+ *
+ * Each image is its own instance of the problem of eq. (fp) -- its own size,
+ * PSF, alpha and beta -- under one boundary condition and precision for the
+ * whole batch.  Every stage of the method (diffusivity and eigenvalue setup,
+ * residual, the transform passes of the preconditioner of Section 3.2, the
+ * operator application) is one kernel launch covering all images; each image
+ * keeps its own CG scalars and its own stopping test (Section 5), and an
+ * image whose PCG has stopped skips its share of later launches.  The
+ * arithmetic of each image is that of tvdeblur_solve with the same
+ * parameters, so each image's result matches a single-image solve up to
+ * floating-point rounding order.
+ *
+ * Restrictions: separable PSFs (h = g_y g_x^T, e.g. Gaussians) of half-width
+ * <= 16, and a transform preconditioner (TVD_PREC_X, TVD_PREC_D_X or
+ * TVD_PREC_X_D).  Other cases use tvdeblur_solve. */
+
+typedef struct tvdeblur_batch* tvdeblur_batch_t;
+
+typedef struct {
+    int ny, nx;                 /* image size, >= 3 each, <= 2048 */
+    const double* psf_host;     /* row-major py x px PSF, checked as in tvdeblur_set_psf */
+    int py, px;
+} tvd_image_desc;
+
+typedef struct {
+    const double* alpha_host;   /* count per-image alpha (> 0) */
+    const double* beta_host;    /* count per-image beta (> 0), or NULL: beta for all */
+    double beta;
+    int    max_outer;           /* fixed-point steps, 1..TVD_MAX_OUTER */
+    double fp_tol;              /* per image: stop its steps when the relative change
+                                   falls below fp_tol; 0 = every image runs max_outer */
+    double inner_tol;           /* PCG stop ||r|| < inner_tol ||r_0||, per image */
+    int    max_inner;           /* PCG iteration cap per step, >= 1 */
+    int    precond;             /* TVD_PREC_X, TVD_PREC_D_X or TVD_PREC_X_D */
+    int    use_graph;           /* != 0: replay the PCG iteration launches from HIP
+                                   graphs captured on the batch's stream */
+    const int* replay_host;     /* NULL, or count x max_outer PCG iteration counts
+                                   (image-major: [i * max_outer + k]) to run exactly,
+                                   stopping test skipped, as tvd_params.replay_host */
+} tvd_batch_params;
+
+#define TVD_TUNE_MAX 4
+typedef struct {
+    int    count;                       /* images in the batch */
+    int    line_threads;                /* threads per block of the transform passes */
+    int    tables_in_lds;               /* FFT tables staged in LDS */
+    int    from_cache;                  /* choice reused from an earlier batch of the same shapes */
+    int    n_candidates;                /* candidates timed (0 when from_cache) */
+    int    cand_threads[TVD_TUNE_MAX];
+    double cand_us[TVD_TUNE_MAX];       /* time of one set of transform passes */
+    long long graph_launches;           /* graph replays since create */
+    double time_setup_s;                /* last solve: diffusivity/eigenvalue setup */
+    double time_inner_s;                /* last solve: PCG loops */
+} tvd_batch_info;
+
+/* Create a batch of `count` (1..4096) image problems on the current HIP
+ * device.  The PSFs are copied.  Work runs on a stream owned by the batch;
+ * it waits for the work queued so far on hip_stream (a hipStream_t, NULL =
+ * null stream) at each solve, and each solve returns with its results
+ * complete.  At create the thread count of the transform passes is picked by
+ * timing the candidates on this batch's shapes (cached per process by the
+ * shapes, PSF widths, BC and precision).
+ * Errors: TVD_EINVAL, TVD_ENOTSYM, TVD_ENORM, TVD_ESIZE, TVD_EDEVICE,
+ * TVD_ENOMEM (message from tvdeblur_batch_last_error(NULL)). */
+int tvdeblur_batch_create(tvdeblur_batch_t* out, int count, const tvd_image_desc* descs, int precision,
+                          int bc, void* hip_stream);
+
+/* Solve every image: v_dev_host[i] / u_dev_host[i] (host arrays of `count`
+ * device pointers; image i is a dense row-major ny_i x nx_i array of the
+ * batch's element type; no u may alias any v).  u^0 = v.  stats_host (may be
+ * NULL) receives `count` tvd_stats, one per image; their time fields are
+ * the batch's.  A breakdown stops that image only; the call then returns
+ * TVD_EBREAKDOWN after the others have finished.
+ * Errors: TVD_EINVAL, TVD_EDEVICE, TVD_EBREAKDOWN. */
+int tvdeblur_batch_solve(tvdeblur_batch_t b, const void* const* v_dev_host, void* const* u_dev_host,
+                         const tvd_batch_params* p, tvd_stats* stats_host);
+
+/* Tuning choice and timings of the batch (host *out). */
+int tvdeblur_batch_get_info(tvdeblur_batch_t b, tvd_batch_info* out);
+
+/* Release the batch. NULL is accepted. */
+int tvdeblur_batch_destroy(tvdeblur_batch_t b);
+
+/* Message of the last failure on b, or of the last failed batch create when b is NULL. */
+const char* tvdeblur_batch_last_error(tvdeblur_batch_t b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -161,7 +164,12 @@ class KernelTimer {
 };
 
 template <typename T>
+class BatchSolver;
+
+template <typename T>
 class Solver final : public SolverBase {
+    friend class BatchSolver<T>;
+
    public:
     Solver(int ny, int nx, hipStream_t s, size_t max_lds) : ny_(ny), nx_(nx), N_(size_t(ny) * nx), s_(s), max_lds_(max_lds) {
         TVD_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_st_), sizeof(PcgState), hipHostMallocDefault));
@@ -354,12 +362,35 @@ class Solver final : public SolverBase {
         s2.push_back(gp(ny_, nx_, ny_, 1, {{Puy_, Yg_[0], 1.0}, {Puly_, Yg_[1], -2.0}, {Ply_, Yg_[2], 1.0}}, LamX_));
         s2.push_back(gp(ny_, nx_, nx_, 0, {{Zg_[0], Pux_, 1.0}, {Zg_[1], Pulx_, -2.0}, {Zg_[2], Plx_, 1.0}}, LamY_));
         s2.push_back(gp(ny_, nx_, nx_, 0, {{Sd_, Wx_, 1.0}}, LamD_));
+        gemm1_host_ = s1;
+        gemm2_host_ = s2;
         gemm1_ = static_cast<GemmProblem*>(geo_.alloc(s1.size() * sizeof(GemmProblem)));
         gemm2_ = static_cast<GemmProblem*>(geo_.alloc(s2.size() * sizeof(GemmProblem)));
         TVD_HIP(hipMemcpyAsync(gemm1_, s1.data(), s1.size() * sizeof(GemmProblem), hipMemcpyHostToDevice, s_));
         TVD_HIP(hipMemcpyAsync(gemm2_, s2.data(), s2.size() * sizeof(GemmProblem), hipMemcpyHostToDevice, s_));
         TVD_HIP(hipStreamSynchronize(s_));
         have_setup_ = false;
+    }
+
+    // Line geometry of a batched launch whose blocks have `threads` threads,
+    // FFT tables in LDS or not; false (nothing changed) if it does not fit.
+    bool set_batch_geometry(int threads, bool tab_lds) {
+        LineGeom gx = line_geom_block<T>(ny_, nx_, planX_.M, threads);
+        LineGeom gy = line_geom_block<T>(nx_, ny_, planY_.M, threads);
+        if (gx.tpu == 0 || gy.tpu == 0) return false;
+        if (tab_lds) {
+            gx.lds += lds_table_bytes<T>(planX_.blob_len);
+            gy.lds += lds_table_bytes<T>(planY_.blob_len);
+        }
+        LineGeom gxi = gx;
+        if (xpass_) gxi.lds += ((size_t(xband_len_) * sizeof(T) + 1023) / 1024) * 1024;
+        if (std::max({gx.lds, gy.lds, gxi.lds}) + kStaticLds > max_lds_) return false;
+        gx_ = gx;
+        gy_ = gy;
+        gxi_ = gxi;
+        planX_.tables_in_lds = tab_lds ? 1 : 0;
+        planY_.tables_in_lds = tab_lds ? 1 : 0;
+        return true;
     }
 
     // ------------------------------------------------------------ operators
@@ -438,6 +469,25 @@ class Solver final : public SolverBase {
         residual_hp_launch(x, r, rr_out);
         timer_.end(s_);
     }
+    BandArgsT<T, T, double, T> residual_fused_args(const T* x, T* r, double* rr_out) const {
+        BandArgsT<T, T, double, T> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.wy = 2 * my_;
+        a.wx = 2 * mx_;
+        a.nterms = 1;
+        a.By = KyD_;
+        a.Bx = KxD_;
+        a.X = x;
+        a.kap = Kapd_;
+        a.alpha = alpha_;
+        a.Bvec = BD_;
+        a.Y = r;
+        a.dot_part = rr_out;
+        a.dotmode = 2;
+        a.st = st_;
+        return a;
+    }
     void residual_hp_launch(const T* x, T* r, double* rr_out) {
         if (fused_) {
             BandArgsT<T, T, double, T> a{};
@@ -493,6 +543,14 @@ class Solver final : public SolverBase {
     // PCG direction update fused with q = A p, column half (the row half
     // w = (I (x) K_x) z ran inside the inverse row transform).
     void ypass_update(int it) {
+        const YPassArgs<T> a = ypass_args(it);
+        int nb = 0;
+        timer_.begin(KernelTimer::kBand, s_);
+        TVD_HIP(launch_ypass<T>(a, s_, &nb));
+        timer_.end(s_);
+        n_pq_ = nb;
+    }
+    YPassArgs<T> ypass_args(int it) const {
         YPassArgs<T> a{};
         a.ny = ny_;
         a.nx = nx_;
@@ -512,11 +570,7 @@ class Solver final : public SolverBase {
         a.q = Q_;
         a.pq_part = pq_;
         a.st = st_;
-        int nb = 0;
-        timer_.begin(KernelTimer::kBand, s_);
-        TVD_HIP(launch_ypass<T>(a, s_, &nb));
-        timer_.end(s_);
-        n_pq_ = nb;
+        return a;
     }
 
     // PCG direction update fused with q = A p and <p, q> partials.
@@ -798,6 +852,12 @@ class Solver final : public SolverBase {
     }
 
     void rowpass(int it, bool update, T* r, double* part_out, int /*unused*/) {
+        const RowPassArgs<T> a = rowfwd_args(it, update, r, part_out);
+        timer_.begin(KernelTimer::kRowFwd, s_);
+        TVD_HIP(launch_rowpass<T>(a, s_));
+        timer_.end(s_);
+    }
+    RowPassArgs<T> rowfwd_args(int it, bool update, T* r, double* part_out) const {
         RowPassArgs<T> a{};
         a.ny = ny_;
         a.nx = nx_;
@@ -818,11 +878,15 @@ class Solver final : public SolverBase {
         a.part_out = part_out;
         a.st = st_;
         a.iter = it;
-        timer_.begin(KernelTimer::kRowFwd, s_);
-        TVD_HIP(launch_rowpass<T>(a, s_));
-        timer_.end(s_);
+        return a;
     }
     void colpass(int it, bool check, int n_rr, const double* rr = nullptr) {
+        const ColPassArgs<T> a = col_args(it, check, n_rr, rr);
+        timer_.begin(KernelTimer::kCol, s_);
+        TVD_HIP(launch_colpass<T>(a, s_));
+        timer_.end(s_);
+    }
+    ColPassArgs<T> col_args(int it, bool check, int n_rr, const double* rr) const {
         ColPassArgs<T> a{};
         a.ny = ny_;
         a.nx = nx_;
@@ -836,11 +900,15 @@ class Solver final : public SolverBase {
         a.n_rr = n_rr;
         a.st = st_;
         a.iter = it;
-        timer_.begin(KernelTimer::kCol, s_);
-        TVD_HIP(launch_colpass<T>(a, s_));
-        timer_.end(s_);
+        return a;
     }
     void rowpass_inv(T* z, T* r, double* rz_out, bool xpass = false) {
+        const RowPassArgs<T> a = rowinv_args(z, r, rz_out, xpass);
+        timer_.begin(KernelTimer::kRowInv, s_);
+        TVD_HIP(launch_rowpass<T>(a, s_));
+        timer_.end(s_);
+    }
+    RowPassArgs<T> rowinv_args(T* z, T* r, double* rz_out, bool xpass) const {
         RowPassArgs<T> a{};
         a.ny = ny_;
         a.nx = nx_;
@@ -861,9 +929,7 @@ class Solver final : public SolverBase {
         a.dst = z;
         a.part_out = rz_out;
         a.st = st_;
-        timer_.begin(KernelTimer::kRowInv, s_);
-        TVD_HIP(launch_rowpass<T>(a, s_));
-        timer_.end(s_);
+        return a;
     }
 
     // -------------------------------------------------------- op entry points
@@ -1030,10 +1096,531 @@ class Solver final : public SolverBase {
     PcgState* st_ = nullptr;
     PcgState* host_st_ = nullptr;
     GemmProblem *gemm1_ = nullptr, *gemm2_ = nullptr;
+    std::vector<GemmProblem> gemm1_host_, gemm2_host_;
     hipEvent_t ev_a_{}, ev_b_{}, ev_c_{};
     double alpha_ = 0, beta_ = 0;
     int variant_ = TVD_PREC_X_D;
     bool have_setup_ = false;
+};
+
+
+// ---------------------------------------------------------------------------
+// Batching form.  Every stage of the method is one launch over all images
+// (image = blockIdx.z, per-image argument blocks in device memory); each
+// image keeps its own CG scalars and stopping test, and an image whose PCG
+// has stopped skips its blocks.  The per-image arithmetic is that of
+// Solver<T>::pcg on the transform-preconditioned path with the x-pass.
+// ---------------------------------------------------------------------------
+class BatchBase {
+   public:
+    virtual ~BatchBase() = default;
+    virtual void solve(const void* const* v, void* const* u, const tvd_batch_params& p, tvd_stats* st) = 0;
+    virtual void info(tvd_batch_info* out) const = 0;
+};
+
+// Thread count chosen for the transform passes, per process, keyed by the
+// batch's shapes, PSF widths, BC and element type.
+struct TuneChoice {
+    int threads;
+    bool tab_lds;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune_cache;
+
+template <typename T>
+class BatchSolver final : public BatchBase {
+   public:
+    BatchSolver(int count, const tvd_image_desc* d, int bc, hipStream_t user, size_t max_lds)
+        : B_(count), user_(user), max_lds_(max_lds) {
+        TVD_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+        try {
+            TVD_HIP(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
+            TVD_HIP(hipEventCreate(&ev_a_));
+            TVD_HIP(hipEventCreate(&ev_b_));
+            TVD_HIP(hipEventCreate(&ev_c_));
+            TVD_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_st_), B_ * sizeof(PcgState), hipHostMallocDefault));
+            TVD_HIP(hipHostMalloc(reinterpret_cast<void**>(&init_host_), B_ * sizeof(InitArgs), hipHostMallocDefault));
+            std::ostringstream key;
+            key << sizeof(T) << ':' << bc;
+            for (int i = 0; i < B_; ++i) {
+                img_.emplace_back(new Solver<T>(d[i].ny, d[i].nx, s_, max_lds));
+                const std::vector<double> psf(d[i].psf_host, d[i].psf_host + size_t(d[i].py) * d[i].px);
+                img_[i]->build(psf, d[i].py, d[i].px, bc);
+                if (!img_[i]->xpass_)
+                    throw ApiError{TVD_EINVAL, "image " + std::to_string(i) +
+                                                   ": batched solves need a separable PSF of half-width <= 16"};
+                key << ';' << d[i].ny << 'x' << d[i].nx << '/' << d[i].py << 'x' << d[i].px;
+            }
+            key_ = key.str();
+            st_ = static_cast<PcgState*>(arena_.alloc(B_ * sizeof(PcgState)));
+            for (int i = 0; i < B_; ++i) img_[i]->st_ = st_ + i;
+            alloc_tables();
+            tune();
+        } catch (...) {
+            release();
+            throw;
+        }
+    }
+    ~BatchSolver() override { release(); }
+
+    void info(tvd_batch_info* out) const override { *out = info_; }
+
+    void solve(const void* const* v, void* const* u, const tvd_batch_params& p, tvd_stats* stats) override {
+        const auto t0 = std::chrono::steady_clock::now();
+        // inputs were produced on the caller's stream
+        TVD_HIP(hipEventRecord(ev_in_, user_));
+        TVD_HIP(hipStreamWaitEvent(s_, ev_in_, 0));
+        for (int i = 0; i < B_; ++i) {
+            Solver<T>& S = *img_[i];
+            S.alpha_ = p.alpha_host[i];
+            S.beta_ = p.beta_host ? p.beta_host[i] : p.beta;
+            S.variant_ = p.precond;
+            S.n_pq_ = ypass_blocks(S.ny_, S.nx_);
+            S.n_rz_ = S.gx_.blocks;
+        }
+        fill_tables();
+        std::vector<int> frozen(B_, 0), broke(B_, 0), prev(B_, 8);
+        std::vector<tvd_stats> st(B_);
+        for (auto& x : st) {
+            std::memset(&x, 0, sizeof(x));
+            x.all_converged = 1;
+        }
+        for (int i = 0; i < B_; ++i) {
+            Solver<T>& S = *img_[i];
+            S.rhs_hp(static_cast<const T*>(v[i]));
+            TVD_HIP(hipMemcpyAsync(S.U_, v[i], S.N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        }
+        const bool use_d = p.precond == TVD_PREC_X_D;
+        float ms_setup = 0.f, ms_inner = 0.f;
+        for (int k = 0; k < p.max_outer; ++k) {
+            int active = 0, predicted = 1, maxit = p.max_inner;
+            if (p.replay_host) maxit = 0;
+            for (int i = 0; i < B_; ++i) {
+                const int cap = p.replay_host ? p.replay_host[size_t(i) * p.max_outer + k] : 0;
+                const bool off = frozen[i] || broke[i] || (p.replay_host && cap == 0);
+                init_host_[i] = InitArgs{st_ + i, p.replay_host ? 0.0 : p.inner_tol, off ? 1 : 0, cap};
+                if (!off) {
+                    ++active;
+                    predicted = std::max(predicted, p.replay_host ? cap : prev[i]);
+                    if (p.replay_host) maxit = std::max(maxit, cap);
+                }
+            }
+            if (active == 0) {
+                if (!p.replay_host) break;
+                // replay of a step with no PCG iterations in any image: u^{k+1} = u^k
+                for (int i = 0; i < B_; ++i)
+                    if (!frozen[i] && !broke[i]) st[i].outer_steps = k + 1;
+                continue;
+            }
+            TVD_HIP(hipEventRecord(ev_a_, s_));
+            setup_all(use_d);
+            TVD_HIP(hipEventRecord(ev_b_, s_));
+            TVD_HIP(hipMemcpyAsync(init_a_, init_host_, B_ * sizeof(InitArgs), hipMemcpyHostToDevice, s_));
+            TVD_HIP(launch_init_b(init_a_, B_, s_));
+            pcg_all(maxit, predicted, p.use_graph != 0);
+            TVD_HIP(hipMemcpyAsync(host_st_, st_, B_ * sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+            TVD_HIP(hipStreamSynchronize(s_));
+            float a = 0.f, b = 0.f;
+            TVD_HIP(hipEventElapsedTime(&a, ev_a_, ev_b_));
+            ms_setup += a;
+            for (int i = 0; i < B_; ++i) {
+                if (frozen[i] || broke[i]) continue;
+                const PcgState& hs = host_st_[i];
+                tvd_stats& x = st[i];
+                x.inner_iters[k] = hs.iters;
+                x.relres[k] = hs.relres;
+                x.fp_change[k] = hs.fp_change;
+                x.total_inner_iters += hs.iters;
+                x.outer_steps = k + 1;
+                prev[i] = std::max(1, hs.iters);
+                if (hs.done != 1 && hs.iters >= p.max_inner && !p.replay_host) x.all_converged = 0;
+                if (hs.done == 2) {
+                    x.breakdown = 1;
+                    x.all_converged = 0;
+                    broke[i] = 1;
+                }
+                if (p.fp_tol > 0.0 && hs.fp_change < p.fp_tol) frozen[i] = 1;
+            }
+            TVD_HIP(hipEventElapsedTime(&b, ev_b_, ev_c_));
+            ms_inner += b;
+        }
+        for (int i = 0; i < B_; ++i)
+            TVD_HIP(hipMemcpyAsync(u[i], img_[i]->U_, img_[i]->N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        TVD_HIP(hipStreamSynchronize(s_));
+        info_.time_setup_s = ms_setup * 1e-3;
+        info_.time_inner_s = ms_inner * 1e-3;
+        const double total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        bool any_break = false;
+        for (int i = 0; i < B_; ++i) {
+            st[i].time_total_s = total;
+            st[i].time_setup_s = info_.time_setup_s;
+            st[i].time_inner_s = info_.time_inner_s;
+            any_break = any_break || broke[i];
+        }
+        if (stats) std::memcpy(stats, st.data(), B_ * sizeof(tvd_stats));
+        if (any_break) throw ApiError{TVD_EBREAKDOWN, "PCG breakdown (p^T A p <= 0) in at least one image"};
+    }
+
+   private:
+    template <typename A>
+    A* table() {
+        return static_cast<A*>(arena_.alloc(B_ * sizeof(A)));
+    }
+    template <typename A>
+    void put(A* dst, const std::vector<A>& src) {
+        TVD_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(A), hipMemcpyHostToDevice, s_));
+    }
+
+    void alloc_tables() {
+        kap_a_ = table<KappaArgs<T>>();
+        op_a_ = table<OperandArgs>();
+        mu_a_ = table<MuArgs<T>>();
+        init_a_ = table<InitArgs>();
+        cp_ux_ = table<CopyArgs<T>>();
+        cp_xu_ = table<CopyArgs<T>>();
+        res_a_ = table<BandArgsT<T, T, double, T>>();
+        rf0_ = table<RowPassArgs<T>>();
+        rf_[0] = table<RowPassArgs<T>>();
+        rf_[1] = table<RowPassArgs<T>>();
+        ri_[0] = table<RowPassArgs<T>>();
+        ri_[1] = table<RowPassArgs<T>>();
+        c0_ = table<ColPassArgs<T>>();
+        c_ = table<ColPassArgs<T>>();
+        cn_ = table<ColPassArgs<T>>();
+        y1_ = table<YPassArgs<T>>();
+        y_[0] = table<YPassArgs<T>>();
+        y_[1] = table<YPassArgs<T>>();
+        fp_a_ = table<FpArgs<T>>();
+        fin_a_ = table<FinArgs>();
+        // setup GEMM work lists of all images, with and without the D term
+        std::vector<GemmProblem> g1[2], g2[2];
+        for (auto& S : img_) {
+            for (int d = 0; d < 2; ++d) {
+                g1[d].insert(g1[d].end(), S->gemm1_host_.begin(), S->gemm1_host_.begin() + (d ? 7 : 6));
+                g2[d].insert(g2[d].end(), S->gemm2_host_.begin(), S->gemm2_host_.begin() + (d ? 3 : 2));
+            }
+        }
+        for (int d = 0; d < 2; ++d) {
+            n1_[d] = int(g1[d].size());
+            n2_[d] = int(g2[d].size());
+            g1_[d] = static_cast<GemmProblem*>(arena_.alloc(g1[d].size() * sizeof(GemmProblem)));
+            g2_[d] = static_cast<GemmProblem*>(arena_.alloc(g2[d].size() * sizeof(GemmProblem)));
+            put(g1_[d], g1[d]);
+            put(g2_[d], g2[d]);
+        }
+        // grids of the size-independent stages
+        int maxnx = 0, maxny = 0;
+        size_t maxN = 0;
+        for (auto& S : img_) {
+            maxnx = std::max(maxnx, S->nx_);
+            maxny = std::max(maxny, S->ny_);
+            maxN = std::max(maxN, S->N_);
+            maxM_ = std::max({maxM_, S->ny_, S->nx_});
+        }
+        g_px_ = BatchGrid{(maxnx + 255) / 256, maxny, B_, 0, 256};
+        g_el_ = BatchGrid{int((maxN + 255) / 256), 1, B_, 0, 256};
+        g_fp_ = BatchGrid{int(std::min<size_t>(1024, (maxN + 255) / 256)), 1, B_, 0, 256};
+        g_res_ = BatchGrid{0, 0, B_, 0, 0};
+        g_y_ = BatchGrid{0, 0, B_, 0, 0};
+        for (auto& S : img_) {
+            const int ty = S->ty_res_;
+            const int gy = (S->ny_ + ty - 1) / ty;
+            g_res_.gx = std::max(g_res_.gx, band_blocks(S->ny_, S->nx_, ty) / gy);
+            g_res_.gy = std::max(g_res_.gy, gy);
+            BandArgsT<T, T, double, T> probe = S->residual_fused_args(S->X_, S->R_, S->rr_[0]);
+            g_res_.lds = std::max(g_res_.lds, band_lds_bytes(probe, ty));
+            g_y_.gx = std::max(g_y_.gx, (S->nx_ + 63) / 64);
+            g_y_.gy = std::max(g_y_.gy, (S->ny_ + 15) / 16);
+            g_y_.lds = std::max(g_y_.lds, ypass_lds_bytes(2 * S->my_, sizeof(T)));
+        }
+        TVD_HIP(hipStreamSynchronize(s_));
+    }
+
+    // Per-image argument blocks of every stage (after the per-image scalars
+    // and the line geometry are set).
+    void fill_tables() {
+        std::vector<KappaArgs<T>> ka;
+        std::vector<OperandArgs> oa;
+        std::vector<MuArgs<T>> ma;
+        std::vector<CopyArgs<T>> ux, xu;
+        std::vector<BandArgsT<T, T, double, T>> ra;
+        std::vector<RowPassArgs<T>> f0, f1, f2, i0, i1;
+        std::vector<ColPassArgs<T>> c0, c1, cn;
+        std::vector<YPassArgs<T>> y1, ye, yo;
+        std::vector<FpArgs<T>> fa;
+        std::vector<FinArgs> fi;
+        g_rf_ = g_ri_ = g_col_ = BatchGrid{0, 1, B_, 0, line_threads_};
+        for (auto& P : img_) {
+            Solver<T>& S = *P;
+            const int N = int(S.N_);
+            ka.push_back(KappaArgs<T>{S.ny_, S.nx_, S.U_, S.alpha_, S.beta_, S.variant_, S.Kap_, S.Kapd_, S.Sap_,
+                                      S.Smu_, S.Dd_});
+            oa.push_back(OperandArgs{S.ny_, S.nx_, S.Kapd_, S.Smu_, S.Aop_[0], S.Aop_[1], S.Aop_[2], S.Bop_[0],
+                                     S.Bop_[1], S.Bop_[2]});
+            ma.push_back(MuArgs<T>{N, S.lamh2_, S.LamX_, S.LamY_, S.LamD_, S.variant_ == TVD_PREC_X_D, S.alpha_,
+                                   S.Mu_, S.MuInv_});
+            ux.push_back(CopyArgs<T>{N, S.U_, S.X_});
+            xu.push_back(CopyArgs<T>{N, S.X_, S.U_});
+            BandArgsT<T, T, double, T> r = S.residual_fused_args(S.X_, S.R_, S.rr_[0]);
+            r.tile_y = S.ty_res_;
+            r.bgy = (S.ny_ + r.tile_y - 1) / r.tile_y;
+            r.bgx = band_blocks(S.ny_, S.nx_, r.tile_y) / r.bgy;
+            ra.push_back(r);
+            f0.push_back(S.rowfwd_args(0, false, S.R_, nullptr));
+            f1.push_back(S.rowfwd_args(1, true, S.R_, S.rr_[0]));
+            f2.push_back(S.rowfwd_args(2, true, S.R_, S.rr_[0]));
+            i0.push_back(S.rowinv_args(S.Z_, S.R_, S.rz_[0], true));
+            i1.push_back(S.rowinv_args(S.Z_, S.R_, S.rz_[1], true));
+            c0.push_back(S.col_args(0, true, S.nb_res_, S.rr_[0]));
+            c1.push_back(S.col_args(1, true, S.gx_.blocks, S.rr_[0]));
+            cn.push_back(S.col_args(0, false, 0, nullptr));
+            y1.push_back(S.ypass_args(1));
+            ye.push_back(S.ypass_args(2));
+            yo.push_back(S.ypass_args(3));
+            const int nfp = std::min(1024, (N + 255) / 256);
+            fa.push_back(FpArgs<T>{N, nfp, S.X_, S.U_, S.fp_});
+            fi.push_back(FinArgs{S.st_, S.rr_[0], S.gx_.blocks, S.fp_, nfp, 0});
+            g_rf_.gx = std::max(g_rf_.gx, S.gx_.blocks);
+            g_rf_.lds = std::max(g_rf_.lds, S.gx_.lds);
+            g_ri_.gx = std::max(g_ri_.gx, S.gxi_.blocks);
+            g_ri_.lds = std::max(g_ri_.lds, S.gxi_.lds);
+            g_col_.gx = std::max(g_col_.gx, S.gy_.blocks);
+            g_col_.lds = std::max(g_col_.lds, S.gy_.lds);
+        }
+        put(kap_a_, ka);
+        put(op_a_, oa);
+        put(mu_a_, ma);
+        put(cp_ux_, ux);
+        put(cp_xu_, xu);
+        put(res_a_, ra);
+        put(rf0_, f0);
+        put(rf_[1], f1);
+        put(rf_[0], f2);
+        put(ri_[0], i0);
+        put(ri_[1], i1);
+        put(c0_, c0);
+        put(c_, c1);
+        put(cn_, cn);
+        put(y1_, y1);
+        put(y_[0], ye);
+        put(y_[1], yo);
+        put(fp_a_, fa);
+        fin_host_ = fi;
+        put(fin_a_, fi);
+        TVD_HIP(hipStreamSynchronize(s_));
+    }
+
+    void setup_all(bool use_d) {
+        TVD_HIP(launch_kappa_b<T>(kap_a_, g_px_, s_));
+        TVD_HIP(launch_operands_b(op_a_, g_px_, s_));
+        TVD_HIP(launch_gemm(g1_[use_d], n1_[use_d], maxM_, maxM_, s_));
+        TVD_HIP(launch_gemm(g2_[use_d], n2_[use_d], maxM_, maxM_, s_));
+        TVD_HIP(launch_mu_b<T>(mu_a_, g_el_, s_));
+    }
+
+    // One PCG iteration of every image (the tail of iteration maxit stops
+    // after the x, r update, as in the single-image loop).
+    void iteration(int it, bool tail) {
+        TVD_HIP(launch_ypass_b<T>(it == 1 ? y1_ : y_[it & 1], g_y_, s_));
+        TVD_HIP(launch_rowpass_b<T>(rf_[it & 1], it, tab_lds_, g_rf_, s_));
+        if (tail) return;
+        TVD_HIP(launch_colpass_b<T>(c_, it, tab_lds_, g_col_, s_));
+        TVD_HIP(launch_rowpass_b<T>(ri_[it & 1], it, tab_lds_, g_ri_, s_));
+    }
+
+    static constexpr int kChunk = 2;  // iterations per captured graph
+
+    hipGraphExec_t graph_for(int it0) {
+        auto f = graphs_.find(it0);
+        if (f != graphs_.end()) return f->second;
+        hipGraph_t g = nullptr;
+        TVD_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeRelaxed));
+        try {
+            for (int it = it0; it < it0 + kChunk; ++it) iteration(it, false);
+        } catch (...) {
+            hipGraph_t dummy = nullptr;
+            (void)hipStreamEndCapture(s_, &dummy);
+            if (dummy) (void)hipGraphDestroy(dummy);
+            throw;
+        }
+        TVD_HIP(hipStreamEndCapture(s_, &g));
+        hipGraphExec_t e = nullptr;
+        const hipError_t rc = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        TVD_HIP(rc);
+        graphs_[it0] = e;
+        return e;
+    }
+
+    void pcg_all(int maxit, int predicted, bool use_graph) {
+        TVD_HIP(launch_copy_b<T>(cp_ux_, g_el_, s_));
+        TVD_HIP((launch_band_b<T, T, double, T>(res_a_, g_res_, s_)));
+        TVD_HIP(launch_rowpass_b<T>(rf0_, 0, tab_lds_, g_rf_, s_));
+        TVD_HIP(launch_colpass_b<T>(c0_, 0, tab_lds_, g_col_, s_));
+        TVD_HIP(launch_rowpass_b<T>(ri_[0], 0, tab_lds_, g_ri_, s_));
+        int next_poll = std::max(2, predicted - 1);
+        int it = 1;
+        while (it <= maxit) {
+            int last = it;
+            if (use_graph && it + kChunk - 1 < maxit) {
+                TVD_HIP(hipGraphLaunch(graph_for(it), s_));
+                ++info_.graph_launches;
+                last = it + kChunk - 1;
+            } else {
+                iteration(it, it == maxit);
+            }
+            it = last + 1;
+            if (last >= next_poll && last < maxit) {
+                TVD_HIP(hipMemcpyAsync(host_st_, st_, B_ * sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+                TVD_HIP(hipStreamSynchronize(s_));
+                bool all = true;
+                for (int i = 0; i < B_ && all; ++i) all = host_st_[i].done != 0;
+                if (all) break;
+                next_poll = last + 2;
+            }
+        }
+        TVD_HIP(launch_fpchange_b<T>(fp_a_, g_fp_, s_));
+        for (auto& f : fin_host_) f.max_iter = maxit;
+        put(fin_a_, fin_host_);
+        TVD_HIP(launch_finalize_b(fin_a_, B_, s_));
+        TVD_HIP(launch_copy_b<T>(cp_xu_, g_el_, s_));
+        TVD_HIP(hipEventRecord(ev_c_, s_));
+    }
+
+    // Pick the thread count of the transform passes by timing them on this
+    // batch (forward row pass, column pass, inverse row pass with x-pass).
+    void tune() {
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto f = g_tune_cache.find(key_);
+            if (f != g_tune_cache.end()) {
+                apply(f->second.threads, f->second.tab_lds);
+                info_.from_cache = 1;
+                return;
+            }
+        }
+        // defined contents for the timing runs
+        for (auto& S : img_) {
+            TVD_HIP(hipMemsetAsync(S->R_, 0, S->N_ * sizeof(T), s_));
+            TVD_HIP(hipMemsetAsync(S->Sap_, 0, S->N_ * sizeof(T), s_));
+            TVD_HIP(hipMemsetAsync(S->MuInv_, 0, S->N_ * sizeof(T), s_));
+            S->alpha_ = 1e-3;
+            S->beta_ = 0.1;
+            S->variant_ = TVD_PREC_X_D;
+            S->n_pq_ = ypass_blocks(S->ny_, S->nx_);
+        }
+        for (int i = 0; i < B_; ++i) init_host_[i] = InitArgs{st_ + i, 0.0, 0, 0};
+        TVD_HIP(hipMemcpyAsync(init_a_, init_host_, B_ * sizeof(InitArgs), hipMemcpyHostToDevice, s_));
+        TVD_HIP(launch_init_b(init_a_, B_, s_));
+        TuneChoice best{0, false};
+        double best_us = 0.0;
+        for (int threads : {256, 512, 1024}) {
+            bool tab = true;
+            if (!apply(threads, true)) {
+                if (!apply(threads, false)) continue;
+                tab = false;
+            }
+            for (auto& S : img_) S->n_rz_ = S->gx_.blocks;
+            fill_tables();
+            auto pass = [&]() {
+                TVD_HIP(launch_rowpass_b<T>(rf0_, 0, tab_lds_, g_rf_, s_));
+                TVD_HIP(launch_colpass_b<T>(cn_, 0, tab_lds_, g_col_, s_));
+                TVD_HIP(launch_rowpass_b<T>(ri_[0], 0, tab_lds_, g_ri_, s_));
+            };
+            pass();
+            TVD_HIP(hipEventRecord(ev_a_, s_));
+            constexpr int kReps = 5;
+            for (int r = 0; r < kReps; ++r) pass();
+            TVD_HIP(hipEventRecord(ev_b_, s_));
+            TVD_HIP(hipEventSynchronize(ev_b_));
+            float ms = 0.f;
+            TVD_HIP(hipEventElapsedTime(&ms, ev_a_, ev_b_));
+            const double us = 1e3 * ms / kReps;
+            if (info_.n_candidates < TVD_TUNE_MAX) {
+                info_.cand_threads[info_.n_candidates] = threads;
+                info_.cand_us[info_.n_candidates] = us;
+                ++info_.n_candidates;
+            }
+            if (best.threads == 0 || us < best_us) {
+                best = TuneChoice{threads, tab};
+                best_us = us;
+            }
+        }
+        if (best.threads == 0) throw ApiError{TVD_ESIZE, "no transform-pass geometry fits the batch"};
+        apply(best.threads, best.tab_lds);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key_] = best;
+    }
+
+    bool apply(int threads, bool tab) {
+        for (auto& S : img_)
+            if (!S->set_batch_geometry(threads, tab)) {
+                // restore a consistent state on the images already changed
+                if (line_threads_) {
+                    for (auto& R : img_) R->set_batch_geometry(line_threads_, tab_lds_);
+                }
+                return false;
+            }
+        line_threads_ = threads;
+        tab_lds_ = tab;
+        info_.count = B_;
+        info_.line_threads = threads;
+        info_.tables_in_lds = tab ? 1 : 0;
+        for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+        graphs_.clear();
+        return true;
+    }
+
+    void release() {
+        if (s_) (void)hipStreamSynchronize(s_);
+        for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+        graphs_.clear();
+        img_.clear();
+        arena_.release();
+        if (host_st_) (void)hipHostFree(host_st_);
+        if (init_host_) (void)hipHostFree(init_host_);
+        host_st_ = nullptr;
+        init_host_ = nullptr;
+        if (ev_in_) (void)hipEventDestroy(ev_in_);
+        if (ev_a_) (void)hipEventDestroy(ev_a_);
+        if (ev_b_) (void)hipEventDestroy(ev_b_);
+        if (ev_c_) (void)hipEventDestroy(ev_c_);
+        ev_in_ = ev_a_ = ev_b_ = ev_c_ = nullptr;
+        if (s_) (void)hipStreamDestroy(s_);
+        s_ = nullptr;
+    }
+
+    int B_;
+    hipStream_t user_ = nullptr, s_ = nullptr;
+    size_t max_lds_;
+    std::string key_;
+    std::vector<std::unique_ptr<Solver<T>>> img_;
+    DeviceArena arena_;
+    PcgState* st_ = nullptr;
+    PcgState* host_st_ = nullptr;
+    InitArgs* init_host_ = nullptr;
+    hipEvent_t ev_in_ = nullptr, ev_a_ = nullptr, ev_b_ = nullptr, ev_c_ = nullptr;
+    KappaArgs<T>* kap_a_ = nullptr;
+    OperandArgs* op_a_ = nullptr;
+    MuArgs<T>* mu_a_ = nullptr;
+    InitArgs* init_a_ = nullptr;
+    CopyArgs<T>*cp_ux_ = nullptr, *cp_xu_ = nullptr;
+    BandArgsT<T, T, double, T>* res_a_ = nullptr;
+    RowPassArgs<T>*rf0_ = nullptr, *rf_[2] = {}, *ri_[2] = {};
+    ColPassArgs<T>*c0_ = nullptr, *c_ = nullptr, *cn_ = nullptr;
+    YPassArgs<T>*y1_ = nullptr, *y_[2] = {};
+    FpArgs<T>* fp_a_ = nullptr;
+    FinArgs* fin_a_ = nullptr;
+    std::vector<FinArgs> fin_host_;
+    GemmProblem* g1_[2] = {};
+    GemmProblem* g2_[2] = {};
+    int n1_[2] = {}, n2_[2] = {};
+    int maxM_ = 0;
+    BatchGrid g_px_{}, g_el_{}, g_fp_{}, g_res_{}, g_y_{}, g_rf_{}, g_ri_{}, g_col_{};
+    int line_threads_ = 0;
+    bool tab_lds_ = false;
+    std::map<int, hipGraphExec_t> graphs_;
+    tvd_batch_info info_{};
 };
 
 }  // namespace
@@ -1203,6 +1790,136 @@ int tvdeblur_destroy(tvdeblur_t h) {
 }
 
 const char* tvdeblur_last_error(tvdeblur_t h) { return h ? h->err.c_str() : tvd::g_create_error.c_str(); }
+
+}  // extern "C"
+
+struct tvdeblur_batch {
+    std::string err;
+    int count = 0;
+    std::unique_ptr<tvd::BatchBase> impl;
+};
+
+namespace {
+
+std::string g_batch_create_error;
+
+int bfail(tvdeblur_batch_t b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_batch_create_error = msg;
+    return code;
+}
+
+template <typename F>
+int bguarded(tvdeblur_batch_t b, F&& f) {
+    try {
+        return f();
+    } catch (const tvd::ApiError& e) {
+        return bfail(b, e.code, e.msg);
+    } catch (const tvd::HipError& e) {
+        return bfail(b, TVD_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc&) {
+        return bfail(b, TVD_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return bfail(b, TVD_EDEVICE, "unexpected internal error");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvdeblur_batch_create(tvdeblur_batch_t* out, int count, const tvd_image_desc* descs, int precision, int bc,
+                          void* hip_stream) {
+    if (!out) return bfail(nullptr, TVD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > 4096) return bfail(nullptr, TVD_EINVAL, "count must be in 1..4096");
+    if (!descs) return bfail(nullptr, TVD_EINVAL, "descs is NULL");
+    if (precision != TVD_F64 && precision != TVD_F32_MIXED) return bfail(nullptr, TVD_EINVAL, "bad precision");
+    if (bc != TVD_BC_REFLECTIVE && bc != TVD_BC_ANTIREFLECTIVE) return bfail(nullptr, TVD_EINVAL, "bad boundary condition");
+    for (int i = 0; i < count; ++i) {
+        const tvd_image_desc& d = descs[i];
+        const std::string who = "image " + std::to_string(i) + ": ";
+        if (d.ny < 3 || d.nx < 3 || d.ny > 2048 || d.nx > 2048)
+            return bfail(nullptr, TVD_ESIZE, who + "sides must be in 3..2048");
+        std::string err;
+        const int rc = tvd::validate_psf(d.psf_host, d.py, d.px, err);
+        if (rc == -1) return bfail(nullptr, TVD_EINVAL, who + err);
+        if (rc == -2) return bfail(nullptr, TVD_ENOTSYM, who + err);
+        if (rc == -3) return bfail(nullptr, TVD_ENORM, who + err);
+        const int my = d.py / 2, mx = d.px / 2;
+        const int lim = bc == TVD_BC_ANTIREFLECTIVE ? 1 : 0;
+        if (my > d.ny - lim || mx > d.nx - lim) return bfail(nullptr, TVD_ESIZE, who + "PSF too large for the image");
+    }
+    tvdeblur_batch_t b = new (std::nothrow) tvdeblur_batch();
+    if (!b) return bfail(nullptr, TVD_ENOMEM, "host allocation failed");
+    b->count = count;
+    const int rc = bguarded(nullptr, [&]() {
+        int dev = 0, lds = 0;
+        TVD_HIP(hipGetDevice(&dev));
+        TVD_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        hipStream_t us = static_cast<hipStream_t>(hip_stream);
+        if (precision == TVD_F64) b->impl.reset(new tvd::BatchSolver<double>(count, descs, bc, us, size_t(lds)));
+        else b->impl.reset(new tvd::BatchSolver<float>(count, descs, bc, us, size_t(lds)));
+        return TVD_OK;
+    });
+    if (rc != TVD_OK) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return TVD_OK;
+}
+
+int tvdeblur_batch_solve(tvdeblur_batch_t b, const void* const* v_dev_host, void* const* u_dev_host,
+                         const tvd_batch_params* p, tvd_stats* stats_host) {
+    if (!b) return bfail(nullptr, TVD_EINVAL, "NULL batch");
+    if (!v_dev_host || !u_dev_host || !p || !p->alpha_host) return bfail(b, TVD_EINVAL, "NULL argument");
+    if (p->max_outer < 1 || p->max_outer > TVD_MAX_OUTER) return bfail(b, TVD_EINVAL, "max_outer out of range");
+    if (p->max_inner < 1 || !(p->inner_tol >= 0) || !(p->fp_tol >= 0))
+        return bfail(b, TVD_EINVAL, "bad inner_tol / max_inner / fp_tol");
+    if (p->precond != TVD_PREC_X && p->precond != TVD_PREC_D_X && p->precond != TVD_PREC_X_D)
+        return bfail(b, TVD_EINVAL, "batched solves take TVD_PREC_X, TVD_PREC_D_X or TVD_PREC_X_D");
+    if (p->replay_host)
+        for (size_t k = 0; k < size_t(b->count) * p->max_outer; ++k)
+            if (p->replay_host[k] < 0 || p->replay_host[k] > 100000)
+                return bfail(b, TVD_EINVAL, "replay counts must be in 0..100000");
+    std::vector<const void*> vs(v_dev_host, v_dev_host + b->count);
+    std::sort(vs.begin(), vs.end());
+    for (int i = 0; i < b->count; ++i) {
+        const double a = p->alpha_host[i];
+        const double be = p->beta_host ? p->beta_host[i] : p->beta;
+        if (!std::isfinite(a) || !std::isfinite(be) || a < 0 || !(be > 0))
+            return bfail(b, TVD_EINVAL, "image " + std::to_string(i) + ": alpha must be >= 0 and beta > 0, both finite");
+        if (!v_dev_host[i] || !u_dev_host[i]) return bfail(b, TVD_EINVAL, "NULL image pointer");
+        if (std::binary_search(vs.begin(), vs.end(), static_cast<const void*>(u_dev_host[i])))
+            return bfail(b, TVD_EINVAL, "an output aliases an input");
+    }
+    return bguarded(b, [&]() {
+        b->impl->solve(v_dev_host, u_dev_host, *p, stats_host);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_batch_get_info(tvdeblur_batch_t b, tvd_batch_info* out) {
+    if (!b) return bfail(nullptr, TVD_EINVAL, "NULL batch");
+    if (!out) return bfail(b, TVD_EINVAL, "out is NULL");
+    b->impl->info(out);
+    return TVD_OK;
+}
+
+int tvdeblur_batch_destroy(tvdeblur_batch_t b) {
+    if (!b) return TVD_OK;
+    bguarded(b, [&]() {
+        b->impl.reset();
+        return TVD_OK;
+    });
+    delete b;
+    return TVD_OK;
+}
+
+const char* tvdeblur_batch_last_error(tvdeblur_batch_t b) {
+    return b ? b->err.c_str() : g_batch_create_error.c_str();
+}
 
 int tvdeblur_op_blur(tvdeblur_t h, const void* x_dev, void* y_dev) {
     if (!h || !x_dev || !y_dev) return fail(h, TVD_EINVAL, "NULL argument");

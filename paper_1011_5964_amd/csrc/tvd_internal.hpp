@@ -23,9 +23,10 @@ struct PcgState {
     double tol;        // inner tolerance
     double relres;     // ||r_i|| / ||r_0|| at the last convergence test
     double fp_change;  // ||x - u|| / ||x||, filled by the step finaliser
-    int done;          // 0 running, 1 converged, 2 breakdown
+    int done;          // 0 running, 1 converged, 2 breakdown, 3 no steps this solve
     int iters;         // iterations completed when done != 0
-    int pad[2];
+    int cap;           // > 0: stop after exactly this many iterations (replay)
+    int pad;
 };
 
 // Transform plan for one axis: 1D DST-I on the interior (anti-reflective)
@@ -87,6 +88,7 @@ struct BandArgsT {
     int dotmode;           // 0 none, 1 <stencil input, result>, 2 <Y, Y>
     const PcgState* st;    // exit when st->done (nullable)
     int tile_y;            // tile height (8 or 16), chosen by the launcher
+    int bgx, bgy;          // this image's grid (set by the launcher; batched launches)
 };
 template <typename T>
 using BandArgs = BandArgsT<T, T, T, T>;
@@ -171,6 +173,94 @@ struct GemmProblem {
     GemmTerm t[3];
     double* C;
 };
+
+// Per-image argument blocks of the small per-step kernels (batched launches).
+template <typename T>
+struct KappaArgs {
+    int ny, nx;
+    const T* u;
+    double alpha, beta;
+    int variant;
+    T* kap;
+    double* kapd;
+    T* s_apply;
+    double* s_mu;
+    double* Dd;
+};
+struct OperandArgs {
+    int ny, nx;
+    const double* kapd;
+    const double* s_mu;
+    double *A1, *A2, *A3, *B1, *B2, *B3;
+};
+template <typename T>
+struct MuArgs {
+    int n;
+    const double *lamh2, *lamx, *lamy, *lamd;
+    int use_lamd;
+    double alpha;
+    double* mu;
+    T* muinv;
+};
+template <typename T>
+struct FpArgs {
+    int n, nb;
+    const T* x;
+    const T* u;
+    double* part;
+};
+struct FinArgs {
+    PcgState* st;
+    const double* rr_part;
+    int n_rr;
+    const double* fp_part;
+    int n_fp;
+    int max_iter;
+};
+struct InitArgs {
+    PcgState* st;
+    double tol;
+    int frozen;  // nonzero: the image takes no PCG steps (done = 3)
+    int cap;     // PcgState::cap
+};
+template <typename T>
+struct CopyArgs {
+    int n;
+    const T* src;
+    T* dst;
+};
+
+// Batched launches: one kernel per stage for all images of a batch
+// (image = blockIdx.z, argument blocks in device memory).
+struct BatchGrid {
+    int gx, gy, count;
+    size_t lds;
+    int threads;
+};
+template <typename T>
+hipError_t launch_kappa_b(const KappaArgs<T>* a, BatchGrid g, hipStream_t s);
+hipError_t launch_operands_b(const OperandArgs* a, BatchGrid g, hipStream_t s);
+template <typename T>
+hipError_t launch_mu_b(const MuArgs<T>* a, BatchGrid g, hipStream_t s);
+template <typename T>
+hipError_t launch_fpchange_b(const FpArgs<T>* a, BatchGrid g, hipStream_t s);
+hipError_t launch_finalize_b(const FinArgs* a, int count, hipStream_t s);
+hipError_t launch_init_b(const InitArgs* a, int count, hipStream_t s);
+template <typename T>
+hipError_t launch_copy_b(const CopyArgs<T>* a, BatchGrid g, hipStream_t s);
+template <typename TX, typename TS, typename TA, typename TY>
+hipError_t launch_band_b(const BandArgsT<TX, TS, TA, TY>* a, BatchGrid g, hipStream_t s);
+template <typename T>
+hipError_t launch_rowpass_b(const RowPassArgs<T>* a, int it, bool tab_lds, BatchGrid g, hipStream_t s);
+template <typename T>
+hipError_t launch_colpass_b(const ColPassArgs<T>* a, int it, bool tab_lds, BatchGrid g, hipStream_t s);
+template <typename T>
+hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s);
+// Line geometry for a batched pass whose blocks all have `threads` threads
+// (tpu = 0 if a line does not fit).
+template <typename T>
+LineGeom line_geom_block(int lines, int n, int M, int threads);
+size_t ypass_lds_bytes(int w, size_t elem);
 
 // ---- kernel launchers (tvd_kernels.hip) ----
 // Launch with tile height ty (8 or 16); band_lds_bytes gives the dynamic

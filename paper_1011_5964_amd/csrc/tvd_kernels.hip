@@ -90,7 +90,7 @@ __device__ __forceinline__ void stage_lds(int count, int tid, int nthreads, Load
 }
 
 template <typename TX, typename TS, typename T, typename TOut>
-__global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut> a) {
+__device__ __forceinline__ void band_body(const BandArgsT<TX, TS, T, TOut>& a, int bx, int by, int gx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[17];
     if (a.st && a.st->done) return;
@@ -99,8 +99,8 @@ __global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut
     const int tx = tid & (kBandTX - 1);
     const int ty = tid / kBandTX;            // 0..3
     const int TY = a.tile_y;
-    const int i0 = blockIdx.y * TY;
-    const int j0 = blockIdx.x * kBandTX;
+    const int i0 = by * TY;
+    const int j0 = bx * kBandTX;
     const int ny = a.ny, nx = a.nx;
     const bool stencil = a.kap != nullptr;
     const bool sten_tile = stencil && a.S == nullptr;
@@ -290,8 +290,21 @@ __global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut
     }
     if (a.dotmode) {
         const double s = block_sum(dot, red);
-        if (tid == 0) a.dot_part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+        if (tid == 0) a.dot_part[by * gx + bx] = s;
     }
+}
+
+template <typename TX, typename TS, typename T, typename TOut>
+__global__ void __launch_bounds__(kBandThreads) k_band(BandArgsT<TX, TS, T, TOut> a) {
+    band_body(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// Batched launch: image blockIdx.z, its own grid (bgx, bgy) inside the launch grid.
+template <typename TX, typename TS, typename T, typename TOut>
+__global__ void __launch_bounds__(kBandThreads) k_band_b(const BandArgsT<TX, TS, T, TOut>* __restrict__ as) {
+    const BandArgsT<TX, TS, T, TOut> a = as[blockIdx.z];
+    if (int(blockIdx.x) >= a.bgx || int(blockIdx.y) >= a.bgy) return;
+    band_body(a, blockIdx.x, blockIdx.y, a.bgx);
 }
 
 // ------------------------------------------------------------------------
@@ -539,13 +552,13 @@ constexpr int kLinePos = 2;  // positions per thread per line (n <= 2 * tpu)
 // Row pass.  mode 0: (optional x,r update) then T1 = Qx (s o r) row-wise.
 //            mode 1: z = s o (Qx^T T2) row-wise, <r, z> partials.
 template <typename T, bool kTabLds>
-__global__ void k_rowpass(RowPassArgs<T> a) {
+__device__ __forceinline__ void rowpass_body(const RowPassArgs<T>& a, int bx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[17];
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int ul = tid / a.g.tpu, lt = tid - ul * a.g.tpu;
-    const int unit = blockIdx.x * a.g.upb + ul;
+    const int unit = bx * a.g.upb + ul;
     const int nx = a.nx, ny = a.ny;
     const int tpu = a.g.tpu;
     cx<T>* tab = reinterpret_cast<cx<T>*>(smem_raw);
@@ -601,7 +614,7 @@ __global__ void k_rowpass(RowPassArgs<T> a) {
             const double g = block_sum(pq, red);
             const double rz = block_sum(rzp, red);
             if (!(g > 0.0)) {  // curvature <= 0 (or NaN): stop, keep x_{i-1}
-                if (blockIdx.x == 0 && tid == 0) {
+                if (bx == 0 && tid == 0) {
                     a.st->done = 2;
                     a.st->iters = a.iter - 1;
                 }
@@ -647,7 +660,7 @@ __global__ void k_rowpass(RowPassArgs<T> a) {
         }
         if (upd) {
             const double sm = block_sum(part, red);
-            if (tid == 0) a.part_out[blockIdx.x] = sm;
+            if (tid == 0) a.part_out[bx] = sm;
         }
     } else {
         T zpa[kLinePos], zpb[kLinePos];
@@ -720,20 +733,33 @@ __global__ void k_rowpass(RowPassArgs<T> a) {
             }
         }
         const double sm = block_sum(part, red);
-        if (tid == 0) a.part_out[blockIdx.x] = sm;
+        if (tid == 0) a.part_out[bx] = sm;
     }
+}
+
+template <typename T, bool kTabLds>
+__global__ void k_rowpass(RowPassArgs<T> a) {
+    rowpass_body<T, kTabLds>(a, blockIdx.x);
+}
+
+template <typename T, bool kTabLds>
+__global__ void k_rowpass_b(const RowPassArgs<T>* __restrict__ as, int it) {
+    RowPassArgs<T> a = as[blockIdx.z];
+    if (int(blockIdx.x) >= a.g.blocks || a.st->done) return;  // converged images idle
+    a.iter = it;
+    rowpass_body<T, kTabLds>(a, blockIdx.x);
 }
 
 // Column pass: convergence test, forward column transform, divide by mu,
 // inverse column transform.
 template <typename T, bool kTabLds>
-__global__ void k_colpass(ColPassArgs<T> a) {
+__device__ __forceinline__ void colpass_body(const ColPassArgs<T>& a, int bx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[17];
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int ul = tid / a.g.tpu, lt = tid - ul * a.g.tpu;
-    const int unit = blockIdx.x * a.g.upb + ul;
+    const int unit = bx * a.g.upb + ul;
     const int nx = a.nx, ny = a.ny;
     const int tpu = a.g.tpu;
     cx<T>* tab = reinterpret_cast<cx<T>*>(smem_raw);
@@ -750,6 +776,7 @@ __global__ void k_colpass(ColPassArgs<T> a) {
     const int done = a.st->done;
     const double r0 = a.st->r0norm;
     const double tol = a.st->tol;
+    const int cap = a.st->cap;
     const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, nthr) : 0.0;
     T xa[kLinePos], xb[kLinePos], ma[kLinePos], mb[kLinePos];
 #pragma unroll
@@ -767,7 +794,7 @@ __global__ void k_colpass(ColPassArgs<T> a) {
     if (a.check) {
         const double rn = sqrt(block_sum(rrp, red));
         if (a.iter == 0) {
-            if (blockIdx.x == 0 && tid == 0) {
+            if (bx == 0 && tid == 0) {
                 a.st->r0norm = rn;
                 a.st->relres = rn > 0.0 ? 1.0 : 0.0;
                 if (rn == 0.0) {
@@ -777,9 +804,9 @@ __global__ void k_colpass(ColPassArgs<T> a) {
             }
             if (rn == 0.0) return;
         } else {
-            if (blockIdx.x == 0 && tid == 0) a.st->relres = rn / r0;
-            if (rn < tol * r0) {
-                if (blockIdx.x == 0 && tid == 0) {
+            if (bx == 0 && tid == 0) a.st->relres = rn / r0;
+            if (rn < tol * r0 || (cap > 0 && a.iter >= cap)) {
+                if (bx == 0 && tid == 0) {
                     a.st->done = 1;
                     a.st->iters = a.iter;
                 }
@@ -827,16 +854,29 @@ __global__ void k_colpass(ColPassArgs<T> a) {
     }
 }
 
+template <typename T, bool kTabLds>
+__global__ void k_colpass(ColPassArgs<T> a) {
+    colpass_body<T, kTabLds>(a, blockIdx.x);
+}
+
+template <typename T, bool kTabLds>
+__global__ void k_colpass_b(const ColPassArgs<T>* __restrict__ as, int it) {
+    ColPassArgs<T> a = as[blockIdx.z];
+    if (int(blockIdx.x) >= a.g.blocks || a.st->done) return;
+    a.iter = it;
+    colpass_body<T, kTabLds>(a, blockIdx.x);
+}
+
 // Column half of the fused normal operator (see YPassArgs), 64 x 16 outputs
 // per block, one output per thread, all inputs in one batch of loads.
 constexpr int kYTX = 64, kYTY = 16, kYThreads = kYTX * kYTY;
 template <typename T>
-__global__ void __launch_bounds__(kYThreads) k_ypass(YPassArgs<T> a) {
+__device__ __forceinline__ void ypass_body(const YPassArgs<T>& a, int bx, int by, int gx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[17];
     const int tid = threadIdx.x, tx = tid & (kYTX - 1), ty = tid / kYTX;
     const int tyu = __builtin_amdgcn_readfirstlane(ty);
-    const int i0 = blockIdx.y * kYTY, j0 = blockIdx.x * kYTX;
+    const int i0 = by * kYTY, j0 = bx * kYTX;
     const int ny = a.ny, nx = a.nx, w = a.w;
     const int TH = kYTY + 2 * w;
     constexpr int PW = kYTX + 2;
@@ -924,7 +964,20 @@ __global__ void __launch_bounds__(kYThreads) k_ypass(YPassArgs<T> a) {
         dot = double(pc) * double(qv);
     }
     const double sm = block_sum(dot, red);
-    if (tid == 0) a.pq_part[blockIdx.y * gridDim.x + blockIdx.x] = sm;
+    if (tid == 0) a.pq_part[by * gx + bx] = sm;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kYThreads) k_ypass(YPassArgs<T> a) {
+    ypass_body(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kYThreads) k_ypass_b(const YPassArgs<T>* __restrict__ as) {
+    const YPassArgs<T> a = as[blockIdx.z];
+    const int gx = (a.nx + kYTX - 1) / kYTX, gy = (a.ny + kYTY - 1) / kYTY;
+    if (int(blockIdx.x) >= gx || int(blockIdx.y) >= gy || a.st->done) return;
+    ypass_body(a, blockIdx.x, blockIdx.y, gx);
 }
 
 // Diagonal / identity preconditioner iteration tail (no transform):
@@ -999,11 +1052,9 @@ __global__ void k_diag_update(int n, T* x, T* r, const T* p, const T* q, const T
 // Per-step setup
 // ------------------------------------------------------------------------
 template <typename T>
-__global__ void k_kappa(int ny, int nx, const T* __restrict__ u, double alpha, double beta, int variant,
-                        T* kap, double* kapd, T* s_apply, double* s_mu, double* Dd) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= nx) return;
+__device__ __forceinline__ void kappa_at(int i, int j, int ny, int nx, const T* __restrict__ u, double alpha,
+                                         double beta, int variant, T* kap, double* kapd, T* s_apply, double* s_mu,
+                                         double* Dd) {
     const double b2 = beta * beta;
     auto U = [&](int ii, int jj) { return double(u[size_t(ii) * nx + jj]); };
     auto K = [&](int ii, int jj) {
@@ -1029,11 +1080,27 @@ __global__ void k_kappa(int ny, int nx, const T* __restrict__ u, double alpha, d
     s_mu[g] = (variant == 4) ? s : 1.0;
 }
 
-__global__ void k_gemm_operands(int ny, int nx, const double* __restrict__ kap, const double* __restrict__ s,
-                                double* A1, double* A2, double* A3, double* B1, double* B2, double* B3) {
+template <typename T>
+__global__ void k_kappa(int ny, int nx, const T* __restrict__ u, double alpha, double beta, int variant,
+                        T* kap, double* kapd, T* s_apply, double* s_mu, double* Dd) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (j >= nx) return;
+    kappa_at(i, j, ny, nx, u, alpha, beta, variant, kap, kapd, s_apply, s_mu, Dd);
+}
+
+template <typename T>
+__global__ void k_kappa_b(const KappaArgs<T>* __restrict__ as) {
+    const KappaArgs<T> a = as[blockIdx.z];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (i >= a.ny || j >= a.nx) return;
+    kappa_at(i, j, a.ny, a.nx, a.u, a.alpha, a.beta, a.variant, a.kap, a.kapd, a.s_apply, a.s_mu, a.Dd);
+}
+
+__device__ __forceinline__ void operands_at(int i, int j, int ny, int nx, const double* __restrict__ kap,
+                                            const double* __restrict__ s, double* A1, double* A2, double* A3,
+                                            double* B1, double* B2, double* B3) {
     const size_t g = size_t(i) * nx + j;
     const double k = kap[g], sc = s[g];
     const double sd = (i < ny - 1) ? s[g + nx] : 0.0;
@@ -1044,6 +1111,22 @@ __global__ void k_gemm_operands(int ny, int nx, const double* __restrict__ kap, 
     B1[g] = k * sr * sr;
     B2[g] = k * sr * sc;
     B3[g] = (j < nx - 1) ? k * sc * sc : 0.0;
+}
+
+__global__ void k_gemm_operands(int ny, int nx, const double* __restrict__ kap, const double* __restrict__ s,
+                                double* A1, double* A2, double* A3, double* B1, double* B2, double* B3) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= nx) return;
+    operands_at(i, j, ny, nx, kap, s, A1, A2, A3, B1, B2, B3);
+}
+
+__global__ void k_operands_b(const OperandArgs* __restrict__ as) {
+    const OperandArgs a = as[blockIdx.z];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (i >= a.ny || j >= a.nx) return;
+    operands_at(i, j, a.ny, a.nx, a.kapd, a.s_mu, a.A1, a.A2, a.A3, a.B1, a.B2, a.B3);
 }
 
 // C = sum_t coef_t op(A_t) B_t, FP64, 64x64 tiles, 4x4 outputs per thread;
@@ -1140,6 +1223,43 @@ __global__ void k_mu(int n, const double* lamh2, const double* lamx, const doubl
 }
 
 template <typename T>
+__global__ void k_mu_b(const MuArgs<T>* __restrict__ as) {
+    const MuArgs<T> a = as[blockIdx.z];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    double h2 = a.lamh2[k];
+    if (a.use_lamd) h2 *= a.lamd[k] * a.lamd[k];
+    const double m = h2 + a.alpha * (a.lamx[k] + a.lamy[k]);
+    a.mu[k] = m;
+    a.muinv[k] = T(1.0 / m);
+}
+
+template <typename T>
+__global__ void k_fpchange_b(const FpArgs<T>* __restrict__ as) {
+    __shared__ double red[17];
+    const FpArgs<T> a = as[blockIdx.z];
+    if (int(blockIdx.x) >= a.nb) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += a.nb * blockDim.x) {
+        const double xv = a.x[k], d = xv - double(a.u[k]);
+        s1 += d * d;
+        s2 += xv * xv;
+    }
+    const double t1 = block_sum(s1, red);
+    const double t2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+        a.part[2 * blockIdx.x] = t1;
+        a.part[2 * blockIdx.x + 1] = t2;
+    }
+}
+
+template <typename T>
+__global__ void k_copy_b(const CopyArgs<T>* __restrict__ as) {
+    const CopyArgs<T> a = as[blockIdx.z];
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += gridDim.x * blockDim.x) a.dst[k] = a.src[k];
+}
+
+template <typename T>
 __global__ void k_fpchange(int n, const T* x, const T* u, double* part) {
     __shared__ double red[17];
     double a = 0.0, b = 0.0;
@@ -1176,6 +1296,43 @@ __global__ void k_finalize(PcgState* st, const double* rr_part, int n_rr, const 
     }
 }
 
+__device__ __forceinline__ void finalize_body(PcgState* st, const double* rr_part, int n_rr, const double* fp_part,
+                                              int n_fp, int max_iter) {
+    __shared__ double red[17];
+    const double rr = sum_partials(rr_part, n_rr, red);
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < n_fp; k += blockDim.x) {
+        a += fp_part[2 * k];
+        b += fp_part[2 * k + 1];
+    }
+    a = block_sum(a, red);
+    b = block_sum(b, red);
+    if (threadIdx.x == 0) {
+        if (st->done == 0) {
+            st->iters = max_iter;
+            st->relres = st->r0norm > 0.0 ? sqrt(rr) / st->r0norm : 0.0;
+        }
+        st->fp_change = sqrt(a) / fmax(sqrt(b), 1e-300);
+    }
+}
+
+__global__ void k_finalize_b(const FinArgs* __restrict__ as) {
+    const FinArgs a = as[blockIdx.x];
+    finalize_body(a.st, a.rr_part, a.n_rr, a.fp_part, a.n_fp, a.max_iter);
+}
+
+__global__ void k_init_b(const InitArgs* __restrict__ as) {
+    const InitArgs a = as[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    a.st->r0norm = 0.0;
+    a.st->tol = a.tol;
+    a.st->relres = 0.0;
+    a.st->fp_change = 0.0;
+    a.st->done = a.frozen ? 3 : 0;
+    a.st->iters = 0;
+    a.st->cap = a.cap;
+}
+
 __global__ void k_init_state(PcgState* st, double tol) {
     st->r0norm = 0.0;
     st->tol = tol;
@@ -1183,6 +1340,7 @@ __global__ void k_init_state(PcgState* st, double tol) {
     st->fp_change = 0.0;
     st->done = 0;
     st->iters = 0;
+    st->cap = 0;
 }
 
 // Adjoint step: vbar += H lambda; e = D_x lam o D_x u^{k+1} + D_y lam o
@@ -1440,7 +1598,101 @@ hipError_t launch_add_to_double(int n, const T* src, double* dst, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T>
+LineGeom line_geom_block(int lines, int n, int M, int threads) {
+    LineGeom g{};
+    g.units = (lines + 1) / 2;
+    // same threads-per-pair rule as line_geom, capped by the block size;
+    // the block then holds threads / tpu pairs so that every lane has a pair
+    int tpu = std::min(256, std::max(64, M / 8));
+    while (tpu < n && tpu < 1024) tpu *= 2;
+    tpu = std::min(tpu, threads);
+    if (tpu * kLinePos < n || threads % tpu != 0) return LineGeom{};
+    g.tpu = tpu;
+    g.upb = threads / tpu;
+    g.blocks = (g.units + g.upb - 1) / g.upb;
+    g.lds = size_t(2) * padded_len(M) * sizeof(cx<T>) * g.upb;
+    return g;
+}
+
+size_t ypass_lds_bytes(int w, size_t elem) {
+    return (size_t(kYTY + 2 * w) * kYTX + size_t(kYTY + 2) * (kYTX + 2)) * elem;
+}
+
+static void allow_lds(const void* k, size_t lds) {
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+}
+
+template <typename T>
+hipError_t launch_kappa_b(const KappaArgs<T>* a, BatchGrid g, hipStream_t s) {
+    hipLaunchKernelGGL(k_kappa_b<T>, dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_operands_b(const OperandArgs* a, BatchGrid g, hipStream_t s) {
+    hipLaunchKernelGGL(k_operands_b, dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_mu_b(const MuArgs<T>* a, BatchGrid g, hipStream_t s) {
+    hipLaunchKernelGGL(k_mu_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_fpchange_b(const FpArgs<T>* a, BatchGrid g, hipStream_t s) {
+    hipLaunchKernelGGL(k_fpchange_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_finalize_b(const FinArgs* a, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_b, dim3(count), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_init_b(const InitArgs* a, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_b, dim3(count), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_copy_b(const CopyArgs<T>* a, BatchGrid g, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename TX, typename TS, typename TA, typename TY>
+hipError_t launch_band_b(const BandArgsT<TX, TS, TA, TY>* a, BatchGrid g, hipStream_t s) {
+    allow_lds(reinterpret_cast<const void*>(&k_band_b<TX, TS, TA, TY>), g.lds);
+    hipLaunchKernelGGL((k_band_b<TX, TS, TA, TY>), dim3(g.gx, g.gy, g.count), dim3(kBandThreads), g.lds, s, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_rowpass_b(const RowPassArgs<T>* a, int it, bool tab_lds, BatchGrid g, hipStream_t s) {
+    auto k = tab_lds ? &k_rowpass_b<T, true> : &k_rowpass_b<T, false>;
+    allow_lds(reinterpret_cast<const void*>(k), g.lds);
+    hipLaunchKernelGGL(k, dim3(g.gx, 1, g.count), dim3(g.threads), g.lds, s, a, it);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_colpass_b(const ColPassArgs<T>* a, int it, bool tab_lds, BatchGrid g, hipStream_t s) {
+    auto k = tab_lds ? &k_colpass_b<T, true> : &k_colpass_b<T, false>;
+    allow_lds(reinterpret_cast<const void*>(k), g.lds);
+    hipLaunchKernelGGL(k, dim3(g.gx, 1, g.count), dim3(g.threads), g.lds, s, a, it);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
+    allow_lds(reinterpret_cast<const void*>(&k_ypass_b<T>), g.lds);
+    hipLaunchKernelGGL(k_ypass_b<T>, dim3(g.gx, g.gy, g.count), dim3(kYThreads), g.lds, s, a);
+    return hipGetLastError();
+}
+
 #define TVD_INSTANTIATE(T)                                                                                    \
+    template hipError_t launch_kappa_b<T>(const KappaArgs<T>*, BatchGrid, hipStream_t);                       \
+    template hipError_t launch_mu_b<T>(const MuArgs<T>*, BatchGrid, hipStream_t);                             \
+    template hipError_t launch_fpchange_b<T>(const FpArgs<T>*, BatchGrid, hipStream_t);                       \
+    template hipError_t launch_copy_b<T>(const CopyArgs<T>*, BatchGrid, hipStream_t);                         \
+    template hipError_t launch_band_b<T, T, double, T>(const BandArgsT<T, T, double, T>*, BatchGrid,          \
+                                                       hipStream_t);                                          \
+    template hipError_t launch_rowpass_b<T>(const RowPassArgs<T>*, int, bool, BatchGrid, hipStream_t);        \
+    template hipError_t launch_colpass_b<T>(const ColPassArgs<T>*, int, bool, BatchGrid, hipStream_t);        \
+    template hipError_t launch_ypass_b<T>(const YPassArgs<T>*, BatchGrid, hipStream_t);                       \
+    template LineGeom line_geom_block<T>(int, int, int, int);                                                 \
     template hipError_t launch_adj_accum<T>(int, int, const T*, const T*, const T*, const double*, double*,   \
                                             double*, double*, int*, hipStream_t);                             \
     template hipError_t launch_adj_ubar<T>(int, int, const double*, const T*, double, double*, hipStream_t);  \

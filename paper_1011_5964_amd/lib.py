@@ -29,8 +29,10 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_create", "tvdeblur_set_psf", "tvdeblur_set_bc", "tvdeblur_solve", "tvdeblur_destroy",
     "tvdeblur_last_error", "tvdeblur_op_blur", "tvdeblur_op_blur_adjoint", "tvdeblur_op_setup",
     "tvdeblur_op_normal", "tvdeblur_op_precond", "tvdeblur_op_export", "tvdeblur_set_profiling",
-    "tvdeblur_get_kernel_times", "tvdeblur_solve_adjoint",
+    "tvdeblur_get_kernel_times", "tvdeblur_solve_adjoint", "tvdeblur_batch_create", "tvdeblur_batch_solve",
+    "tvdeblur_batch_get_info", "tvdeblur_batch_destroy", "tvdeblur_batch_last_error",
 )
+BATCH_PRECOND = ("x", "d_x", "x_d")
 
 
 class TvdError(RuntimeError):
@@ -68,6 +70,29 @@ class KernelTimes(ctypes.Structure):
                 ("launches", ctypes.c_longlong * 8), ("total_ms", ctypes.c_double * 8)]
 
 
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int), ("nx", ctypes.c_int), ("psf_host", ctypes.POINTER(ctypes.c_double)),
+                ("py", ctypes.c_int), ("px", ctypes.c_int)]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [("alpha_host", ctypes.POINTER(ctypes.c_double)), ("beta_host", ctypes.POINTER(ctypes.c_double)),
+                ("beta", ctypes.c_double), ("max_outer", ctypes.c_int), ("fp_tol", ctypes.c_double),
+                ("inner_tol", ctypes.c_double), ("max_inner", ctypes.c_int), ("precond", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("replay_host", ctypes.POINTER(ctypes.c_int))]
+
+
+TUNE_MAX = 4
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("line_threads", ctypes.c_int), ("tables_in_lds", ctypes.c_int),
+                ("from_cache", ctypes.c_int), ("n_candidates", ctypes.c_int),
+                ("cand_threads", ctypes.c_int * TUNE_MAX), ("cand_us", ctypes.c_double * TUNE_MAX),
+                ("graph_launches", ctypes.c_longlong), ("time_setup_s", ctypes.c_double),
+                ("time_inner_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -96,13 +121,19 @@ def load():
         "tvdeblur_get_kernel_times": [vp, ctypes.POINTER(KernelTimes)],
         "tvdeblur_solve_adjoint": [vp, vp, i, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d),
                                    ctypes.POINTER(Params), ctypes.POINTER(Stats)],
+        "tvdeblur_batch_create": [ctypes.POINTER(vp), i, ctypes.POINTER(ImageDesc), i, i, vp],
+        "tvdeblur_batch_solve": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(BatchParams),
+                                 ctypes.POINTER(Stats)],
+        "tvdeblur_batch_get_info": [vp, ctypes.POINTER(BatchInfo)],
+        "tvdeblur_batch_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = i
-    lib.tvdeblur_last_error.argtypes = [vp]
-    lib.tvdeblur_last_error.restype = ctypes.c_char_p
+    for name in ("tvdeblur_last_error", "tvdeblur_batch_last_error"):
+        getattr(lib, name).argtypes = [vp]
+        getattr(lib, name).restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -249,3 +280,92 @@ class TVDeblur:
         with torch.cuda.device(self.device):
             self._check(self.lib.tvdeblur_op_export(self.h, EXPORT[which], _ptr(out)))
         return out
+
+
+class TVDeblurBatch:
+    """Batching form: independent images of different sizes, each with its
+    own PSF, alpha and beta, solved together (one launch per PCG stage for
+    the whole batch).  shapes: list of (ny, nx); psfs: list of 2D arrays."""
+
+    def __init__(self, shapes, psfs, bc, precision="f32_mixed", stream=None):
+        import torch
+        if len(shapes) != len(psfs) or not shapes:
+            raise ValueError("shapes and psfs must be non-empty lists of the same length")
+        self.lib = load()
+        self.shapes = [(int(a), int(b)) for a, b in shapes]
+        self.count = len(self.shapes)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.device = stream.device
+        self._psfs = [np.ascontiguousarray(h, dtype=np.float64) for h in psfs]
+        descs = (ImageDesc * self.count)()
+        for k, ((ny, nx), h) in enumerate(zip(self.shapes, self._psfs)):
+            descs[k] = ImageDesc(ny, nx, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), h.shape[0], h.shape[1])
+        b = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_batch_create(ctypes.byref(b), self.count, descs, PRECISION[precision], BC[bc],
+                                                ctypes.c_void_p(stream.cuda_stream))
+        if rc != TVD_OK:
+            raise TvdError(rc, self.lib.tvdeblur_batch_last_error(None).decode())
+        self.b = b
+
+    def _check(self, rc):
+        if rc != TVD_OK:
+            raise TvdError(rc, self.lib.tvdeblur_batch_last_error(self.b).decode())
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.tvdeblur_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, vs, alphas, beta=0.05, betas=None, max_outer=10, inner_tol=1e-6, max_inner=100,
+              precond="x_d", fp_tol=0.0, use_graph=True, outs=None, replay=None):
+        """Returns (list of restored images, list of per-image stats dicts).
+        replay: None, or per image a list of max_outer PCG iteration counts."""
+        import torch
+        if len(vs) != self.count or len(alphas) != self.count:
+            raise ValueError("one v and one alpha per image")
+        for k, v in enumerate(vs):
+            if v.dtype != self.dtype or tuple(v.shape) != self.shapes[k] or not v.is_contiguous() \
+                    or v.device != self.device:
+                raise ValueError(f"v[{k}] must be a contiguous {self.dtype} {self.shapes[k]} tensor on {self.device}")
+        us = outs if outs is not None else [torch.empty_like(v) for v in vs]
+        vp = (ctypes.c_void_p * self.count)(*[v.data_ptr() for v in vs])
+        up = (ctypes.c_void_p * self.count)(*[u.data_ptr() for u in us])
+        a = (ctypes.c_double * self.count)(*[float(x) for x in alphas])
+        p = BatchParams()
+        p.alpha_host = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+        bkeep = None
+        if betas is not None:
+            bkeep = (ctypes.c_double * self.count)(*[float(x) for x in betas])
+            p.beta_host = ctypes.cast(bkeep, ctypes.POINTER(ctypes.c_double))
+        p.beta, p.max_outer, p.fp_tol = float(beta), int(max_outer), float(fp_tol)
+        p.inner_tol, p.max_inner, p.precond = float(inner_tol), int(max_inner), PRECOND[precond]
+        p.use_graph = 1 if use_graph else 0
+        rkeep = None
+        if replay is not None:
+            flat = [int(c) for r in replay for c in (list(r) + [0] * max_outer)[:max_outer]]
+            rkeep = (ctypes.c_int * len(flat))(*flat)
+            p.replay_host = ctypes.cast(rkeep, ctypes.POINTER(ctypes.c_int))
+        st = (Stats * self.count)()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_batch_solve(self.b, vp, up, ctypes.byref(p), st)
+        self._check(rc)
+        return us, [s.to_dict() for s in st]
+
+    def info(self):
+        bi = BatchInfo()
+        self._check(self.lib.tvdeblur_batch_get_info(self.b, ctypes.byref(bi)))
+        n = bi.n_candidates
+        return {"count": bi.count, "line_threads": bi.line_threads, "tables_in_lds": bool(bi.tables_in_lds),
+                "from_cache": bool(bi.from_cache), "candidates": list(bi.cand_threads[:n]),
+                "candidate_us": list(bi.cand_us[:n]), "graph_launches": int(bi.graph_launches),
+                "time_setup_s": bi.time_setup_s, "time_inner_s": bi.time_inner_s}

@@ -3,6 +3,8 @@
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -28,11 +30,34 @@ def test_library_loads_and_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-@pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="library not built")
-def test_struct_layouts_match_header():
-    """Binding structs have the sizes implied by the header's field list."""
-    assert ctypes.sizeof(L.Params) == 8 * 2 + 8 + 8 * 2 + 8 + 8 * 3
-    assert ctypes.sizeof(L.Stats) == 4 + 4 * 256 + 4 + 8 * 256 * 2 + 4 + 4 + 8 + 8 * 3
+STRUCTS = {"tvd_params": L.Params, "tvd_stats": L.Stats, "tvd_kernel_times": L.KernelTimes,
+           "tvd_image_desc": L.ImageDesc, "tvd_batch_params": L.BatchParams, "tvd_batch_info": L.BatchInfo}
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="no C compiler")
+def test_struct_layouts_match_header(tmp_path):
+    """Every binding struct has the size and field offsets that a C compiler
+    gives the header's declaration."""
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "tvdeblur.h"', "int main(void) {"]
+    for cname, py in STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for cname, py in STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 @pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="library not built")
@@ -41,3 +66,29 @@ def test_null_handle_errors_without_gpu():
     assert lib.tvdeblur_set_bc(None, 2) == -1
     assert lib.tvdeblur_destroy(None) == 0
     assert lib.tvdeblur_last_error(None) is not None
+    assert lib.tvdeblur_batch_destroy(None) == 0
+    assert lib.tvdeblur_batch_get_info(None, None) == -1
+    assert lib.tvdeblur_batch_last_error(None) is not None
+
+
+@pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="library not built")
+def test_batch_create_argument_errors_without_gpu():
+    """Argument checks of batch creation run before any device call."""
+    lib = L.load()
+    out = ctypes.c_void_p()
+    assert lib.tvdeblur_batch_create(None, 1, None, 1, 2, None) == -1
+    assert lib.tvdeblur_batch_create(ctypes.byref(out), 0, None, 1, 2, None) == -1
+    import numpy as np
+    h = np.zeros((3, 3))
+    h[1, 1] = 1.0
+    d = (L.ImageDesc * 1)(L.ImageDesc(2, 8, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 3, 3))
+    assert lib.tvdeblur_batch_create(ctypes.byref(out), 1, d, 1, 2, None) == -4          # too small
+    d[0].ny = 8
+    assert lib.tvdeblur_batch_create(ctypes.byref(out), 1, d, 7, 2, None) == -1          # bad precision
+    assert lib.tvdeblur_batch_create(ctypes.byref(out), 1, d, 1, 9, None) == -1          # bad BC
+    hb = np.full((3, 3), 1.0 / 9)
+    hb[0, 0] += 1e-3
+    hb /= hb.sum()
+    d[0].psf_host = hb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.tvdeblur_batch_create(ctypes.byref(out), 1, d, 1, 2, None) == -2          # not symmetric
+    assert b"image 0" in lib.tvdeblur_batch_last_error(None)
