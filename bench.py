@@ -1,22 +1,31 @@
 #!/usr/bin/env python
 """Benchmark of the lagged-diffusivity TV deblurring hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms all|none] [--cpu-steps S]
 
-A step is one complete tvdeblur_solve of the 512 x 512 anti-reflective
-workload (64-shape phantom, 21 x 21 Gaussian PSF sigma 3, 1% noise,
-alpha 5e-4, beta 0.05, X_D preconditioner M_D, 15 fixed-point steps, PCG tol
-1e-6, at most 100 iterations), FP32-mixed precision, with v already resident
-in device memory.  Prints one JSON line: PCG iterations per second over K
-timed steps (restore time per step beside it), the roofline of the dominant
-kernel (durations from HIP events recorded by the library on its own stream
-during the timed steps), the relative error against the FP64 oracle, and the
-oracle timed on this host's CPU on a bounded sample of the same workload.
+Headline (one step = one complete tvdeblur_solve, input already in HBM): the
+512 x 512 anti-reflective workload (64-shape phantom, 21 x 21 Gaussian PSF
+sigma 3, 1% noise, alpha 5e-4, beta 0.05, X_D preconditioner, 15 fixed-point
+steps, PCG tol 1e-6, at most 100 iterations) in FP32-mixed precision.
+`value` = PCG iterations per second of whole solves over the K timed steps;
+the restore time per solve (median) and the inner-loop-only rate sit beside
+it.  During the K timed solves one launch in PROFILE_EVERY of each PCG-loop
+kernel carries a start/stop event pair on its own dispatch (no marker
+packets); the dominant kernel's roofline comes from those durations.
+
+Forms (default --forms all): the plain FP64 path on the same workload, the
+batching form on the 64-image ragged workload against 64 single-image solves,
+and the differentiation form (forward + adjoint against forward), each with
+its speedup over the plain GPU FP64 path and its error against the FP64
+oracle.  The oracle itself is timed on this host's cores on a bounded sample
+(cpu_baseline).
 """
 
 import argparse
+import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -25,17 +34,210 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor peak
 
-# Algorithmic HBM bytes per launch of each kernel class, per pixel, in units
-# of the element size w (what the kernel must read + write at minimum):
-#   band_normal  z, p_old, kappa read; p_new, q written         -> 5
-#   row_forward  x, p, q, r, s read; x, r, T1 written           -> 8
-#   column       T1, 1/mu read; T2 written                      -> 3
-#   row_inverse  T2, s, r read; z written                       -> 4
+# Algorithmic HBM words per pixel of each PCG-loop kernel (what that stage
+# of the method must read + write; w bytes per word):
+#   band_normal  p_old, z, kappa read; p_new, q written            -> 5
+#   row_forward  x, r, p, q, s read; x, r, T1 written              -> 8
+#   column       T1, 1/mu read; T2 written                         -> 3
+#   row_inverse  T2, s, r read; z written                          -> 4
 ALGO_WORDS = {"band_normal": 5, "row_forward": 8, "column": 3, "row_inverse": 4}
+# Per PCG iteration the method moves x, r, p (R/W), q, z (W/R), kappa, s,
+# 1/mu (R): 13 words per pixel, plus 4 for the two transform intermediates.
+ITER_WORDS = 13
+ITER_WORDS_WITH_TRANSPOSES = 17
+
+# HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters (scaled by the same counters on a plain copy kernel of known size)
+# for the kernels in the source whose SHA-256 prefix is recorded; ignored when
+# the kernel source has changed since.
+TRAFFIC = {"source_sha256": None, "bytes_per_launch": {}}
+
+# Kernel durations are sampled on 1 launch in PROFILE_EVERY of each class
+# during the timed solves (a timed launch delays the next by ~9 us).
+PROFILE_EVERY = 32
 
 WORKLOAD = ("512x512 piecewise-constant phantom (64 rectangles/disks, seed 512), 21x21 Gaussian PSF "
-            "sigma 3, 1% noise, anti-reflective BCs, M_D (X_D) DST-I preconditioner, alpha 5e-4, "
+            "sigma 3, 1% noise, anti-reflective BCs, X_D (M_D) DST-I preconditioner, alpha 5e-4, "
             "beta 0.05, 15 fixed-point steps, PCG tol 1e-6, max 100")
+
+
+def kernel_source_sha():
+    with open(os.path.join(ROOT, "paper_1011_5964_amd", "csrc", "tvd_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def rel2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def time_calls(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    times, out = [], None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return times, out
+
+
+def headline(args, p, prec):
+    """Times K solves of the metric workload; returns a dict of figures and
+    the last restored image (host, float64)."""
+    import torch
+    from paper_1011_5964_amd.lib import TVDeblur
+    n = p.v.shape[0]
+    dt = torch.float32 if prec == "f32_mixed" else torch.float64
+    v = torch.tensor(p.v, dtype=dt, device="cuda")
+    h = TVDeblur(n, n, prec)
+    h.set_psf(p.psf)
+    h.set_bc(p.bc)
+    stats = []
+
+    def solve():
+        u, st = h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        stats.append(st)
+        return u
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    stats.clear()
+    h.set_profiling(PROFILE_EVERY)
+    times, u = time_calls(solve, args.steps, 0)
+    kt = h.kernel_times()
+    h.set_profiling(False)
+    iters = sum(s["total_inner_iters"] for s in stats)
+    inner = sum(s["time_inner_s"] for s in stats)
+    total = sum(times)
+    w = 4 if prec == "f32_mixed" else 8
+    N = n * n
+    res = {"restore_time_s": statistics.median(times), "ms_per_step": 1e3 * total / args.steps,
+           "pcg_iters_per_s": iters / total, "pcg_iters_per_s_inner_loop": iters / inner,
+           "pcg_iters_per_solve": iters // args.steps, "iters_per_step": stats[-1]["inner_iters"],
+           "setup_share": sum(s["time_setup_s"] for s in stats) / total}
+    # whole-iteration roofline: the method's 13 words per pixel per iteration
+    per_iter_s = inner / iters
+    res["iteration_roofline"] = {
+        "bound": "hbm", "per_iteration_us": round(per_iter_s * 1e6, 3),
+        "algorithmic_bytes_per_iteration": ITER_WORDS * N * w,
+        "achieved": round(ITER_WORDS * N * w / per_iter_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(ITER_WORDS * N * w / per_iter_s / 1e9 / HBM_PEAK_GBS, 4),
+        "frac_with_transposes": round(ITER_WORDS_WITH_TRANSPOSES * N * w / per_iter_s / 1e9 / HBM_PEAK_GBS, 4)}
+    cls = {k: x for k, x in kt.items() if k in ALGO_WORDS and x["launches"] > 0}
+    dom = max(cls, key=lambda k: cls[k]["total_ms"])
+    avg_s = cls[dom]["total_ms"] * 1e-3 / cls[dom]["launches"]
+    algo = ALGO_WORDS[dom] * N * w
+    traffic = None
+    if TRAFFIC["source_sha256"] == kernel_source_sha() and prec == "f32_mixed":
+        traffic = TRAFFIC["bytes_per_launch"].get(dom)
+    res["roofline"] = {"bound": "hbm", "achieved": round(algo / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(algo / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
+                       "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 3), "launches": cls[dom]["launches"],
+                       "algorithmic_bytes_per_launch": algo}
+    res["kernel_classes"] = {k: {"launches": x["launches"], "avg_us": round(1e3 * x["total_ms"] / x["launches"], 3),
+                                 "share_of_step": round(x["total_ms"] / (1e3 * total), 4)}
+                             for k, x in kt.items() if x["launches"] > 0}
+    h.close()
+    return res, u.double().cpu().numpy()
+
+
+def batch_form(args, p_ref_f64_restore_s):
+    """64-image ragged batch (FP32-mixed, graph replay) against 64
+    single-image solves of the same images (FP32-mixed and FP64)."""
+    import torch
+    from paper_1011_5964_amd import synth
+    from paper_1011_5964_amd.lib import TVDeblur, TVDeblurBatch
+    probs = synth.config("c4")
+    px = sum(p.v.size for p in probs)
+    t0 = time.perf_counter()
+    b = TVDeblurBatch([p.v.shape for p in probs], [p.psf for p in probs], probs[0].bc, "f32_mixed")
+    create_s = time.perf_counter() - t0
+    vs = [torch.tensor(p.v, dtype=torch.float32, device="cuda") for p in probs]
+    alphas = [p.alpha for p in probs]
+    last = {}
+
+    def run():
+        us, st = b.solve(vs, alphas, beta=0.05, max_outer=probs[0].n_outer, inner_tol=1e-6, max_inner=100,
+                         precond="x_d", use_graph=True)
+        last["u"], last["st"] = us, st
+        return us
+
+    times, _ = time_calls(run, max(2, args.steps // 2), 1)
+    t_batch = statistics.median(times)
+    info = b.info()
+    res = {"workload": "64 images, sides U{128,192,256,384,512}, Gaussian PSF odd size 9..21 sigma U[1,4], "
+                       "alpha log-uniform [1e-4,1e-2], beta 0.05, AR, X_D, 10 fixed-point steps, FP32-mixed",
+           "pixels": px, "batch_solve_s": t_batch, "images_per_s": len(probs) / t_batch,
+           "megapixels_per_s": px / t_batch / 1e6, "create_s": create_s,
+           "all_converged": all(s["all_converged"] for s in last["st"]),
+           "pcg_iters_total": int(sum(s["total_inner_iters"] for s in last["st"])),
+           "tuning": {k: info[k] for k in ("line_threads", "tables_in_lds", "from_cache", "candidates",
+                                           "candidate_us")},
+           "setup_share": info["time_setup_s"] / t_batch}
+    # 64 single-image solves, one after another, both precisions
+    for prec, dt in (("f32_mixed", torch.float32), ("f64", torch.float64)):
+        hs = []
+        for p in probs:
+            h = TVDeblur(*p.v.shape, prec)
+            h.set_psf(p.psf)
+            h.set_bc(p.bc)
+            hs.append((h, torch.tensor(p.v, dtype=dt, device="cuda"), p))
+
+        def seq():
+            for h, v, p in hs:
+                h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+
+        st, _ = time_calls(seq, 1, 1)
+        res[f"sequential_{prec}_s"] = st[0]
+        for h, _, _ in hs:
+            h.close()
+    res["speedup_vs_64_single_f32_mixed"] = res["sequential_f32_mixed_s"] / t_batch
+    res["speedup_vs_64_single_f64"] = res["sequential_f64_s"] / t_batch
+    b.close()
+    return res, probs, last
+
+
+def diff_form(args, f64_restore_s):
+    """Forward (with checkpoints) and forward + adjoint on the 512^2
+    differentiation workload, FP32-mixed."""
+    import torch
+    from paper_1011_5964_amd import synth
+    from paper_1011_5964_amd.autograd import tv_restore
+    from paper_1011_5964_amd.lib import TVDeblur
+    p = synth.config("c5")
+    n = p.v.shape[0]
+    h = TVDeblur(n, n, "f32_mixed")
+    h.set_psf(p.psf)
+    h.set_bc(p.bc)
+    ut = torch.tensor(p.u_true, dtype=torch.float32, device="cuda")
+    v0 = torch.tensor(p.v, dtype=torch.float32, device="cuda")
+
+    def fwd():
+        with torch.no_grad():
+            return tv_restore(v0, p.alpha, p.beta, handle=h, n_outer=p.n_outer)
+
+    def fwd_bwd():
+        v = v0.clone().requires_grad_(True)
+        a = torch.tensor(p.alpha, dtype=torch.float64, device="cuda", requires_grad=True)
+        u = tv_restore(v, a, p.beta, handle=h, n_outer=p.n_outer)
+        loss = ((u - ut) ** 2).sum()
+        loss.backward()
+        return v.grad, a.grad
+
+    tf, _ = time_calls(fwd, 3, 1)
+    tb, (gv, ga) = time_calls(fwd_bwd, 3, 1)
+    h.close()
+    return {"workload": "512x512, 21x21 Gaussian sigma 3, AR, alpha 5e-4, beta 0.05, 15 steps, FP32-mixed, "
+                        "loss ||u - u_true||^2, grads w.r.t. v and alpha",
+            "forward_s": statistics.median(tf), "forward_backward_s": statistics.median(tb),
+            "backward_over_forward": statistics.median(tb) / statistics.median(tf) - 1.0,
+            "grad_alpha": float(ga), "grad_v_norm": float(gv.double().norm()),
+            "speedup_fwd_bwd_vs_plain_f64_forward": f64_restore_s / statistics.median(tb)}
 
 
 def main():
@@ -43,20 +245,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="f32_mixed", choices=["f32_mixed", "f64"])
+    ap.add_argument("--forms", default="all", choices=["all", "none"])
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="fixed-point steps of the oracle CPU sample (0 = skip the oracle)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain elementwise copy (y = -x, float32) of this many MiB three times: "
+                         "the reference kernel that scales hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (requested --gpus {args.gpus}); the single-GPU "
-              "workload is the whole job here. Run with --gpus 1.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (requested --gpus {args.gpus}): this build has no multi-GPU "
+              "path; the single-GPU workload is the whole job. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
 
     from paper_1011_5964_amd import synth
-    from paper_1011_5964_amd.lib import TVDeblur
 
     if not torch.cuda.is_available():
         print("no HIP device visible", file=sys.stderr)
@@ -64,83 +268,95 @@ def main():
 
     p = synth.config("m512")
     n = p.v.shape[0]
-    dt = torch.float32 if args.precision == "f32_mixed" else torch.float64
-    v = torch.tensor(p.v, dtype=dt, device="cuda")
-    h = TVDeblur(n, n, args.precision)
-    h.set_psf(p.psf)
-    h.set_bc(p.bc)
-
-    def solve():
-        return h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
-
-    for _ in range(args.warmup):
-        solve()
-    torch.cuda.synchronize()
-    h.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = 0
-    u = None
-    for _ in range(args.steps):
-        u, st = solve()
-        iters += st["total_inner_iters"]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = h.kernel_times()
-    h.set_profiling(False)
-    elapsed = t1 - t0
-    value = iters / elapsed
-    ms_per_step = 1e3 * elapsed / args.steps
-
-    # roofline of the dominant kernel class
-    w = 4 if args.precision == "f32_mixed" else 8
-    N = n * n
-    cls = {k: v_ for k, v_ in kt.items() if k in ALGO_WORDS and v_["launches"] > 0}
-    dom = max(cls, key=lambda k: cls[k]["total_ms"])
-    avg_s = cls[dom]["total_ms"] * 1e-3 / cls[dom]["launches"]
-    algo_bytes = ALGO_WORDS[dom] * N * w
-    achieved = algo_bytes / avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-                "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_bytes_per_launch": algo_bytes}
-    kernel_classes = {k: {"launches": v_["launches"], "avg_us": round(1e3 * v_["total_ms"] / v_["launches"], 3),
-                          "share_of_step": round(v_["total_ms"] / (1e3 * elapsed), 4)}
-                      for k, v_ in kt.items() if v_["launches"] > 0}
-
+    print(f"[bench] headline f32_mixed {n}x{n}: {args.warmup} warm-up + {args.steps} timed solves",
+          file=sys.stderr, flush=True)
+    r32, u32 = headline(args, p, "f32_mixed")
     out = {"metric": "512² AR-BC TV restore time (s) & PCG iters/s at ≤1e-5 rel err vs FP64 oracle",
-           "value": round(value, 1), "unit": "PCG iters/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-           "restore_time_s": round(ms_per_step / 1e3, 5), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32" if args.precision == "f32_mixed" else "f64",
-           "precision": args.precision, "data": "synthetic",
+           "value": round(r32["pcg_iters_per_s"], 1), "unit": "PCG iters/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 3),
+           "restore_time_s": round(r32["restore_time_s"], 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "precision": "f32_mixed (FP64 dots, scalars, stopping test)",
+           "data": "synthetic",
            "config": {"workload": WORKLOAD, "n": n, "psf": "gaussian 21x21 sigma 3", "bc": "antireflective",
-                      "precond": "x_d", "fixed_point_steps": p.n_outer, "pcg_iters_per_solve": iters // args.steps},
-           "roofline": roofline, "kernel_classes": kernel_classes}
+                      "precond": "x_d", "fixed_point_steps": p.n_outer,
+                      "pcg_iters_per_solve": r32["pcg_iters_per_solve"]},
+           "roofline": r32["roofline"], "iteration_roofline": r32["iteration_roofline"],
+           "pcg_iters_per_s_inner_loop": round(r32["pcg_iters_per_s_inner_loop"], 1),
+           "setup_share": round(r32["setup_share"], 4), "kernel_classes": r32["kernel_classes"]}
+
+    forms = {}
+    u64 = None
+    if args.forms == "all":
+        print("[bench] plain FP64 path", file=sys.stderr, flush=True)
+        r64, u64 = headline(args, p, "f64")
+        forms["plain_f64"] = {k: r64[k] for k in ("restore_time_s", "pcg_iters_per_s", "pcg_iters_per_s_inner_loop",
+                                                  "pcg_iters_per_solve", "setup_share")}
+        forms["plain_f64"]["iteration_roofline"] = r64["iteration_roofline"]
+        forms["f32_mixed"] = {"restore_time_s": r32["restore_time_s"],
+                              "speedup_vs_plain_f64": r64["restore_time_s"] / r32["restore_time_s"]}
+        print("[bench] batching form (64 ragged images)", file=sys.stderr, flush=True)
+        rb, probs, last = batch_form(args, r64["restore_time_s"])
+        forms["batch"] = rb
+        print("[bench] differentiation form", file=sys.stderr, flush=True)
+        forms["differentiation"] = diff_form(args, r64["restore_time_s"])
 
     if args.cpu_steps > 0:
+        import scipy.fft
         import threadpoolctl
 
         import oracle as O
-        vq = v.double().cpu().numpy()
+        cores = os.cpu_count() or 1
         k = min(args.cpu_steps, p.n_outer)
-        blas = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
-        c0 = time.perf_counter()
-        uo, so = O.fp_solve(vq, p.psf, p.bc, p.alpha, p.beta, k, p.inner_tol, p.max_inner, "x_d")
-        c1 = time.perf_counter()
+        print(f"[bench] oracle on {cores} host cores: {k} fixed-point steps", file=sys.stderr, flush=True)
+        with threadpoolctl.threadpool_limits(cores), scipy.fft.set_workers(cores):
+            c0 = time.perf_counter()
+            uo, so = O.fp_solve(p.v, p.psf, p.bc, p.alpha, p.beta, k, p.inner_tol, p.max_inner, "x_d")
+            c1 = time.perf_counter()
         o_iters = int(sum(so["inner_iters"]))
-        out["cpu_baseline"] = {"value": round(o_iters / (c1 - c0), 2), "unit": "PCG iters/s", "cores": blas,
+        k1 = min(2, k)
+        with threadpoolctl.threadpool_limits(1), scipy.fft.set_workers(1):
+            d0 = time.perf_counter()
+            _, s1 = O.fp_solve(p.v, p.psf, p.bc, p.alpha, p.beta, k1, p.inner_tol, p.max_inner, "x_d")
+            d1 = time.perf_counter()
+        out["cpu_baseline"] = {"value": round(o_iters / (c1 - c0), 2), "unit": "PCG iters/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": f"first {k} of {p.n_outer} fixed-point steps of the same 512x512 "
-                                         f"workload ({o_iters} PCG iterations, {c1 - c0:.1f} s; FFTs and "
-                                         f"convolutions single-threaded, matmuls on {blas} BLAS threads)"}
+                               "sample": f"first {k} of {p.n_outer} fixed-point steps of the same 512x512 workload "
+                                         f"({o_iters} PCG iterations in {c1 - c0:.1f} s, BLAS and scipy.fft on "
+                                         f"{cores} threads)",
+                               "one_core": {"value": round(sum(s1["inner_iters"]) / (d1 - d0), 2),
+                                            "sample": f"first {k1} fixed-point steps on 1 thread "
+                                                      f"({sum(s1['inner_iters'])} PCG iterations, "
+                                                      f"{d1 - d0:.1f} s)"}}
         if k == p.n_outer:
-            ug = u.double().cpu().numpy()
-        else:
-            ug = h.solve(v, p.alpha, p.beta, k, p.inner_tol, p.max_inner, "x_d")[0].double().cpu().numpy()
-        out["rel_err_vs_oracle"] = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
-        out["oracle_fp_steps_compared"] = k
-        out["gpu_iters_per_step"] = st["inner_iters"]
-        out["oracle_iters_per_step"] = so["inner_iters"]
+            out["rel_err_vs_oracle"] = rel2(u32, uo)
+            out["gpu_iters_per_step"] = r32["iters_per_step"]
+            out["oracle_iters_per_step"] = so["inner_iters"]
+            if u64 is not None:
+                forms["plain_f64"]["rel_err_vs_oracle"] = rel2(u64, uo)
+            forms.setdefault("f32_mixed", {})["rel_err_vs_oracle"] = out["rel_err_vs_oracle"]
+        if args.forms == "all":
+            # per-image error of the batch: one image of each of the three smallest sizes
+            errs = {}
+            for i, q in enumerate(probs):
+                s = q.v.shape[0]
+                if s in (128, 192, 256) and str(s) not in errs:
+                    vq = q.v.astype(np.float32).astype(np.float64)
+                    with threadpoolctl.threadpool_limits(cores), scipy.fft.set_workers(cores):
+                        uq, _ = O.fp_solve(vq, q.psf, q.bc, q.alpha, q.beta, q.n_outer, q.inner_tol,
+                                           q.max_inner, "x_d")
+                    errs[str(s)] = {"image": i, "rel_err_vs_oracle": rel2(last["u"][i].double().cpu().numpy(), uq)}
+            forms["batch"]["sampled_rel_err_vs_oracle"] = errs
+    if forms:
+        out["forms"] = forms
+    if args.copy_calibration > 0:
+        x = torch.ones(args.copy_calibration * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"kernel": "torch.neg float32", "bytes_read": x.numel() * 4,
+                                   "bytes_written": y.numel() * 4, "launches": 3}
+    out["kernel_source_sha256"] = kernel_source_sha()
     print(json.dumps(out), flush=True)
 
 

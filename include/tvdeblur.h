@@ -192,16 +192,19 @@ int tvdeblur_op_export(tvdeblur_t h, int which, void* dst_dev);
 typedef struct {
     int    n_kinds;                         /* entries filled */
     char   name[TVD_KTIME_KINDS][24];       /* kernel class */
-    long long launches[TVD_KTIME_KINDS];    /* launches timed */
+    long long launches[TVD_KTIME_KINDS];    /* launches timed (the sampled ones) */
     double total_ms[TVD_KTIME_KINDS];       /* summed event-to-event time */
 } tvd_kernel_times;
 
-/* enable != 0: from now on every kernel launch of tvdeblur_solve is
- * bracketed by a pair of HIP events on the handle's stream and its duration
- * accumulated per kernel class (band operator, forward row transform, column
- * transform, inverse row transform, residual, setup, other); the counters
- * are reset.  enable == 0 stops recording.  Costs one event pair per launch. */
-int tvdeblur_set_profiling(tvdeblur_t h, int enable);
+/* every >= 1: from now on every every-th launch of each kernel class of
+ * tvdeblur_solve is timed and its duration accumulated per class (band
+ * operator, forward row transform, column transform, inverse row transform,
+ * residual, setup, other); the counters are reset.  A single-kernel class is
+ * timed by a start/stop event pair carried on that kernel's own dispatch
+ * (its execution time); the residual and setup classes, which span several
+ * kernels, by marker events around them.  A timed launch delays the next
+ * one by several microseconds, hence the sampling.  every == 0 stops. */
+int tvdeblur_set_profiling(tvdeblur_t h, int every);
 
 /* Copy the accumulated per-class counts and times into *out (host). */
 int tvdeblur_get_kernel_times(tvdeblur_t h, tvd_kernel_times* out);

@@ -82,7 +82,7 @@ class SolverBase {
     virtual void op_normal(const void* x, void* y) = 0;
     virtual void op_precond(const void* r, void* z) = 0;
     virtual void op_export(int which, void* dst) = 0;
-    virtual void set_profiling(bool on) = 0;
+    virtual void set_profiling(int every) = 0;
     virtual void get_times(tvd_kernel_times* out) = 0;
 };
 
@@ -93,28 +93,41 @@ class KernelTimer {
     ~KernelTimer() {
         for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
     }
-    void enable(bool on) {
-        on_ = on;
+    // every > 0: time every every-th launch of each kernel class; 0: off.
+    void enable(int every) {
+        on_ = every > 0;
+        every_ = every > 0 ? every : 1;
         for (int k = 0; k < kKinds; ++k) {
             count_[k] = 0;
             ms_[k] = 0.0;
+            seen_[k] = 0;
         }
         pending_.clear();
         used_ = 0;
     }
     bool on() const { return on_; }
-    // returns the event to record before a launch (nullptr when off)
-    void begin(Kind k, hipStream_t s) {
-        if (!on_) return;
+    // Bracket the launches of one kernel class.  single: exactly one kernel
+    // follows, timed by events attached to its dispatch; otherwise marker
+    // events are recorded around the launches.
+    void begin(Kind k, hipStream_t s, bool single = true) {
+        active_ = on_ && (seen_[k]++ % every_ == 0);
+        if (!active_) return;
         cur_ = k;
+        single_ = single;
         e0_ = get();
-        (void)hipEventRecord(e0_, s);
+        e1_ = get();
+        if (single) arm_kernel_events(e0_, e1_);
+        else (void)hipEventRecord(e0_, s);
     }
     void end(hipStream_t s) {
-        if (!on_) return;
-        hipEvent_t e1 = get();
-        (void)hipEventRecord(e1, s);
-        pending_.push_back({cur_, e0_, e1});
+        if (!active_) return;
+        active_ = false;
+        if (single_) {
+            if (disarm_kernel_events()) pending_.push_back({cur_, e0_, e1_});
+        } else {
+            (void)hipEventRecord(e1_, s);
+            pending_.push_back({cur_, e0_, e1_});
+        }
     }
     // after a stream synchronisation: harvest all pending pairs
     void harvest() {
@@ -153,9 +166,12 @@ class KernelTimer {
         }
         return pool_[used_++];
     }
-    bool on_ = false;
+    bool on_ = false, active_ = false;
+    int every_ = 1;
+    long long seen_[kKinds] = {};
+    bool single_ = true;
     int cur_ = 0;
-    hipEvent_t e0_{};
+    hipEvent_t e0_{}, e1_{};
     std::vector<hipEvent_t> pool_;
     size_t used_ = 0;
     std::vector<Pair> pending_;
@@ -465,7 +481,7 @@ class Solver final : public SolverBase {
     // diffusivity and accumulation; r rounded to the working precision),
     // with ||r||^2 partials.  One per fixed-point step.
     void residual_hp(const T* x, T* r, double* rr_out) {
-        timer_.begin(KernelTimer::kResidual, s_);
+        timer_.begin(KernelTimer::kResidual, s_, false);
         residual_hp_launch(x, r, rr_out);
         timer_.end(s_);
     }
@@ -626,7 +642,7 @@ class Solver final : public SolverBase {
 
     // Per-step setup from u^k: kappa, D, s, mu.
     void setup(const T* uk, double alpha, double beta, int variant) {
-        timer_.begin(KernelTimer::kSetup, s_);
+        timer_.begin(KernelTimer::kSetup, s_, false);
         setup_launch(uk, alpha, beta, variant);
         timer_.end(s_);
     }
@@ -979,7 +995,7 @@ class Solver final : public SolverBase {
         TVD_HIP(hipStreamSynchronize(s_));
     }
 
-    void set_profiling(bool on) override { timer_.enable(on); }
+    void set_profiling(int every) override { timer_.enable(every); }
     void get_times(tvd_kernel_times* out) override { timer_.fill(out); }
 
    private:
@@ -1975,10 +1991,11 @@ int tvdeblur_op_precond(tvdeblur_t h, const void* r_dev, void* z_dev) {
     });
 }
 
-int tvdeblur_set_profiling(tvdeblur_t h, int enable) {
+int tvdeblur_set_profiling(tvdeblur_t h, int every) {
     if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (every < 0) return fail(h, TVD_EINVAL, "every must be >= 0");
     return guarded(h, [&]() {
-        h->solver->set_profiling(enable != 0);
+        h->solver->set_profiling(every);
         return TVD_OK;
     });
 }

@@ -262,6 +262,11 @@ template <typename T>
 LineGeom line_geom_block(int lines, int n, int M, int threads);
 size_t ypass_lds_bytes(int w, size_t elem);
 
+// Arm a start/stop event pair for the next kernel launch of this thread;
+// disarm returns whether a launch consumed them.
+void arm_kernel_events(hipEvent_t start, hipEvent_t stop);
+bool disarm_kernel_events();
+
 // ---- kernel launchers (tvd_kernels.hip) ----
 // Launch with tile height ty (8 or 16); band_lds_bytes gives the dynamic
 // LDS the launch needs, band_blocks the grid size (= number of partials).

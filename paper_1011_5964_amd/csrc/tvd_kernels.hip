@@ -10,11 +10,45 @@
 // fixed order (deterministic, no atomics); the CG scalars never leave the GPU.
 #include "tvd_internal.hpp"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 namespace tvd {
+
+// Kernel timing: when a pair of events is armed, the next launch carries
+// them on its own dispatch (start and end of that kernel's execution), so
+// the measured time has no marker packets around it.
+namespace {
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+thread_local bool t_ev_used = false;
+
+template <typename F, typename... Args>
+void tvd_launch(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+    if (t_ev_start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, std::uint32_t(lds), s, t_ev_start, t_ev_stop, 0u, args...);
+        t_ev_start = t_ev_stop = nullptr;
+        t_ev_used = true;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    }
+}
+}  // namespace
+
+void arm_kernel_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+    t_ev_used = false;
+}
+
+bool disarm_kernel_events() {
+    const bool used = t_ev_used;
+    t_ev_start = t_ev_stop = nullptr;
+    t_ev_used = false;
+    return used;
+}
+
 
 namespace {
 
@@ -1438,7 +1472,7 @@ hipError_t launch_band(const BandArgsT<TX, TS, T, TY>& a0, int ty, hipStream_t s
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band<TX, TS, T, TY>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    hipLaunchKernelGGL((k_band<TX, TS, T, TY>), grid, dim3(kBandThreads), lds, s, a);
+    tvd_launch((k_band<TX, TS, T, TY>), grid, dim3(kBandThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1472,7 +1506,7 @@ hipError_t launch_rowpass(const RowPassArgs<T>& a, hipStream_t s) {
     if (a.g.lds > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(a.g.lds));
-    hipLaunchKernelGGL(k, dim3(a.g.blocks), dim3(a.g.upb * a.g.tpu), a.g.lds, s, a);
+    tvd_launch(k, dim3(a.g.blocks), dim3(a.g.upb * a.g.tpu), a.g.lds, s, a);
     return hipGetLastError();
 }
 
@@ -1482,7 +1516,7 @@ hipError_t launch_colpass(const ColPassArgs<T>& a, hipStream_t s) {
     if (a.g.lds > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(a.g.lds));
-    hipLaunchKernelGGL(k, dim3(a.g.blocks), dim3(a.g.upb * a.g.tpu), a.g.lds, s, a);
+    tvd_launch(k, dim3(a.g.blocks), dim3(a.g.upb * a.g.tpu), a.g.lds, s, a);
     return hipGetLastError();
 }
 
@@ -1494,7 +1528,7 @@ hipError_t launch_ypass(const YPassArgs<T>& a, hipStream_t s, int* nblocks) {
     const size_t lds = (size_t(kYTY + 2 * a.w) * kYTX + size_t(kYTY + 2) * (kYTX + 2)) * sizeof(T);
     dim3 grid((a.nx + kYTX - 1) / kYTX, (a.ny + kYTY - 1) / kYTY);
     if (nblocks) *nblocks = grid.x * grid.y;
-    hipLaunchKernelGGL(k_ypass<T>, grid, dim3(kYThreads), lds, s, a);
+    tvd_launch(k_ypass<T>, grid, dim3(kYThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1509,7 +1543,7 @@ hipError_t launch_diag_update(int n, T* x, T* r, const T* p, const T* q, const T
                               int check, const double* rr_in, int n_rr_in, int* nblocks, hipStream_t s) {
     const int nb = elem_blocks(n, 256, 1024);
     if (nblocks) *nblocks = nb;
-    hipLaunchKernelGGL(k_diag_update<T>, dim3(nb), dim3(256), 0, s, n, x, r, p, q, dinv, z, pq_part, n_pq,
+    tvd_launch(k_diag_update<T>, dim3(nb), dim3(256), 0, s, n, x, r, p, q, dinv, z, pq_part, n_pq,
                        rz_part, n_rz, rr_out, rz_out, st, iter, do_update, check, rr_in, n_rr_in);
     return hipGetLastError();
 }
@@ -1518,7 +1552,7 @@ template <typename T>
 hipError_t launch_kappa(int ny, int nx, const T* u, double alpha, double beta, int variant, T* kap,
                         double* kapd, T* s_apply, double* s_mu, double* Dd, hipStream_t s) {
     dim3 grid((nx + 255) / 256, ny);
-    hipLaunchKernelGGL(k_kappa<T>, grid, dim3(256), 0, s, ny, nx, u, alpha, beta, variant, kap, kapd, s_apply,
+    tvd_launch(k_kappa<T>, grid, dim3(256), 0, s, ny, nx, u, alpha, beta, variant, kap, kapd, s_apply,
                        s_mu, Dd);
     return hipGetLastError();
 }
@@ -1526,20 +1560,20 @@ hipError_t launch_kappa(int ny, int nx, const T* u, double alpha, double beta, i
 hipError_t launch_gemm_operands(int ny, int nx, const double* kapd, const double* s_mu, double* A1,
                                 double* A2, double* A3, double* B1, double* B2, double* B3, hipStream_t s) {
     dim3 grid((nx + 255) / 256, ny);
-    hipLaunchKernelGGL(k_gemm_operands, grid, dim3(256), 0, s, ny, nx, kapd, s_mu, A1, A2, A3, B1, B2, B3);
+    tvd_launch(k_gemm_operands, grid, dim3(256), 0, s, ny, nx, kapd, s_mu, A1, A2, A3, B1, B2, B3);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmProblem* probs_dev, int nprob, int maxM, int maxN, hipStream_t s) {
     dim3 grid((maxN + kGT - 1) / kGT, (maxM + kGT - 1) / kGT, nprob);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, probs_dev);
+    tvd_launch(k_gemm, grid, dim3(256), 0, s, probs_dev);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_mu(int n, const double* lamh2, const double* lamx, const double* lamy, const double* lamd,
                      int use_lamd, double alpha, double* mu, T* muinv, hipStream_t s) {
-    hipLaunchKernelGGL(k_mu<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, lamh2, lamx, lamy, lamd, use_lamd,
+    tvd_launch(k_mu<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, lamh2, lamx, lamy, lamd, use_lamd,
                        alpha, mu, muinv);
     return hipGetLastError();
 }
@@ -1548,25 +1582,25 @@ template <typename T>
 hipError_t launch_fpchange(int n, const T* x, const T* u, double* part, int* nblocks, hipStream_t s) {
     const int nb = elem_blocks(n, 256, 512);
     *nblocks = nb;
-    hipLaunchKernelGGL(k_fpchange<T>, dim3(nb), dim3(256), 0, s, n, x, u, part);
+    tvd_launch(k_fpchange<T>, dim3(nb), dim3(256), 0, s, n, x, u, part);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_finalize(PcgState* st, const double* rr_part, int n_rr, const double* fp_part, int n_fp,
                            int max_iter, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, st, rr_part, n_rr, fp_part, n_fp, max_iter);
+    tvd_launch(k_finalize, dim3(1), dim3(256), 0, s, st, rr_part, n_rr, fp_part, n_fp, max_iter);
     return hipGetLastError();
 }
 
 hipError_t launch_init_state(PcgState* st, double tol, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, tol);
+    tvd_launch(k_init_state, dim3(1), dim3(1), 0, s, st, tol);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cast_to_double(int n, const T* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_cast_double<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, src, dst);
+    tvd_launch(k_cast_double<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, src, dst);
     return hipGetLastError();
 }
 
@@ -1575,26 +1609,26 @@ hipError_t launch_adj_accum(int ny, int nx, const T* lam, const T* hlam, const T
                             double* vbar, double* g, double* part, int* nblocks, hipStream_t s) {
     const int nb = elem_blocks(ny * nx, 256, 1024);
     *nblocks = nb;
-    hipLaunchKernelGGL(k_adj_accum<T>, dim3(nb), dim3(256), 0, s, ny, nx, lam, hlam, uk1, kapd, vbar, g, part);
+    tvd_launch(k_adj_accum<T>, dim3(nb), dim3(256), 0, s, ny, nx, lam, hlam, uk1, kapd, vbar, g, part);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_adj_ubar(int ny, int nx, const double* g, const T* uk, double alpha, double* ubar, hipStream_t s) {
     const int nb = elem_blocks(ny * nx, 256, 2048);
-    hipLaunchKernelGGL(k_adj_ubar<T>, dim3(nb), dim3(256), 0, s, ny, nx, g, uk, alpha, ubar);
+    tvd_launch(k_adj_ubar<T>, dim3(nb), dim3(256), 0, s, ny, nx, g, uk, alpha, ubar);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cast_from_double(int n, const double* src, T* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_cast_from_double<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, src, dst);
+    tvd_launch(k_cast_from_double<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, src, dst);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_add_to_double(int n, const T* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_add_to_double<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, src, dst);
+    tvd_launch(k_add_to_double<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, src, dst);
     return hipGetLastError();
 }
 
@@ -1625,60 +1659,60 @@ static void allow_lds(const void* k, size_t lds) {
 
 template <typename T>
 hipError_t launch_kappa_b(const KappaArgs<T>* a, BatchGrid g, hipStream_t s) {
-    hipLaunchKernelGGL(k_kappa_b<T>, dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a);
+    tvd_launch(k_kappa_b<T>, dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_operands_b(const OperandArgs* a, BatchGrid g, hipStream_t s) {
-    hipLaunchKernelGGL(k_operands_b, dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a);
+    tvd_launch(k_operands_b, dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_mu_b(const MuArgs<T>* a, BatchGrid g, hipStream_t s) {
-    hipLaunchKernelGGL(k_mu_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
+    tvd_launch(k_mu_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_fpchange_b(const FpArgs<T>* a, BatchGrid g, hipStream_t s) {
-    hipLaunchKernelGGL(k_fpchange_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
+    tvd_launch(k_fpchange_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_finalize_b(const FinArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_b, dim3(count), dim3(256), 0, s, a);
+    tvd_launch(k_finalize_b, dim3(count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_init_b(const InitArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_b, dim3(count), dim3(64), 0, s, a);
+    tvd_launch(k_init_b, dim3(count), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_copy_b(const CopyArgs<T>* a, BatchGrid g, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
+    tvd_launch(k_copy_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 template <typename TX, typename TS, typename TA, typename TY>
 hipError_t launch_band_b(const BandArgsT<TX, TS, TA, TY>* a, BatchGrid g, hipStream_t s) {
     allow_lds(reinterpret_cast<const void*>(&k_band_b<TX, TS, TA, TY>), g.lds);
-    hipLaunchKernelGGL((k_band_b<TX, TS, TA, TY>), dim3(g.gx, g.gy, g.count), dim3(kBandThreads), g.lds, s, a);
+    tvd_launch((k_band_b<TX, TS, TA, TY>), dim3(g.gx, g.gy, g.count), dim3(kBandThreads), g.lds, s, a);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_rowpass_b(const RowPassArgs<T>* a, int it, bool tab_lds, BatchGrid g, hipStream_t s) {
     auto k = tab_lds ? &k_rowpass_b<T, true> : &k_rowpass_b<T, false>;
     allow_lds(reinterpret_cast<const void*>(k), g.lds);
-    hipLaunchKernelGGL(k, dim3(g.gx, 1, g.count), dim3(g.threads), g.lds, s, a, it);
+    tvd_launch(k, dim3(g.gx, 1, g.count), dim3(g.threads), g.lds, s, a, it);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_colpass_b(const ColPassArgs<T>* a, int it, bool tab_lds, BatchGrid g, hipStream_t s) {
     auto k = tab_lds ? &k_colpass_b<T, true> : &k_colpass_b<T, false>;
     allow_lds(reinterpret_cast<const void*>(k), g.lds);
-    hipLaunchKernelGGL(k, dim3(g.gx, 1, g.count), dim3(g.threads), g.lds, s, a, it);
+    tvd_launch(k, dim3(g.gx, 1, g.count), dim3(g.threads), g.lds, s, a, it);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
     allow_lds(reinterpret_cast<const void*>(&k_ypass_b<T>), g.lds);
-    hipLaunchKernelGGL(k_ypass_b<T>, dim3(g.gx, g.gy, g.count), dim3(kYThreads), g.lds, s, a);
+    tvd_launch(k_ypass_b<T>, dim3(g.gx, g.gy, g.count), dim3(kYThreads), g.lds, s, a);
     return hipGetLastError();
 }
 

@@ -238,8 +238,10 @@ class TVDeblur:
         self._check(rc)
         return vbar, ab.value, bb.value, st.to_dict()
 
-    def set_profiling(self, enable):
-        self._check(self.lib.tvdeblur_set_profiling(self.h, 1 if enable else 0))
+    def set_profiling(self, every):
+        """every: time every every-th launch of each kernel class (True = 1);
+        0 / False stops."""
+        self._check(self.lib.tvdeblur_set_profiling(self.h, int(every)))
 
     def kernel_times(self):
         kt = KernelTimes()

@@ -221,3 +221,27 @@ def test_run_to_run_determinism():
     b, sb = gpu_solve(p, "f32_mixed")
     np.testing.assert_array_equal(a, b)
     assert sa["inner_iters"] == sb["inner_iters"]
+
+
+def test_kernel_timing_sampling():
+    """Per-class kernel timing: with every=1 each PCG-loop launch is timed
+    (at least one per PCG iteration); with every=4 exactly one in four of the
+    same, deterministic launch sequence; durations are positive."""
+    from paper_1011_5964_amd.lib import TVDeblur
+    p = synth.config("c1")
+    h = TVDeblur(64, 64, "f32_mixed")
+    h.set_psf(p.psf)
+    h.set_bc(p.bc)
+    v = dev(p.v, "f32_mixed")
+    runs = {}
+    for every in (1, 4):
+        h.set_profiling(every)
+        _, st = h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        runs[every] = (h.kernel_times(), st)
+    h.set_profiling(0)
+    k1, st = runs[1]
+    k4, _ = runs[4]
+    assert k1["band_normal"]["launches"] >= st["total_inner_iters"]
+    for cls in ("band_normal", "row_forward", "column", "row_inverse", "residual", "setup"):
+        assert k1[cls]["launches"] > 0 and k1[cls]["total_ms"] > 0, cls
+        assert k4[cls]["launches"] == -(-k1[cls]["launches"] // 4), cls
