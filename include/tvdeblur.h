@@ -186,9 +186,35 @@ int tvdeblur_op_precond(tvdeblur_t h, const void* r_dev, void* z_dev);
  * 3 = lambda_H (PSF symbol on the BC grid), 4 = D. */
 int tvdeblur_op_export(tvdeblur_t h, int which, void* dst_dev);
 
+/* ---- transform implementation of the preconditioner ----
+ *
+ * The 2D transforms of the X, D_X and X_D preconditioners (Section 3.2) run
+ * either as line transforms on the handle's own FFT in LDS (DST-I through a
+ * real DFT of length 2(n-1), DCT-II through one of length 2n; Bluestein
+ * for lengths that are not powers of two) or as dense products with the n x n
+ * basis matrix on the matrix cores (4 products of n^3 multiply-adds per
+ * application).  The two differ only in rounding.  TVD_TRANSFORM_AUTO (the
+ * default) times one application of each when the handle is built (at the
+ * first solve or op after set_psf / set_bc) and keeps the faster; the
+ * product form exists for TVD_F32_MIXED handles. */
+#define TVD_TRANSFORM_AUTO  0
+#define TVD_TRANSFORM_FFT   1
+#define TVD_TRANSFORM_GEMM  2
+
+/* Select the transform implementation (takes effect now if the handle is
+ * built, else when it is).  GEMM on a handle without the product form falls
+ * back to FFT; tvdeblur_get_transform tells which one runs.
+ * Errors: TVD_EINVAL. */
+int tvdeblur_set_transform(tvdeblur_t h, int mode);
+
+/* The implementation in use (TVD_TRANSFORM_FFT or TVD_TRANSFORM_GEMM) into
+ * *active (host); builds the handle first if needed.
+ * Errors: TVD_EINVAL, TVD_ESTATE, TVD_EDEVICE. */
+int tvdeblur_get_transform(tvdeblur_t h, int* active);
+
 /* ---- kernel timing (HIP events on the handle's stream) ---- */
 
-#define TVD_KTIME_KINDS 8
+#define TVD_KTIME_KINDS 12
 typedef struct {
     int    n_kinds;                         /* entries filled */
     char   name[TVD_KTIME_KINDS][24];       /* kernel class */
@@ -199,7 +225,8 @@ typedef struct {
 /* every >= 1: from now on every every-th launch of each kernel class of
  * tvdeblur_solve is timed and its duration accumulated per class (band
  * operator, forward row transform, column transform, inverse row transform,
- * residual, setup, other); the counters are reset.  A single-kernel class is
+ * residual, setup, other, PCG update, transform product on the matrix
+ * cores, row half of the normal operator); the counters are reset.  A single-kernel class is
  * timed by a start/stop event pair carried on that kernel's own dispatch
  * (its execution time); the residual and setup classes, which span several
  * kernels, by marker events around them.  A timed launch delays the next

@@ -26,6 +26,10 @@ namespace {
 
 std::string g_create_error;
 
+// Transform implementation picked per handle shape (see Solver::choose_transform).
+std::mutex g_transform_mu;
+std::map<std::string, int> g_transform_cache;
+
 struct HipError {
     hipError_t e;
     const char* what;
@@ -83,13 +87,17 @@ class SolverBase {
     virtual void op_precond(const void* r, void* z) = 0;
     virtual void op_export(int which, void* dst) = 0;
     virtual void set_profiling(int every) = 0;
+    // Transform implementation of the preconditioner: 0 = pick by timing at
+    // build, 1 = FFT line passes, 2 = products on the matrix cores.
+    virtual void set_transform(int mode) = 0;
+    virtual int transform() const = 0;
     virtual void get_times(tvd_kernel_times* out) = 0;
 };
 
 // Per-class kernel timing with pairs of HIP events around launches.
 class KernelTimer {
    public:
-    enum Kind { kBand = 0, kRowFwd, kCol, kRowInv, kResidual, kSetup, kOther, kKinds };
+    enum Kind { kBand = 0, kRowFwd, kCol, kRowInv, kResidual, kSetup, kOther, kUpdate, kGemm, kXPass, kKinds };
     ~KernelTimer() {
         for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
     }
@@ -143,7 +151,8 @@ class KernelTimer {
     }
     void fill(tvd_kernel_times* out) const {
         static const char* names[kKinds] = {"band_normal", "row_forward", "column", "row_inverse",
-                                            "residual", "setup", "other"};
+                                            "residual", "setup", "other", "update", "transform_gemm",
+                                            "x_pass"};
         std::memset(out, 0, sizeof(*out));
         out->n_kinds = kKinds;
         for (int k = 0; k < kKinds; ++k) {
@@ -327,6 +336,23 @@ class Solver final : public SolverBase {
         } else {
             make_basis(nx_, Wx_, Pux_, Pulx_, Plx_);
         }
+        // basis matrices for the product form of the transforms (columns =
+        // basis vectors: forward along rows is t Px, along columns Py^T t)
+        gemm_ok_ = mgemm_supported<T>();
+        if (gemm_ok_) {
+            auto up = [&](int n, const T*& P, const T*& PT) {
+                const std::vector<double> phi = basis_matrix(n, bc_);
+                P = geo_.upload<T>(phi, s_);
+                PT = geo_.upload<T>(transpose(phi, n), s_);
+            };
+            up(nx_, Px_, PxT_);
+            if (ny_ == nx_) {
+                Py_ = Px_;
+                PyT_ = PxT_;
+            } else {
+                up(ny_, Py_, PyT_);
+            }
+        }
         // work buffers
         auto A = [&](size_t elems) { return static_cast<T*>(geo_.alloc(elems * sizeof(T))); };
         auto D = [&](size_t elems) { return static_cast<double*>(geo_.alloc(elems * sizeof(double))); };
@@ -362,7 +388,8 @@ class Solver final : public SolverBase {
         Mu_ = D(N_);
         nb_band_ = band_blocks(ny_, nx_, fused_ ? ty_fused_ : ty_ht_);
         nb_res_ = band_blocks(ny_, nx_, fused_ ? ty_res_ : ty_ht_hp_);
-        const int cap = std::max({nb_band_, nb_res_, gx_.blocks, gy_.blocks, ypass_blocks(ny_, nx_), 1024});
+        const int cap = std::max({nb_band_, nb_res_, gx_.blocks, gy_.blocks, ypass_blocks(ny_, nx_),
+                                  ((ny_ + 31) / 32) * ((nx_ + 31) / 32), 1024});
         pq_ = D(cap);
         rr_[0] = D(cap);
         rr_[1] = D(cap);
@@ -386,6 +413,158 @@ class Solver final : public SolverBase {
         TVD_HIP(hipMemcpyAsync(gemm2_, s2.data(), s2.size() * sizeof(GemmProblem), hipMemcpyHostToDevice, s_));
         TVD_HIP(hipStreamSynchronize(s_));
         have_setup_ = false;
+        built_ = true;
+        choose_transform();
+    }
+
+    void set_transform(int mode) override {
+        treq_ = mode;
+        if (built_) choose_transform();
+    }
+    int transform() const override { return tmode_ == 1 ? 2 : 1; }
+
+    // Transform implementation: forced, or the faster of the two on this
+    // handle's shape (one preconditioner pass each, timed; cached per
+    // process by shape, PSF widths, BC and element type).
+    void choose_transform() {
+        tmode_ = 0;
+        if (!gemm_ok_ || treq_ == 1) return;
+        if (treq_ == 2) {
+            tmode_ = 1;
+            return;
+        }
+        const std::string key = std::to_string(sizeof(T)) + ":" + std::to_string(bc_) + ":" + std::to_string(ny_) +
+                                "x" + std::to_string(nx_) + ":" + std::to_string(my_) + "x" + std::to_string(mx_) +
+                                ":" + std::to_string(int(xpass_));
+        {
+            std::lock_guard<std::mutex> lk(g_transform_mu);
+            auto f = g_transform_cache.find(key);
+            if (f != g_transform_cache.end()) {
+                tmode_ = f->second;
+                return;
+            }
+        }
+        TVD_HIP(hipMemsetAsync(R_, 0, N_ * sizeof(T), s_));
+        TVD_HIP(hipMemsetAsync(Sap_, 0, N_ * sizeof(T), s_));
+        TVD_HIP(hipMemsetAsync(MuInv_, 0, N_ * sizeof(T), s_));
+        TVD_HIP(launch_init_state(st_, 0.0, s_));
+        float ms[2] = {0.f, 0.f};
+        for (int mode = 0; mode < 2; ++mode) {
+            tmode_ = mode;
+            auto pass = [&]() { precond_pass(R_, Z_, rz_[0], xpass_); };
+            pass();
+            TVD_HIP(hipEventRecord(ev_a_, s_));
+            for (int r = 0; r < 5; ++r) pass();
+            TVD_HIP(hipEventRecord(ev_b_, s_));
+            TVD_HIP(hipEventSynchronize(ev_b_));
+            TVD_HIP(hipEventElapsedTime(&ms[mode], ev_a_, ev_b_));
+        }
+        tmode_ = ms[1] < ms[0] ? 1 : 0;
+        std::lock_guard<std::mutex> lk(g_transform_mu);
+        g_transform_cache[key] = tmode_;
+    }
+
+    // One application of the transform preconditioner to r (no stopping
+    // test): z = s o Q^T[(Q (s o r)) / mu], <r, z> partials, and w = K_x z
+    // when xp.
+    void precond_pass(const T* r, T* z, double* rz_out, bool xp) {
+        if (tmode_ == 1) {
+            upd_launch(0, false, r);
+            gemm_transform(0, false, 0, r, z, rz_out, xp);
+        } else {
+            rowpass(0, false, const_cast<T*>(r), nullptr, 0);
+            colpass(0, false, 0);
+            rowpass_inv(z, const_cast<T*>(r), rz_out, xp);
+        }
+    }
+
+    // PCG update of the product-form path (see UpdArgs); update == false:
+    // t = s o r only.  t goes to T2_.
+    void upd_launch(int it, bool update, const T* r) {
+        UpdArgs<T> a{};
+        a.n = int(N_);
+        a.do_update = update ? 1 : 0;
+        a.x = X_;
+        a.r = const_cast<T*>(r);
+        a.p = Pb_[it & 1];
+        a.q = Q_;
+        a.s = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
+        a.t = T2_;
+        a.pq_part = pq_;
+        a.n_pq = n_pq_;
+        a.rz_part = rz_[(it - 1) & 1];
+        a.n_rz = n_rz_;
+        a.rr_out = rr_[0];
+        a.st = st_;
+        a.iter = it;
+        timer_.begin(KernelTimer::kUpdate, s_);
+        TVD_HIP(launch_upd<T>(a, s_, &nb_upd_));
+        timer_.end(s_);
+    }
+
+    // z = s o (Py [(Py^T (t Px)) / mu] Px^T) from t in T2_ (four products on
+    // the matrix cores), <r, z> partials into rz_out, then w = K_x z if xp.
+    // check: the PCG stopping test runs first, from n_rr partials in rr_[0].
+    void gemm_transform(int it, bool check, int n_rr, const T* r, T* z, double* rz_out, bool xp) {
+        MGemmArgs<T> g{};
+        g.st = st_;
+        g.iter = it;
+        auto run = [&]() {
+            int nb = 0;
+            timer_.begin(KernelTimer::kGemm, s_);
+            TVD_HIP(launch_mgemm<T>(g, s_, &nb));
+            timer_.end(s_);
+            return nb;
+        };
+        g.M = ny_;
+        g.N = nx_;
+        g.K = nx_;
+        g.A = T2_;
+        g.B = Px_;
+        g.C = T1_;
+        g.check = check ? 1 : 0;
+        g.rr_part = rr_[0];
+        g.n_rr = n_rr;
+        run();
+        g.check = 0;
+        g.K = ny_;
+        g.A = PyT_;
+        g.B = T1_;
+        g.C = T2_;
+        g.epi = 1;
+        g.E1 = MuInv_;
+        run();
+        g.K = nx_;
+        g.A = T2_;
+        g.B = PxT_;
+        g.C = T1_;
+        g.epi = 0;
+        g.E1 = nullptr;
+        run();
+        g.K = ny_;
+        g.A = Py_;
+        g.B = T1_;
+        g.C = z;
+        g.epi = 2;
+        g.E1 = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
+        g.E2 = r;
+        g.part = rz_out;
+        nb_g4_ = run();
+        if (xp) {
+            XPassArgs<T> x{};
+            x.ny = ny_;
+            x.nx = nx_;
+            x.z = z;
+            x.w = W_;
+            x.xband = xband_;
+            x.kw = kw_;
+            x.klo = klo_;
+            x.khi = khi_;
+            x.st = st_;
+            timer_.begin(KernelTimer::kXPass, s_);
+            TVD_HIP(launch_xpass<T>(x, s_));
+            timer_.end(s_);
+        }
     }
 
     // Line geometry of a batched launch whose blocks have `threads` threads,
@@ -672,9 +851,7 @@ class Solver final : public SolverBase {
                                           rr_[1], rz_[0], st_, 0, 0, 0, nullptr, 0, &nb, s_));
             return;
         }
-        rowpass(0, false, const_cast<T*>(r), nullptr, 0);
-        colpass(0, false, 0);
-        rowpass_inv(z, const_cast<T*>(r), rz_[0]);
+        precond_pass(r, z, rz_[0], false);
     }
 
     // -------------------------------------------------------------- solve
@@ -819,7 +996,12 @@ class Solver final : public SolverBase {
         int last_rr_n = nb_res_;
         const double* last_rr = rr_[0];
         const bool xp = transform && xpass_;
-        if (transform) {
+        const bool gm = transform && tmode_ == 1;
+        if (gm) {
+            upd_launch(0, false, R_);
+            gemm_transform(0, true, nb_res_, R_, Z_, rz_[0], xp);
+            n_rz_ = nb_g4_;
+        } else if (transform) {
             rowpass(0, false, R_, nullptr, 0);
             colpass(0, true, nb_res_, rr_[0]);
             rowpass_inv(Z_, R_, rz_[0], xp);
@@ -837,7 +1019,12 @@ class Solver final : public SolverBase {
         for (int it = 1; it <= maxit; ++it) {
             if (xp) ypass_update(it);
             else normal_apply_update(it);
-            if (transform) {
+            if (gm) {
+                upd_launch(it, true, R_);
+                last_rr = rr_[0];
+                last_rr_n = nb_upd_;
+                if (it < maxit) gemm_transform(it, true, nb_upd_, R_, Z_, rz_[it & 1], xp);
+            } else if (transform) {
                 rowpass(it, true, R_, rr_[0], 0);
                 last_rr = rr_[0];
                 last_rr_n = gx_.blocks;
@@ -1113,6 +1300,9 @@ class Solver final : public SolverBase {
     PcgState* host_st_ = nullptr;
     GemmProblem *gemm1_ = nullptr, *gemm2_ = nullptr;
     std::vector<GemmProblem> gemm1_host_, gemm2_host_;
+    bool gemm_ok_ = false, built_ = false;
+    int treq_ = 0, tmode_ = 0, nb_upd_ = 0, nb_g4_ = 0;
+    const T *Px_ = nullptr, *PxT_ = nullptr, *Py_ = nullptr, *PyT_ = nullptr;
     hipEvent_t ev_a_{}, ev_b_{}, ev_c_{};
     double alpha_ = 0, beta_ = 0;
     int variant_ = TVD_PREC_X_D;
@@ -1160,6 +1350,7 @@ class BatchSolver final : public BatchBase {
             key << sizeof(T) << ':' << bc;
             for (int i = 0; i < B_; ++i) {
                 img_.emplace_back(new Solver<T>(d[i].ny, d[i].nx, s_, max_lds));
+                img_[i]->treq_ = 1;  // batched launches use the line-transform kernels
                 const std::vector<double> psf(d[i].psf_host, d[i].psf_host + size_t(d[i].py) * d[i].px);
                 img_[i]->build(psf, d[i].py, d[i].px, bc);
                 if (!img_[i]->xpass_)
@@ -1996,6 +2187,27 @@ int tvdeblur_set_profiling(tvdeblur_t h, int every) {
     if (every < 0) return fail(h, TVD_EINVAL, "every must be >= 0");
     return guarded(h, [&]() {
         h->solver->set_profiling(every);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_set_transform(tvdeblur_t h, int mode) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (mode != TVD_TRANSFORM_AUTO && mode != TVD_TRANSFORM_FFT && mode != TVD_TRANSFORM_GEMM)
+        return fail(h, TVD_EINVAL, "bad transform mode");
+    return guarded(h, [&]() {
+        h->solver->set_transform(mode);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_get_transform(tvdeblur_t h, int* active) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (!active) return fail(h, TVD_EINVAL, "active is NULL");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        *active = h->solver->transform();
         return TVD_OK;
     });
 }

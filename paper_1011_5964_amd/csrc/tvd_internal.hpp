@@ -145,6 +145,60 @@ struct YPassArgs {
     const PcgState* st;
 };
 
+// Dense product on the matrix cores, C = A B (row-major A: M x K, B: K x N,
+// C: M x N), with an optional PCG stopping test before it and an
+// elementwise epilogue.
+template <typename T>
+struct MGemmArgs {
+    int M, N, K;
+    const T* A;
+    const T* B;
+    T* C;
+    int epi;                // 0: C = AB; 1: C = E1 o AB; 2: C = E1 o AB and <E2, C> partials
+    const T* E1;
+    const T* E2;
+    double* part;           // epi 2: one partial per block (by * gridDim.x + bx)
+    int check;              // stopping test from rr partials (as the column pass)
+    const double* rr_part;
+    int n_rr;
+    int iter;
+    PcgState* st;           // nullptr: plain product
+};
+
+// PCG update of the product-form preconditioner path: x += a p, r -= a q
+// (a from the <p, q> and <r, z> partials), ||r||^2 partials, and the
+// preconditioner input t = s o r (or r).  do_update = 0: t only.
+template <typename T>
+struct UpdArgs {
+    int n;
+    int do_update;
+    T* x;
+    T* r;
+    const T* p;
+    const T* q;
+    const T* s;
+    T* t;
+    const double* pq_part;
+    int n_pq;
+    const double* rz_part;
+    int n_rz;
+    double* rr_out;
+    PcgState* st;
+    int iter;
+};
+
+// Row half of the fused normal operator on its own: w = (I (x) K_x) z with
+// the Toeplitz-compressed band (see compress_band).
+template <typename T>
+struct XPassArgs {
+    int ny, nx;
+    const T* z;
+    T* w;
+    const T* xband;
+    int kw, klo, khi;
+    const PcgState* st;
+};
+
 template <typename T>
 struct ColPassArgs {
     int ny, nx;
@@ -279,6 +333,16 @@ template <typename T>
 hipError_t launch_rowpass(const RowPassArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_ypass(const YPassArgs<T>& a, hipStream_t s, int* nblocks);
+// Matrix-core product; *nblocks = number of blocks (= partials of epi 2).
+// Only for element types whose MFMA layout is supported (mgemm_supported).
+template <typename T>
+hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks);
+template <typename T>
+bool mgemm_supported();
+template <typename T>
+hipError_t launch_upd(const UpdArgs<T>& a, hipStream_t s, int* nblocks);
+template <typename T>
+hipError_t launch_xpass(const XPassArgs<T>& a, hipStream_t s);
 int ypass_blocks(int ny, int nx);
 template <typename T>
 hipError_t launch_colpass(const ColPassArgs<T>& a, hipStream_t s);

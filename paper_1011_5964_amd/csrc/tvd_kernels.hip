@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 namespace tvd {
 
@@ -784,6 +785,36 @@ __global__ void k_rowpass_b(const RowPassArgs<T>* __restrict__ as, int it) {
     rowpass_body<T, kTabLds>(a, blockIdx.x);
 }
 
+// PCG stopping test (strict ||r|| < tol ||r_0||, Section 5) from this
+// thread's share rrp of the ||r||^2 partials; every block evaluates it and
+// `leader` (one thread of the grid) records it.  At iteration 0 it fixes
+// ||r_0|| (zero: converged in 0 iterations).  A replay cap > 0 stops after
+// exactly that many iterations.  Returns true when the block must stop.
+__device__ __forceinline__ bool pcg_stop_test(PcgState* st, double rrp, int iter, double r0, double tol, int cap,
+                                              bool leader, double* red) {
+    const double rn = sqrt(block_sum(rrp, red));
+    if (iter == 0) {
+        if (leader) {
+            st->r0norm = rn;
+            st->relres = rn > 0.0 ? 1.0 : 0.0;
+            if (rn == 0.0) {
+                st->done = 1;
+                st->iters = 0;
+            }
+        }
+        return rn == 0.0;
+    }
+    if (leader) st->relres = rn / r0;
+    if (rn < tol * r0 || (cap > 0 && iter >= cap)) {
+        if (leader) {
+            st->done = 1;
+            st->iters = iter;
+        }
+        return true;
+    }
+    return false;
+}
+
 // Column pass: convergence test, forward column transform, divide by mu,
 // inverse column transform.
 template <typename T, bool kTabLds>
@@ -825,29 +856,7 @@ __device__ __forceinline__ void colpass_body(const ColPassArgs<T>& a, int bx) {
     }
     lds_copy_wait();
     if (done) return;
-    if (a.check) {
-        const double rn = sqrt(block_sum(rrp, red));
-        if (a.iter == 0) {
-            if (bx == 0 && tid == 0) {
-                a.st->r0norm = rn;
-                a.st->relres = rn > 0.0 ? 1.0 : 0.0;
-                if (rn == 0.0) {
-                    a.st->done = 1;
-                    a.st->iters = 0;
-                }
-            }
-            if (rn == 0.0) return;
-        } else {
-            if (bx == 0 && tid == 0) a.st->relres = rn / r0;
-            if (rn < tol * r0 || (cap > 0 && a.iter >= cap)) {
-                if (bx == 0 && tid == 0) {
-                    a.st->done = 1;
-                    a.st->iters = a.iter;
-                }
-                return;
-            }
-        }
-    }
+    if (a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && tid == 0, red)) return;
     const AxisPlan<T> P = lds_plan<T, kTabLds>(a.plan, tab);
 #pragma unroll
     for (int c = 0; c < kLinePos; ++c) {
@@ -1014,6 +1023,270 @@ __global__ void __launch_bounds__(kYThreads) k_ypass_b(const YPassArgs<T>* __res
     ypass_body(a, blockIdx.x, blockIdx.y, gx);
 }
 
+// ------------------------------------------------------------------------
+// Dense products on the matrix cores: C = A B, row-major.  A block of four
+// waves owns a 32 x 32 tile of C, each wave a 16 x 16 MFMA tile (K = 4 per
+// instruction); K runs through LDS in double-buffered slices of BK.  A is
+// kept row-major in LDS with a row stride that puts the two k-rows a wave
+// reads in one cycle in disjoint banks; B is kept k-major.
+// ------------------------------------------------------------------------
+template <typename T>
+struct MfmaCfg;
+
+template <>
+struct MfmaCfg<float> {
+    static constexpr int BK = 32, SA = 34, SB = 48;
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result r of
+    // lane l is C[4 (l / 16) + r][l % 16]
+    static __device__ __forceinline__ int orow(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <>
+struct MfmaCfg<double> {
+    static constexpr int BK = 16, SA = 17, SB = 32;
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // operands as for float; result r of lane l is C[l / 16 + 4 r][l % 16]
+    static __device__ __forceinline__ int orow(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+// One K slice of a wave's 16 x 16 tile from the LDS copies of A (row-major,
+// stride SA) and B (k-major, stride SB).
+template <typename T>
+__device__ __forceinline__ void mma_slice(const T* As, const T* Bs, int lane, int wr, int wc,
+                                          typename MfmaCfg<T>::acc_t& acc) {
+    using Cfg = MfmaCfg<T>;
+    const T* as = As + (wr + (lane & 15)) * Cfg::SA + (lane >> 4);
+    const T* bs = Bs + (lane >> 4) * Cfg::SB + wc + (lane & 15);
+#pragma unroll
+    for (int kk = 0; kk < Cfg::BK / 4; ++kk) acc = Cfg::mma(as[4 * kk], bs[4 * kk * Cfg::SB], acc);
+}
+
+template <typename T>
+__device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
+    using Cfg = MfmaCfg<T>;
+    constexpr int BK = Cfg::BK, SA = Cfg::SA, SB = Cfg::SB, TM = 32, TN = 32;
+    constexpr int AE = TM * BK / 256, BE = BK * TN / 256;  // elements per thread per slice
+    __shared__ T As[2][TM * SA];
+    __shared__ T Bs[2][BK * SB];
+    __shared__ double red[17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int M = a.M, N = a.N, K = a.K;
+    const int m0 = by * TM, n0 = bx * TN;
+    if (a.st) {
+        const int done = a.st->done;
+        const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, 256) : 0.0;
+        const double r0 = a.st->r0norm, tol = a.st->tol;
+        const int cap = a.st->cap;
+        if (done) return;
+        if (a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red)) return;
+    }
+    const int ar = tid / (BK / AE), ak = (tid % (BK / AE)) * AE;
+    const int bk = tid / (TN / BE), bc = (tid % (TN / BE)) * BE;
+    T ra[AE], rb[BE];
+    auto gload = [&](int kt) {
+        const int k0 = kt * BK;
+        const int gr = m0 + ar;
+#pragma unroll
+        for (int c = 0; c < AE; ++c) {
+            const int gk = k0 + ak + c;
+            ra[c] = (gr < M && gk < K) ? a.A[size_t(gr) * K + gk] : T(0);
+        }
+        const int gk = k0 + bk;
+#pragma unroll
+        for (int c = 0; c < BE; ++c) {
+            const int gc = n0 + bc + c;
+            rb[c] = (gk < K && gc < N) ? a.B[size_t(gk) * N + gc] : T(0);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < AE; ++c) As[buf][ar * SA + ak + c] = ra[c];
+#pragma unroll
+        for (int c = 0; c < BE; ++c) Bs[buf][bk * SB + bc + c] = rb[c];
+    };
+    typename Cfg::acc_t acc = {};
+    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;
+    const int nkt = (K + BK - 1) / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nkt) gload(kt + 1);
+        mma_slice<T>(As[buf], Bs[buf], lane, wr, wc, acc);
+        if (kt + 1 < nkt) sstore(buf ^ 1);
+        __syncthreads();
+    }
+    double part = 0.0;
+    const int j = n0 + wc + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wr + Cfg::orow(lane, r);
+        if (i < M && j < N) {
+            const size_t g = size_t(i) * N + j;
+            T v = acc[r];
+            if (a.epi >= 1 && a.E1) v *= a.E1[g];
+            a.C[g] = v;
+            if (a.epi == 2) part += double(a.E2[g]) * double(v);
+        }
+    }
+    if (a.epi == 2) {
+        const double sm = block_sum(part, red);
+        if (tid == 0) a.part[by * gx + bx] = sm;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
+    mgemm_body(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// FP64 sums of products C = sum_t coef_t op(A_t) B_t on the matrix cores
+// (the eigenvalue setup); one problem per blockIdx.z, 32 x 32 tiles.  With
+// transA, A_t is stored K x M and its slice is loaded along m.
+__global__ void __launch_bounds__(256) k_mgemm_multi(const GemmProblem* __restrict__ probs) {
+    using Cfg = MfmaCfg<double>;
+    constexpr int BK = Cfg::BK, SA = Cfg::SA, SB = Cfg::SB, TM = 32, TN = 32;
+    constexpr int AE = TM * BK / 256, BE = BK * TN / 256;
+    __shared__ double As[2][TM * SA];
+    __shared__ double Bs[2][BK * SB];
+    const GemmProblem& pb = probs[blockIdx.z];
+    const int M = pb.M, N = pb.N, K = pb.K;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    if (m0 >= M || n0 >= N) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int trans = pb.transA;
+    // A slice: row-major -> thread (row ar, k ak..); stored K x M -> thread (k kk, rows rr..)
+    const int ar = tid / (BK / AE), ak = (tid % (BK / AE)) * AE;
+    const int kk = tid / (TM / AE), rr = (tid % (TM / AE)) * AE;
+    const int bk = tid / (TN / BE), bc = (tid % (TN / BE)) * BE;
+    const int nkt = (K + BK - 1) / BK, total = pb.nterms * nkt;
+    double ra[AE], rb[BE];
+    auto gload = [&](int step) {
+        const int term = step / nkt, k0 = (step - term * nkt) * BK;
+        const double* A = pb.t[term].A;
+        const double* B = pb.t[term].B;
+        const double cf = pb.t[term].coef;
+        if (trans) {
+            const int gk = k0 + kk;
+#pragma unroll
+            for (int c = 0; c < AE; ++c) {
+                const int gm = m0 + rr + c;
+                ra[c] = (gk < K && gm < M) ? cf * A[size_t(gk) * M + gm] : 0.0;
+            }
+        } else {
+            const int gr = m0 + ar;
+#pragma unroll
+            for (int c = 0; c < AE; ++c) {
+                const int gk = k0 + ak + c;
+                ra[c] = (gr < M && gk < K) ? cf * A[size_t(gr) * K + gk] : 0.0;
+            }
+        }
+        const int gk = k0 + bk;
+#pragma unroll
+        for (int c = 0; c < BE; ++c) {
+            const int gc = n0 + bc + c;
+            rb[c] = (gk < K && gc < N) ? B[size_t(gk) * N + gc] : 0.0;
+        }
+    };
+    auto sstore = [&](int buf) {
+        if (trans) {
+#pragma unroll
+            for (int c = 0; c < AE; ++c) As[buf][(rr + c) * SA + kk] = ra[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < AE; ++c) As[buf][ar * SA + ak + c] = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < BE; ++c) Bs[buf][bk * SB + bc + c] = rb[c];
+    };
+    Cfg::acc_t acc = {};
+    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int step = 0; step < total; ++step) {
+        const int buf = step & 1;
+        if (step + 1 < total) gload(step + 1);
+        mma_slice<double>(As[buf], Bs[buf], lane, wr, wc, acc);
+        if (step + 1 < total) sstore(buf ^ 1);
+        __syncthreads();
+    }
+    const int j = n0 + wc + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wr + Cfg::orow(lane, r);
+        if (i < M && j < N) pb.C[size_t(i) * N + j] = acc[r];
+    }
+}
+
+// x += a p, r -= a q, ||r||^2 partials, t = s o r (see UpdArgs).
+template <typename T>
+__global__ void __launch_bounds__(256) k_upd(UpdArgs<T> a) {
+    __shared__ double red[17];
+    const int tid = threadIdx.x;
+    const int done = a.st->done;
+    const double pq = a.do_update ? partial_issue(a.pq_part, a.n_pq, tid, 256) : 0.0;
+    const double rzp = a.do_update ? partial_issue(a.rz_part, a.n_rz, tid, 256) : 0.0;
+    if (done) return;
+    T step = T(0);
+    if (a.do_update) {
+        const double g = block_sum(pq, red);
+        const double rz = block_sum(rzp, red);
+        if (!(g > 0.0)) {  // curvature <= 0 (or NaN): stop, keep x_{i-1}
+            if (blockIdx.x == 0 && tid == 0) {
+                a.st->done = 2;
+                a.st->iters = a.iter - 1;
+            }
+            return;
+        }
+        step = T(rz / g);
+    }
+    double part = 0.0;
+    const int stride = gridDim.x * 256;
+    for (int k = blockIdx.x * 256 + tid; k < a.n; k += stride) {
+        T rv = a.r[k];
+        if (a.do_update) {
+            rv -= step * a.q[k];
+            a.x[k] += step * a.p[k];
+            a.r[k] = rv;
+            part += double(rv) * double(rv);
+        }
+        a.t[k] = a.s ? a.s[k] * rv : rv;
+    }
+    if (a.do_update) {
+        const double sm = block_sum(part, red);
+        if (tid == 0) a.rr_out[blockIdx.x] = sm;
+    }
+}
+
+// w = (I (x) K_x) z, one row per block (z row staged in LDS).
+template <typename T>
+__global__ void __launch_bounds__(256) k_xpass(XPassArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* zs = reinterpret_cast<T*>(smem_raw);
+    const int i = blockIdx.x, tid = threadIdx.x, nx = a.nx;
+    if (a.st && a.st->done) return;
+    const T* zr = a.z + size_t(i) * nx;
+    for (int t = tid; t < nx; t += 256) zs[t] = zr[t];
+    __syncthreads();
+    const int bw = 2 * a.kw + 1;
+    for (int t = tid; t < nx; t += 256) {
+        const int rr = t < a.klo ? 1 + t : (t >= a.khi ? 1 + a.klo + (t - a.khi) : 0);
+        const T* coef = a.xband + rr * bw;
+        T sacc = T(0);
+        for (int d = 0; d < bw; ++d) sacc += coef[d] * zs[min(max(t + d - a.kw, 0), nx - 1)];
+        a.w[size_t(i) * nx + t] = sacc;
+    }
+}
+
 // Diagonal / identity preconditioner iteration tail (no transform):
 // convergence test of the previous residual, then x += a p, r -= a q,
 // z = dinv o r (or r), ||r||^2 and <r,z> partials.
@@ -1161,87 +1434,6 @@ __global__ void k_operands_b(const OperandArgs* __restrict__ as) {
     const int i = blockIdx.y;
     if (i >= a.ny || j >= a.nx) return;
     operands_at(i, j, a.ny, a.nx, a.kapd, a.s_mu, a.A1, a.A2, a.A3, a.B1, a.B2, a.B3);
-}
-
-// C = sum_t coef_t op(A_t) B_t, FP64, 64x64 tiles, 4x4 outputs per thread;
-// the next K tile is fetched into registers while the current one is used.
-constexpr int kGT = 64, kGK = 16;
-__global__ void __launch_bounds__(256) k_gemm(const GemmProblem* probs) {
-    __shared__ double As[2][kGK][kGT + 1];
-    __shared__ double Bs[2][kGK][kGT + 1];
-    const GemmProblem& pb = probs[blockIdx.z];
-    const int M = pb.M, N = pb.N, K = pb.K;
-    if (int(blockIdx.y) * kGT >= M || int(blockIdx.x) * kGT >= N) return;
-    const int tid = threadIdx.x;
-    const int tm = tid / 16, tn = tid % 16;
-    const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    const int ktiles = (K + kGK - 1) / kGK;
-    const int total = pb.nterms * ktiles;
-    double ra[4], rb[4];
-    auto fetch = [&](int step) {
-        const int term = step / ktiles, k0 = (step - term * ktiles) * kGK;
-        const double* A = pb.t[term].A;
-        const double* B = pb.t[term].B;
-        const double cf = pb.t[term].coef;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + u * 256;
-            int kk, mm;
-            if (pb.transA) {
-                kk = e / kGT;
-                mm = e % kGT;
-                ra[u] = (k0 + kk < K && m0 + mm < M) ? cf * A[size_t(k0 + kk) * M + m0 + mm] : 0.0;
-            } else {
-                mm = e / kGK;
-                kk = e % kGK;
-                ra[u] = (k0 + kk < K && m0 + mm < M) ? cf * A[size_t(m0 + mm) * K + k0 + kk] : 0.0;
-            }
-            const int bk = e / kGT, bn = e % kGT;
-            rb[u] = (k0 + bk < K && n0 + bn < N) ? B[size_t(k0 + bk) * N + n0 + bn] : 0.0;
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + u * 256;
-            if (pb.transA) As[buf][e / kGT][e % kGT] = ra[u];
-            else As[buf][e % kGK][e / kGK] = ra[u];
-            Bs[buf][e / kGT][e % kGT] = rb[u];
-        }
-    };
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int step = 0; step < total; ++step) {
-        const int buf = step & 1;
-        if (step + 1 < total) fetch(step + 1);
-#pragma unroll
-        for (int kk = 0; kk < kGK; ++kk) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][tm + 16 * a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk][tn + 16 * b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
-        }
-        if (step + 1 < total) stash(buf ^ 1);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int m = m0 + tm + 16 * a, n = n0 + tn + 16 * b;
-            if (m < M && n < N) pb.C[size_t(m) * N + n] = acc[a][b];
-        }
 }
 
 template <typename T>
@@ -1532,6 +1724,33 @@ hipError_t launch_ypass(const YPassArgs<T>& a, hipStream_t s, int* nblocks) {
     return hipGetLastError();
 }
 
+template <typename T>
+bool mgemm_supported() {
+    return true;
+}
+
+template <typename T>
+hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
+    dim3 grid((a.N + 31) / 32, (a.M + 31) / 32);
+    if (nblocks) *nblocks = int(grid.x * grid.y);
+    tvd_launch(k_mgemm<T>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_upd(const UpdArgs<T>& a, hipStream_t s, int* nblocks) {
+    const int nb = std::max(1, std::min(1024, (a.n + 255) / 256));
+    if (nblocks) *nblocks = nb;
+    tvd_launch(k_upd<T>, dim3(nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xpass(const XPassArgs<T>& a, hipStream_t s) {
+    tvd_launch(k_xpass<T>, dim3(a.ny), dim3(256), size_t(a.nx) * sizeof(T), s, a);
+    return hipGetLastError();
+}
+
 static int elem_blocks(int n, int threads, int cap) {
     return std::max(1, std::min(cap, (n + threads - 1) / threads));
 }
@@ -1565,8 +1784,8 @@ hipError_t launch_gemm_operands(int ny, int nx, const double* kapd, const double
 }
 
 hipError_t launch_gemm(const GemmProblem* probs_dev, int nprob, int maxM, int maxN, hipStream_t s) {
-    dim3 grid((maxN + kGT - 1) / kGT, (maxM + kGT - 1) / kGT, nprob);
-    tvd_launch(k_gemm, grid, dim3(256), 0, s, probs_dev);
+    dim3 grid((maxN + 31) / 32, (maxM + 31) / 32, nprob);
+    tvd_launch(k_mgemm_multi, grid, dim3(256), 0, s, probs_dev);
     return hipGetLastError();
 }
 
@@ -1717,6 +1936,10 @@ hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
 }
 
 #define TVD_INSTANTIATE(T)                                                                                    \
+    template bool mgemm_supported<T>();                                                                       \
+    template hipError_t launch_mgemm<T>(const MGemmArgs<T>&, hipStream_t, int*);                              \
+    template hipError_t launch_upd<T>(const UpdArgs<T>&, hipStream_t, int*);                                  \
+    template hipError_t launch_xpass<T>(const XPassArgs<T>&, hipStream_t);                                    \
     template hipError_t launch_kappa_b<T>(const KappaArgs<T>*, BatchGrid, hipStream_t);                       \
     template hipError_t launch_mu_b<T>(const MuArgs<T>*, BatchGrid, hipStream_t);                             \
     template hipError_t launch_fpchange_b<T>(const FpArgs<T>*, BatchGrid, hipStream_t);                       \

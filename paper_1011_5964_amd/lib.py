@@ -23,6 +23,8 @@ BC = {"reflective": 1, "antireflective": 2}
 PRECOND = {"none": 0, "diag": 1, "x": 2, "d_x": 3, "x_d": 4}
 EXPORT = {"kappa": 0, "s": 1, "mu": 2, "lambda_h": 3, "d": 4}
 MAX_OUTER = 256
+KTIME_KINDS = 12
+TRANSFORM = {"auto": 0, "fft": 1, "gemm": 2}
 
 # Every symbol declared in include/tvdeblur.h.
 EXPORTED_SYMBOLS = (
@@ -31,6 +33,7 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_op_normal", "tvdeblur_op_precond", "tvdeblur_op_export", "tvdeblur_set_profiling",
     "tvdeblur_get_kernel_times", "tvdeblur_solve_adjoint", "tvdeblur_batch_create", "tvdeblur_batch_solve",
     "tvdeblur_batch_get_info", "tvdeblur_batch_destroy", "tvdeblur_batch_last_error",
+    "tvdeblur_set_transform", "tvdeblur_get_transform",
 )
 BATCH_PRECOND = ("x", "d_x", "x_d")
 
@@ -66,8 +69,8 @@ class Stats(ctypes.Structure):
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("n_kinds", ctypes.c_int), ("name", (ctypes.c_char * 24) * 8),
-                ("launches", ctypes.c_longlong * 8), ("total_ms", ctypes.c_double * 8)]
+    _fields_ = [("n_kinds", ctypes.c_int), ("name", (ctypes.c_char * 24) * KTIME_KINDS),
+                ("launches", ctypes.c_longlong * KTIME_KINDS), ("total_ms", ctypes.c_double * KTIME_KINDS)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -126,6 +129,8 @@ def load():
                                  ctypes.POINTER(Stats)],
         "tvdeblur_batch_get_info": [vp, ctypes.POINTER(BatchInfo)],
         "tvdeblur_batch_destroy": [vp],
+        "tvdeblur_set_transform": [vp, i],
+        "tvdeblur_get_transform": [vp, ctypes.POINTER(i)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -237,6 +242,16 @@ class TVDeblur:
                                                  ctypes.byref(st))
         self._check(rc)
         return vbar, ab.value, bb.value, st.to_dict()
+
+    def set_transform(self, mode):
+        """'auto' (pick the faster at build), 'fft' or 'gemm' (see tvdeblur_set_transform)."""
+        self._check(self.lib.tvdeblur_set_transform(self.h, TRANSFORM[mode]))
+
+    def transform(self):
+        """The transform implementation in use: 'fft' or 'gemm'."""
+        v = ctypes.c_int()
+        self._check(self.lib.tvdeblur_get_transform(self.h, ctypes.byref(v)))
+        return {1: "fft", 2: "gemm"}[v.value]
 
     def set_profiling(self, every):
         """every: time every every-th launch of each kernel class (True = 1);

@@ -1,0 +1,129 @@
+"""GPU parity of the two implementations of the preconditioner's 2D
+transforms (Section 3.2): line transforms on the library's FFT in LDS, and
+dense products with the n x n basis matrix on the matrix cores.  Both are
+checked against the FP64 oracle, as single operator applications and as
+whole restorations.
+
+Bars: the preconditioner solve to 1e-12 (FP64) / 1e-5 (FP32-mixed) relative
+(max-norm); restorations to 1e-10 / 1e-5 relative 2-norm, with the oracle's
+iteration counts replayed where a borderline stopping decision differs.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1011_5964_amd import synth
+from parity import check_f64_counts
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+AR, R = "antireflective", "reflective"
+OP_BAR = {"f64": 1e-12, "f32_mixed": 1e-5}
+BAR = {"f64": 1e-10, "f32_mixed": 1e-5}
+
+
+def dev(a, prec):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rel2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def handle(shape, psf, bc, prec, transform):
+    from paper_1011_5964_amd.lib import TVDeblur
+    h = TVDeblur(shape[0], shape[1], prec)
+    h.set_psf(psf)
+    h.set_bc(bc)
+    h.set_transform(transform)
+    return h
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
+@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("variant", ["x", "d_x", "x_d"])
+@pytest.mark.parametrize("shape", [(64, 64), (37, 50), (130, 70), (33, 300)])
+def test_precond_forms_match_oracle(shape, variant, bc, transform, prec):
+    """z = P^{-1} r for both transform implementations on square, ragged and
+    elongated images (several 32 x 32 product tiles plus tails in every
+    direction)."""
+    print(f"case precond {shape} {variant} {bc} {transform} {prec}", flush=True)
+    rng = np.random.default_rng(11)
+    psf = synth.gaussian_psf(7, 1.2)
+    p = synth.small_problem(n=max(shape), psf_size=7, sigma=1.2, bc=bc)
+    uk = p.v[:shape[0], :shape[1]] + 0.01 * rng.standard_normal(shape)
+    alpha, beta = 3e-3, 0.07
+    h = handle(shape, psf, bc, prec, transform)
+    h.setup(dev(uk, prec), alpha, beta, variant)
+    assert h.transform() == transform
+    ukq = host(dev(uk, prec))
+    ref = O.precond_setup(O.kappa(ukq, beta), alpha, O.psf_symbol_eigenvalues(psf, *shape, bc), bc, variant)
+    r = rng.standard_normal(shape)
+    z = host(h.precond(dev(r, prec)))
+    err = relmax(z, O.precond_apply(host(dev(r, prec)), ref, bc))
+    print(f"  rel err {err:.2e}", flush=True)
+    assert err < OP_BAR[prec]
+
+
+def test_auto_choice_is_one_of_the_two():
+    h = handle((96, 80), synth.gaussian_psf(5, 1.0), AR, "f32_mixed", "auto")
+    assert h.transform() in ("fft", "gemm")
+
+
+def restore_parity(p, transform, variant="x_d", prec="f32_mixed"):
+    vq = host(dev(p.v, prec))
+    uo, so = O.fp_solve(vq, p.psf, p.bc, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant)
+    h = handle(p.v.shape, p.psf, p.bc, prec, transform)
+    assert h.transform() == transform
+    v = dev(p.v, prec)
+    u, st = h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant)
+    err = rel2(host(u), uo)
+    print(f"  {transform} {prec}: gpu {st['inner_iters']} oracle {so['inner_iters']} err {err:.2e}", flush=True)
+    if prec == "f64":
+        check_f64_counts(p, variant, vq, p.n_outer, st["inner_iters"], so["inner_iters"])
+    else:
+        assert err <= BAR[prec]
+        assert all(abs(a - b) <= max(3, b // 4) for a, b in zip(st["inner_iters"], so["inner_iters"]))
+    if st["inner_iters"] != so["inner_iters"]:
+        ur, sr = h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant, replay=so["inner_iters"])
+        assert sr["inner_iters"] == so["inner_iters"]
+        err = rel2(host(ur), uo)
+    assert err <= BAR[prec]
+    return st
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
+@pytest.mark.parametrize("variant", ["x", "d_x", "x_d"])
+@pytest.mark.parametrize("bc", [AR, R])
+def test_restoration_both_forms_small_ragged(bc, variant, transform, prec):
+    print(f"case restore {bc} {variant} {transform} {prec}", flush=True)
+    p = synth.small_problem(n=38, ny=45, psf_size=7, sigma=1.3, bc=bc, n_outer=3, alpha=2e-3, beta=0.1)
+    restore_parity(p, transform, variant, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
+def test_restoration_both_forms_c1(transform, prec):
+    print(f"case c1 {transform} {prec}", flush=True)
+    restore_parity(synth.config("c1"), transform, prec=prec)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+def test_restoration_product_form_512(prec):
+    """The 512^2 anti-reflective workload (15 steps) with the product form."""
+    print(f"case m512 gemm {prec}", flush=True)
+    restore_parity(synth.config("m512"), "gemm", prec=prec)
