@@ -279,8 +279,9 @@ class Solver final : public SolverBase {
             if (ty_h_ == 0 || ty_ht_ == 0 || ty_h_hp_ == 0 || ty_ht_hp_ == 0)
                 throw ApiError{TVD_ESIZE, "PSF too large for the device's LDS tile"};
         }
-        // Toeplitz-compressed K_x for the x-pass fused into the inverse row
-        // transform (rank-1 PSFs; the column half runs in k_ypass)
+        // Toeplitz-compressed K_x for the row half of the split normal
+        // operator (rank-1 PSFs; the column half runs in k_ypass)
+        xsplit_ = false;
         xpass_ = false;
         if (fused_ && 2 * my_ <= 32) {
             const ToeplitzBand tb = compress_band(kx, nx_, 2 * mx_);
@@ -292,7 +293,7 @@ class Solver final : public SolverBase {
             kw_ = tb.w;
             klo_ = tb.lo;
             khi_ = tb.hi;
-            xpass_ = true;
+            xsplit_ = true;
         }
         // symbol eigenvalues
         lamh_host_ = symbol_eigenvalues(psf.data(), py, px, ny_, nx_, bc);
@@ -319,12 +320,17 @@ class Solver final : public SolverBase {
         };
         place_tables(planX_, gx_);
         place_tables(planY_, gy_);
+        // The row half goes into the inverse row transform when its band fits
+        // next to the transform buffers, else into a row pass of its own.
         gxi_ = gx_;
-        if (xpass_) {
+        if (xsplit_) {
             const size_t xb = ((size_t(xband_len_) * sizeof(T) + 1023) / 1024) * 1024;
-            const size_t ylds = (size_t(16 + 4 * my_) * 64 + size_t(18) * 66) * sizeof(T);
-            if (gx_.lds + xb + kStaticLds <= max_lds_ && ylds + kStaticLds <= max_lds_) gxi_.lds += xb;
-            else xpass_ = false;
+            if (ypass_lds_bytes(2 * my_, sizeof(T)) + kStaticLds > max_lds_) {
+                xsplit_ = false;
+            } else if (gx_.lds + xb + kStaticLds <= max_lds_) {
+                gxi_.lds += xb;
+                xpass_ = true;
+            }
         }
         // basis matrices for the eigenvalue setup
         make_basis(ny_, Wy_, Puy_, Puly_, Ply_);
@@ -435,7 +441,7 @@ class Solver final : public SolverBase {
         }
         const std::string key = std::to_string(sizeof(T)) + ":" + std::to_string(bc_) + ":" + std::to_string(ny_) +
                                 "x" + std::to_string(nx_) + ":" + std::to_string(my_) + "x" + std::to_string(mx_) +
-                                ":" + std::to_string(int(xpass_));
+                                ":" + std::to_string(int(xsplit_)) + std::to_string(int(xpass_));
         {
             std::lock_guard<std::mutex> lk(g_transform_mu);
             auto f = g_transform_cache.find(key);
@@ -451,7 +457,7 @@ class Solver final : public SolverBase {
         float ms[2] = {0.f, 0.f};
         for (int mode = 0; mode < 2; ++mode) {
             tmode_ = mode;
-            auto pass = [&]() { precond_pass(R_, Z_, rz_[0], xpass_); };
+            auto pass = [&]() { precond_pass(R_, Z_, rz_[0], xsplit_); };
             pass();
             TVD_HIP(hipEventRecord(ev_a_, s_));
             for (int r = 0; r < 5; ++r) pass();
@@ -474,8 +480,27 @@ class Solver final : public SolverBase {
         } else {
             rowpass(0, false, const_cast<T*>(r), nullptr, 0);
             colpass(0, false, 0);
-            rowpass_inv(z, const_cast<T*>(r), rz_out, xp);
+            rowpass_inv(z, const_cast<T*>(r), rz_out, xp && xpass_);
+            if (xp && !xpass_) xpass_launch(z);
         }
+    }
+
+    // w = (I (x) K_x) z in a row pass of its own.
+    void xpass_launch(const T* z) {
+        XPassArgs<T> x{};
+        x.ny = ny_;
+        x.nx = nx_;
+        x.z = z;
+        x.w = W_;
+        x.xband = xband_;
+        x.xband_len = xband_len_;
+        x.kw = kw_;
+        x.klo = klo_;
+        x.khi = khi_;
+        x.st = st_;
+        timer_.begin(KernelTimer::kXPass, s_);
+        TVD_HIP(launch_xpass<T>(x, s_));
+        timer_.end(s_);
     }
 
     // PCG update of the product-form path (see UpdArgs); update == false:
@@ -503,12 +528,16 @@ class Solver final : public SolverBase {
     }
 
     // z = s o (Py [(Py^T (t Px)) / mu] Px^T) from t in T2_ (four products on
-    // the matrix cores), <r, z> partials into rz_out, then w = K_x z if xp.
-    // check: the PCG stopping test runs first, from n_rr partials in rr_[0].
+    // the matrix cores, each C = A Bt^T with k-contiguous operands: the first
+    // and third write their result transposed for the next one), <r, z>
+    // partials into rz_out, then w = K_x z if xp.  check: the PCG stopping
+    // test runs first, from n_rr partials in rr_[0].
     void gemm_transform(int it, bool check, int n_rr, const T* r, T* z, double* rz_out, bool xp) {
         MGemmArgs<T> g{};
         g.st = st_;
         g.iter = it;
+        g.M = ny_;
+        g.N = nx_;
         auto run = [&]() {
             int nb = 0;
             timer_.begin(KernelTimer::kGemm, s_);
@@ -516,55 +545,47 @@ class Solver final : public SolverBase {
             timer_.end(s_);
             return nb;
         };
-        g.M = ny_;
-        g.N = nx_;
+        // T1^T = (t Px)^T
         g.K = nx_;
         g.A = T2_;
-        g.B = Px_;
+        g.Bt = PxT_;
         g.C = T1_;
+        g.transC = 1;
         g.check = check ? 1 : 0;
         g.rr_part = rr_[0];
         g.n_rr = n_rr;
         run();
+        // T2 = (Py^T T1) / mu
         g.check = 0;
         g.K = ny_;
         g.A = PyT_;
-        g.B = T1_;
+        g.Bt = T1_;
         g.C = T2_;
+        g.transC = 0;
         g.epi = 1;
         g.E1 = MuInv_;
         run();
+        // T3^T = (T2 Px^T)^T
         g.K = nx_;
         g.A = T2_;
-        g.B = PxT_;
+        g.Bt = Px_;
         g.C = T1_;
+        g.transC = 1;
         g.epi = 0;
         g.E1 = nullptr;
         run();
+        // z = s o (Py T3), <r, z> partials
         g.K = ny_;
         g.A = Py_;
-        g.B = T1_;
+        g.Bt = T1_;
         g.C = z;
+        g.transC = 0;
         g.epi = 2;
         g.E1 = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
         g.E2 = r;
         g.part = rz_out;
         nb_g4_ = run();
-        if (xp) {
-            XPassArgs<T> x{};
-            x.ny = ny_;
-            x.nx = nx_;
-            x.z = z;
-            x.w = W_;
-            x.xband = xband_;
-            x.kw = kw_;
-            x.klo = klo_;
-            x.khi = khi_;
-            x.st = st_;
-            timer_.begin(KernelTimer::kXPass, s_);
-            TVD_HIP(launch_xpass<T>(x, s_));
-            timer_.end(s_);
-        }
+        if (xp) xpass_launch(z);
     }
 
     // Line geometry of a batched launch whose blocks have `threads` threads,
@@ -995,7 +1016,7 @@ class Solver final : public SolverBase {
         residual_hp(X_, R_, rr_[0]);
         int last_rr_n = nb_res_;
         const double* last_rr = rr_[0];
-        const bool xp = transform && xpass_;
+        const bool xp = transform && xsplit_;
         const bool gm = transform && tmode_ == 1;
         if (gm) {
             upd_launch(0, false, R_);
@@ -1004,7 +1025,8 @@ class Solver final : public SolverBase {
         } else if (transform) {
             rowpass(0, false, R_, nullptr, 0);
             colpass(0, true, nb_res_, rr_[0]);
-            rowpass_inv(Z_, R_, rz_[0], xp);
+            rowpass_inv(Z_, R_, rz_[0], xp && xpass_);
+            if (xp && !xpass_) xpass_launch(Z_);
             n_rz_ = gx_.blocks;
         } else {
             int nb = 0;
@@ -1030,7 +1052,8 @@ class Solver final : public SolverBase {
                 last_rr_n = gx_.blocks;
                 if (it < maxit) {
                     colpass(it, true, gx_.blocks, rr_[0]);
-                    rowpass_inv(Z_, R_, rz_[it & 1], xp);
+                    rowpass_inv(Z_, R_, rz_[it & 1], xp && xpass_);
+                    if (xp && !xpass_) xpass_launch(Z_);
                 }
             } else {
                 int nb = 0;
@@ -1276,7 +1299,8 @@ class Solver final : public SolverBase {
     const double *HyD_ = nullptr, *HxD_ = nullptr, *HTyD_ = nullptr, *HTxD_ = nullptr, *KyD_ = nullptr,
                  *KxD_ = nullptr;
     int ty_res_ = 0, ty_h_hp_ = 0, ty_ht_hp_ = 0, nb_res_ = 0;
-    bool xpass_ = false;
+    bool xsplit_ = false;  // normal operator as row half (K_x) + y-pass
+    bool xpass_ = false;   // row half fused into the inverse row transform
     const T* xband_ = nullptr;
     int xband_len_ = 0, kw_ = 0, klo_ = 0, khi_ = 0;
     LineGeom gxi_{};

@@ -145,15 +145,17 @@ struct YPassArgs {
     const PcgState* st;
 };
 
-// Dense product on the matrix cores, C = A B (row-major A: M x K, B: K x N,
-// C: M x N), with an optional PCG stopping test before it and an
-// elementwise epilogue.
+// Dense product on the matrix cores, C = A Bt^T: A is M x K and Bt is N x K,
+// both row-major (k contiguous); C is M x N row-major, or stored transposed
+// (N x M row-major) with transC.  An optional PCG stopping test runs before
+// the product and an elementwise epilogue after it (on the M x N layout).
 template <typename T>
 struct MGemmArgs {
     int M, N, K;
     const T* A;
-    const T* B;
+    const T* Bt;
     T* C;
+    int transC;
     int epi;                // 0: C = AB; 1: C = E1 o AB; 2: C = E1 o AB and <E2, C> partials
     const T* E1;
     const T* E2;
@@ -195,6 +197,7 @@ struct XPassArgs {
     const T* z;
     T* w;
     const T* xband;
+    int xband_len;
     int kw, klo, khi;
     const PcgState* st;
 };

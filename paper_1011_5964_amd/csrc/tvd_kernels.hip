@@ -815,6 +815,18 @@ __device__ __forceinline__ bool pcg_stop_test(PcgState* st, double rrp, int iter
     return false;
 }
 
+// Block index -> work index such that the blocks the hardware places on one
+// XCD (dispatch is round-robin over the 8 XCDs: block b runs on XCD b % 8)
+// take one contiguous range of work: neighbouring columns and tiles then
+// share that XCD's L2 instead of being fetched into all eight.  A bijection
+// on [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    constexpr int kXcd = 8;
+    const int x = b % kXcd, j = b / kXcd;
+    const int q = nb / kXcd, r = nb % kXcd;
+    return x * q + min(x, r) + j;
+}
+
 // Column pass: convergence test, forward column transform, divide by mu,
 // inverse column transform.
 template <typename T, bool kTabLds>
@@ -899,15 +911,16 @@ __device__ __forceinline__ void colpass_body(const ColPassArgs<T>& a, int bx) {
 
 template <typename T, bool kTabLds>
 __global__ void k_colpass(ColPassArgs<T> a) {
-    colpass_body<T, kTabLds>(a, blockIdx.x);
+    colpass_body<T, kTabLds>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <typename T, bool kTabLds>
 __global__ void k_colpass_b(const ColPassArgs<T>* __restrict__ as, int it) {
     ColPassArgs<T> a = as[blockIdx.z];
-    if (int(blockIdx.x) >= a.g.blocks || a.st->done) return;
+    const int bx = xcd_remap(blockIdx.x, gridDim.x);
+    if (bx >= a.g.blocks || a.st->done) return;
     a.iter = it;
-    colpass_body<T, kTabLds>(a, blockIdx.x);
+    colpass_body<T, kTabLds>(a, bx);
 }
 
 // Column half of the fused normal operator (see YPassArgs), 64 x 16 outputs
@@ -1024,18 +1037,14 @@ __global__ void __launch_bounds__(kYThreads) k_ypass_b(const YPassArgs<T>* __res
 }
 
 // ------------------------------------------------------------------------
-// Dense products on the matrix cores: C = A B, row-major.  A block of four
-// waves owns a 32 x 32 tile of C, each wave a 16 x 16 MFMA tile (K = 4 per
-// instruction); K runs through LDS in double-buffered slices of BK.  A is
-// kept row-major in LDS with a row stride that puts the two k-rows a wave
-// reads in one cycle in disjoint banks; B is kept k-major.
+// Dense products on the matrix cores (MFMA 16x16x4, one 16 x 16 tile of C
+// per wave).  MfmaCfg holds the instruction and its lane layout per type.
 // ------------------------------------------------------------------------
 template <typename T>
 struct MfmaCfg;
 
 template <>
 struct MfmaCfg<float> {
-    static constexpr int BK = 32, SA = 34, SB = 48;
     typedef float acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -1047,6 +1056,7 @@ struct MfmaCfg<float> {
 
 template <>
 struct MfmaCfg<double> {
+    // K slice and LDS strides of the multi-term setup products (k_mgemm_multi)
     static constexpr int BK = 16, SA = 17, SB = 32;
     typedef double acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
@@ -1068,17 +1078,36 @@ __device__ __forceinline__ void mma_slice(const T* As, const T* Bs, int lane, in
     for (int kk = 0; kk < Cfg::BK / 4; ++kk) acc = Cfg::mma(as[4 * kk], bs[4 * kk * Cfg::SB], acc);
 }
 
+// C = A Bt^T (MGemmArgs): a block owns a 32 x 32 tile of C, each wave a
+// 16 x 16 MFMA tile.  A and Bt are both k-contiguous, so every lane loads its
+// own fragments from global memory (L2) straight into registers, VEC
+// consecutive k per load: lane group g = lane / 16 supplies k = VEC j .. and
+// feeds VEC instructions from one load (a permutation of K, the same for A
+// and Bt).  Loads run a stage of kNtU such loads ahead of the MFMAs (register
+// ping-pong); no LDS and no barriers in the product.
 template <typename T>
+struct NtCfg;
+template <>
+struct NtCfg<float> {
+    static constexpr int VEC = 4;
+};
+template <>
+struct NtCfg<double> {
+    static constexpr int VEC = 2;
+};
+constexpr int kNtU = 8;
+
+// kFast: K is a multiple of two stages, so the stage loop has no branches
+// (its last prefetch re-reads the final stage) and the compiler can count
+// the loads in flight exactly; otherwise a general loop with masked tails.
+template <typename T, bool kFast>
 __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
     using Cfg = MfmaCfg<T>;
-    constexpr int BK = Cfg::BK, SA = Cfg::SA, SB = Cfg::SB, TM = 32, TN = 32;
-    constexpr int AE = TM * BK / 256, BE = BK * TN / 256;  // elements per thread per slice
-    __shared__ T As[2][TM * SA];
-    __shared__ T Bs[2][BK * SB];
+    constexpr int VEC = NtCfg<T>::VEC, STEP = 4 * VEC;  // k consumed per load round
+    constexpr int SK = kNtU * STEP;                     // k per stage
     __shared__ double red[17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int M = a.M, N = a.N, K = a.K;
-    const int m0 = by * TM, n0 = bx * TN;
     if (a.st) {
         const int done = a.st->done;
         const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, 256) : 0.0;
@@ -1087,54 +1116,103 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         if (done) return;
         if (a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red)) return;
     }
-    const int ar = tid / (BK / AE), ak = (tid % (BK / AE)) * AE;
-    const int bk = tid / (TN / BE), bc = (tid % (TN / BE)) * BE;
-    T ra[AE], rb[BE];
-    auto gload = [&](int kt) {
-        const int k0 = kt * BK;
-        const int gr = m0 + ar;
-#pragma unroll
-        for (int c = 0; c < AE; ++c) {
-            const int gk = k0 + ak + c;
-            ra[c] = (gr < M && gk < K) ? a.A[size_t(gr) * K + gk] : T(0);
-        }
-        const int gk = k0 + bk;
-#pragma unroll
-        for (int c = 0; c < BE; ++c) {
-            const int gc = n0 + bc + c;
-            rb[c] = (gk < K && gc < N) ? a.B[size_t(gk) * N + gc] : T(0);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int c = 0; c < AE; ++c) As[buf][ar * SA + ak + c] = ra[c];
-#pragma unroll
-        for (int c = 0; c < BE; ++c) Bs[buf][bk * SB + bc + c] = rb[c];
-    };
+    const int wr = by * 32 + (wave >> 1) * 16, wc = bx * 32 + (wave & 1) * 16;
+    const int g = lane >> 4, idx = lane & 15;
+    const int ra = wr + idx, rb = wc + idx;
+    const T* pa = a.A + size_t(ra < M ? ra : 0) * K;
+    const T* pb = a.Bt + size_t(rb < N ? rb : 0) * K;
+    const bool vec_ok = (K % VEC) == 0;  // uniform
+    const int kg = VEC * g;              // this lane's offset inside a round
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
     typename Cfg::acc_t acc = {};
-    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;
-    const int nkt = (K + BK - 1) / BK;
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nkt) gload(kt + 1);
-        mma_slice<T>(As[buf], Bs[buf], lane, wr, wc, acc);
-        if (kt + 1 < nkt) sstore(buf ^ 1);
-        __syncthreads();
+    vec_t fa[2][kNtU], fb[2][kNtU];
+    // A row (Bt row) outside the matrix only feeds rows (columns) of C that
+    // are not stored, so its address is just clamped to row 0; only k beyond
+    // K must read as zero, which happens in the last stage alone.
+    auto load_stage = [&](int buf, int k0) {
+        if (vec_ok && k0 + SK <= K) {
+#pragma unroll
+            for (int u = 0; u < kNtU; ++u) {
+                const int k = k0 + u * STEP + kg;
+                fa[buf][u] = *reinterpret_cast<const vec_t*>(pa + k);
+                fb[buf][u] = *reinterpret_cast<const vec_t*>(pb + k);
+            }
+        } else if (vec_ok) {
+#pragma unroll
+            for (int u = 0; u < kNtU; ++u) {
+                const int k = k0 + u * STEP + kg;
+                const int kc = min(k, K - VEC);
+                const vec_t va = *reinterpret_cast<const vec_t*>(pa + kc);
+                const vec_t vb = *reinterpret_cast<const vec_t*>(pb + kc);
+                fa[buf][u] = k < K ? va : vec_t{};
+                fb[buf][u] = k < K ? vb : vec_t{};
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kNtU; ++u) {
+                const int k = k0 + u * STEP + kg;
+#pragma unroll
+                for (int c = 0; c < VEC; ++c) {
+                    fa[buf][u][c] = k + c < K ? pa[k + c] : T(0);
+                    fb[buf][u][c] = k + c < K ? pb[k + c] : T(0);
+                }
+            }
+        }
+    };
+    auto compute_stage = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < kNtU; ++u)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc = Cfg::mma(fa[buf][u][e], fb[buf][u][e], acc);
+    };
+    const int nst = (K + SK - 1) / SK;
+    if constexpr (kFast) {
+        auto load_full = [&](int buf, int k0) {
+#pragma unroll
+            for (int u = 0; u < kNtU; ++u) {
+                const int k = k0 + u * STEP + kg;
+                fa[buf][u] = *reinterpret_cast<const vec_t*>(pa + k);
+                fb[buf][u] = *reinterpret_cast<const vec_t*>(pb + k);
+            }
+        };
+        // scheduling barriers keep each stage's loads ahead of the previous
+        // stage's MFMAs (the scheduler would otherwise pull every load next
+        // to its use and leave almost nothing in flight)
+        const int last = K - SK;
+        load_full(0, 0);
+        for (int st = 0; st < nst; st += 2) {
+            load_full(1, (st + 1) * SK);
+            __builtin_amdgcn_sched_barrier(0);
+            compute_stage(0);
+            __builtin_amdgcn_sched_barrier(0);
+            load_full(0, min((st + 2) * SK, last));
+            __builtin_amdgcn_sched_barrier(0);
+            compute_stage(1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        load_stage(0, 0);
+        int st = 0;
+        for (; st + 2 <= nst; st += 2) {
+            load_stage(1, (st + 1) * SK);
+            compute_stage(0);
+            if (st + 2 < nst) load_stage(0, (st + 2) * SK);
+            compute_stage(1);
+        }
+        if (st < nst) compute_stage(0);
     }
     double part = 0.0;
-    const int j = n0 + wc + (lane & 15);
+    const int jc = wc + idx;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wr + Cfg::orow(lane, r);
-        if (i < M && j < N) {
-            const size_t g = size_t(i) * N + j;
+        const int i = wr + Cfg::orow(lane, r);
+        if (i < M && jc < N) {
+            const size_t gidx = size_t(i) * N + jc;
             T v = acc[r];
-            if (a.epi >= 1 && a.E1) v *= a.E1[g];
-            a.C[g] = v;
-            if (a.epi == 2) part += double(a.E2[g]) * double(v);
+            if (a.epi >= 1 && a.E1) v *= a.E1[gidx];
+            if (a.transC) a.C[size_t(jc) * M + i] = v;
+            else a.C[gidx] = v;
+            if (a.epi == 2) part += double(a.E2[gidx]) * double(v);
         }
     }
     if (a.epi == 2) {
@@ -1143,9 +1221,10 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     }
 }
 
-template <typename T>
+template <typename T, bool kFast>
 __global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
-    mgemm_body(a, blockIdx.x, blockIdx.y, gridDim.x);
+    const int b = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    mgemm_body<T, kFast>(a, b % gridDim.x, b / gridDim.x, gridDim.x);
 }
 
 // FP64 sums of products C = sum_t coef_t op(A_t) B_t on the matrix cores
@@ -1227,14 +1306,31 @@ __global__ void __launch_bounds__(256) k_mgemm_multi(const GemmProblem* __restri
     }
 }
 
-// x += a p, r -= a q, ||r||^2 partials, t = s o r (see UpdArgs).
+// x += a p, r -= a q, ||r||^2 partials, t = s o r (see UpdArgs).  Each
+// thread owns kUpdE elements (stride 256 inside the block's range); all its
+// loads are issued before the scalar reductions.
+constexpr int kUpdE = 4;
 template <typename T>
 __global__ void __launch_bounds__(256) k_upd(UpdArgs<T> a) {
     __shared__ double red[17];
     const int tid = threadIdx.x;
+    const int base = blockIdx.x * 256 * kUpdE + tid;
     const int done = a.st->done;
     const double pq = a.do_update ? partial_issue(a.pq_part, a.n_pq, tid, 256) : 0.0;
     const double rzp = a.do_update ? partial_issue(a.rz_part, a.n_rz, tid, 256) : 0.0;
+    T rv[kUpdE], qv[kUpdE], xv[kUpdE], pv[kUpdE], sv[kUpdE];
+#pragma unroll
+    for (int c = 0; c < kUpdE; ++c) {
+        const int k = base + 256 * c;
+        const bool in = k < a.n;
+        rv[c] = in ? a.r[k] : T(0);
+        sv[c] = (in && a.s) ? a.s[k] : T(1);
+        if (a.do_update) {
+            qv[c] = in ? a.q[k] : T(0);
+            xv[c] = in ? a.x[k] : T(0);
+            pv[c] = in ? a.p[k] : T(0);
+        }
+    }
     if (done) return;
     T step = T(0);
     if (a.do_update) {
@@ -1250,16 +1346,18 @@ __global__ void __launch_bounds__(256) k_upd(UpdArgs<T> a) {
         step = T(rz / g);
     }
     double part = 0.0;
-    const int stride = gridDim.x * 256;
-    for (int k = blockIdx.x * 256 + tid; k < a.n; k += stride) {
-        T rv = a.r[k];
+#pragma unroll
+    for (int c = 0; c < kUpdE; ++c) {
+        const int k = base + 256 * c;
+        if (k >= a.n) continue;
+        T r = rv[c];
         if (a.do_update) {
-            rv -= step * a.q[k];
-            a.x[k] += step * a.p[k];
-            a.r[k] = rv;
-            part += double(rv) * double(rv);
+            r -= step * qv[c];
+            a.x[k] = xv[c] + step * pv[c];
+            a.r[k] = r;
+            part += double(r) * double(r);
         }
-        a.t[k] = a.s ? a.s[k] * rv : rv;
+        a.t[k] = sv[c] * r;
     }
     if (a.do_update) {
         const double sm = block_sum(part, red);
@@ -1267,20 +1365,24 @@ __global__ void __launch_bounds__(256) k_upd(UpdArgs<T> a) {
     }
 }
 
-// w = (I (x) K_x) z, one row per block (z row staged in LDS).
+// w = (I (x) K_x) z, one row per block; the z row and the band's rows
+// (interior Toeplitz row, then the stored edge rows) are staged in LDS.
 template <typename T>
 __global__ void __launch_bounds__(256) k_xpass(XPassArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* zs = reinterpret_cast<T*>(smem_raw);
-    const int i = blockIdx.x, tid = threadIdx.x, nx = a.nx;
+    const int nx = a.nx;
+    T* cs = zs + nx;
+    const int i = blockIdx.x, tid = threadIdx.x;
     if (a.st && a.st->done) return;
     const T* zr = a.z + size_t(i) * nx;
     for (int t = tid; t < nx; t += 256) zs[t] = zr[t];
+    for (int t = tid; t < a.xband_len; t += 256) cs[t] = a.xband[t];
     __syncthreads();
     const int bw = 2 * a.kw + 1;
     for (int t = tid; t < nx; t += 256) {
         const int rr = t < a.klo ? 1 + t : (t >= a.khi ? 1 + a.klo + (t - a.khi) : 0);
-        const T* coef = a.xband + rr * bw;
+        const T* coef = cs + rr * bw;
         T sacc = T(0);
         for (int d = 0; d < bw; ++d) sacc += coef[d] * zs[min(max(t + d - a.kw, 0), nx - 1)];
         a.w[size_t(i) * nx + t] = sacc;
@@ -1733,13 +1835,15 @@ template <typename T>
 hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
     dim3 grid((a.N + 31) / 32, (a.M + 31) / 32);
     if (nblocks) *nblocks = int(grid.x * grid.y);
-    tvd_launch(k_mgemm<T>, grid, dim3(256), 0, s, a);
+    constexpr int two_stages = 2 * kNtU * 4 * NtCfg<T>::VEC;
+    if (a.K % two_stages == 0) tvd_launch(k_mgemm<T, true>, grid, dim3(256), 0, s, a);
+    else tvd_launch(k_mgemm<T, false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_upd(const UpdArgs<T>& a, hipStream_t s, int* nblocks) {
-    const int nb = std::max(1, std::min(1024, (a.n + 255) / 256));
+    const int nb = std::max(1, (a.n + 256 * kUpdE - 1) / (256 * kUpdE));
     if (nblocks) *nblocks = nb;
     tvd_launch(k_upd<T>, dim3(nb), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -1747,7 +1851,7 @@ hipError_t launch_upd(const UpdArgs<T>& a, hipStream_t s, int* nblocks) {
 
 template <typename T>
 hipError_t launch_xpass(const XPassArgs<T>& a, hipStream_t s) {
-    tvd_launch(k_xpass<T>, dim3(a.ny), dim3(256), size_t(a.nx) * sizeof(T), s, a);
+    tvd_launch(k_xpass<T>, dim3(a.ny), dim3(256), size_t(a.nx + a.xband_len) * sizeof(T), s, a);
     return hipGetLastError();
 }
 
