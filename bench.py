@@ -47,10 +47,12 @@ ITER_WORDS = 13
 ITER_WORDS_WITH_TRANSPOSES = 17
 
 # HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
-# counters (scaled by the same counters on a plain copy kernel of known size)
-# for the kernels in the source whose SHA-256 prefix is recorded; ignored when
-# the kernel source has changed since.
-TRAFFIC = {"source_sha256": None, "bytes_per_launch": {}}
+# counters on the 512x512 FP32-mixed workload, scaled by the same counters on
+# a plain copy kernel of known size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), for
+# the kernel source whose SHA-256 prefix is recorded; ignored (null) once the
+# kernel source has changed since.  Source: profiles/m512_f32_traffic.md.
+TRAFFIC = {"source_sha256": "c1546756f2714177",
+           "bytes_per_launch": {"column": 3759447, "band_normal": 11348199, "row_inverse": 5868783}}
 
 # Kernel durations are sampled on 1 launch in PROFILE_EVERY of each class
 # during the timed solves (a timed launch delays the next by ~9 us).
@@ -245,7 +247,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="all", choices=["all", "none"])
+    ap.add_argument("--forms", default="all",
+                    help="comma list of forms measured beside the headline: f64, batch, diff; 'all' or 'none'")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="fixed-point steps of the oracle CPU sample (0 = skip the oracle)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -284,21 +287,28 @@ def main():
            "pcg_iters_per_s_inner_loop": round(r32["pcg_iters_per_s_inner_loop"], 1),
            "setup_share": round(r32["setup_share"], 4), "kernel_classes": r32["kernel_classes"]}
 
+    sel = {"all": {"f64", "batch", "diff"}, "none": set()}.get(args.forms, set(args.forms.split(",")))
     forms = {}
     u64 = None
-    if args.forms == "all":
+    probs = None
+    r64_time = None
+    if "f64" in sel or "batch" in sel or "diff" in sel:
+        # the speedups of every form are against the plain FP64 path
         print("[bench] plain FP64 path", file=sys.stderr, flush=True)
         r64, u64 = headline(args, p, "f64")
+        r64_time = r64["restore_time_s"]
         forms["plain_f64"] = {k: r64[k] for k in ("restore_time_s", "pcg_iters_per_s", "pcg_iters_per_s_inner_loop",
                                                   "pcg_iters_per_solve", "setup_share")}
         forms["plain_f64"]["iteration_roofline"] = r64["iteration_roofline"]
         forms["f32_mixed"] = {"restore_time_s": r32["restore_time_s"],
-                              "speedup_vs_plain_f64": r64["restore_time_s"] / r32["restore_time_s"]}
+                              "speedup_vs_plain_f64": r64_time / r32["restore_time_s"]}
+    if "batch" in sel:
         print("[bench] batching form (64 ragged images)", file=sys.stderr, flush=True)
-        rb, probs, last = batch_form(args, r64["restore_time_s"])
+        rb, probs, last = batch_form(args, r64_time)
         forms["batch"] = rb
+    if "diff" in sel:
         print("[bench] differentiation form", file=sys.stderr, flush=True)
-        forms["differentiation"] = diff_form(args, r64["restore_time_s"])
+        forms["differentiation"] = diff_form(args, r64_time)
 
     if args.cpu_steps > 0:
         import scipy.fft
@@ -334,7 +344,7 @@ def main():
             if u64 is not None:
                 forms["plain_f64"]["rel_err_vs_oracle"] = rel2(u64, uo)
             forms.setdefault("f32_mixed", {})["rel_err_vs_oracle"] = out["rel_err_vs_oracle"]
-        if args.forms == "all":
+        if probs is not None:
             # per-image error of the batch: one image of each of the three smallest sizes
             errs = {}
             for i, q in enumerate(probs):
