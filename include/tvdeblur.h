@@ -276,6 +276,8 @@ typedef struct {
     const int* replay_host;     /* NULL, or count x max_outer PCG iteration counts
                                    (image-major: [i * max_outer + k]) to run exactly,
                                    stopping test skipped, as tvd_params.replay_host */
+    int    transform;           /* TVD_TRANSFORM_AUTO (the implementation picked at
+                                   create), TVD_TRANSFORM_FFT or TVD_TRANSFORM_GEMM */
 } tvd_batch_params;
 
 #define TVD_TUNE_MAX 4
@@ -287,6 +289,8 @@ typedef struct {
     int    n_candidates;                /* candidates timed (0 when from_cache) */
     int    cand_threads[TVD_TUNE_MAX];
     double cand_us[TVD_TUNE_MAX];       /* time of one set of transform passes */
+    double gemm_us;                     /* the same with the products on the matrix cores */
+    int    transform;                   /* implementation of the last solve (TVD_TRANSFORM_*) */
     long long graph_launches;           /* graph replays since create */
     double time_setup_s;                /* last solve: diffusivity/eigenvalue setup */
     double time_inner_s;                /* last solve: PCG loops */

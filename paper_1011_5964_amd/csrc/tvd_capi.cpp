@@ -493,6 +493,12 @@ class Solver final : public SolverBase {
 
     // w = (I (x) K_x) z in a row pass of its own.
     void xpass_launch(const T* z) {
+        const XPassArgs<T> x = xpass_args(z);
+        timer_.begin(KernelTimer::kXPass, s_);
+        TVD_HIP(launch_xpass<T>(x, s_));
+        timer_.end(s_);
+    }
+    XPassArgs<T> xpass_args(const T* z) const {
         XPassArgs<T> x{};
         x.ny = ny_;
         x.nx = nx_;
@@ -504,14 +510,18 @@ class Solver final : public SolverBase {
         x.klo = klo_;
         x.khi = khi_;
         x.st = st_;
-        timer_.begin(KernelTimer::kXPass, s_);
-        TVD_HIP(launch_xpass<T>(x, s_));
-        timer_.end(s_);
+        return x;
     }
 
     // PCG update of the product-form path (see UpdArgs); update == false:
     // t = s o r only.  t goes to T2_.
     void upd_launch(int it, bool update, const T* r) {
+        const UpdArgs<T> a = upd_args(it, update, r);
+        timer_.begin(KernelTimer::kUpdate, s_);
+        TVD_HIP(launch_upd<T>(a, s_, &nb_upd_));
+        timer_.end(s_);
+    }
+    UpdArgs<T> upd_args(int it, bool update, const T* r) const {
         UpdArgs<T> a{};
         a.n = int(N_);
         a.do_update = update ? 1 : 0;
@@ -528,71 +538,73 @@ class Solver final : public SolverBase {
         a.rr_out = rr_[0];
         a.st = st_;
         a.iter = it;
-        timer_.begin(KernelTimer::kUpdate, s_);
-        TVD_HIP(launch_upd<T>(a, s_, &nb_upd_));
-        timer_.end(s_);
+        return a;
     }
 
-    // z = s o (Py [(Py^T (t Px)) / mu] Px^T) from t in T2_ (four products on
-    // the matrix cores, each C = A Bt^T with k-contiguous operands: the first
-    // and third write their result transposed for the next one), <r, z>
-    // partials into rz_out, then w = K_x z if xp.  check: the PCG stopping
-    // test runs first, from n_rr partials in rr_[0].
+    // The four products of the product form: z = s o (Py [(Py^T (t Px)) / mu]
+    // Px^T) from t in T2_, each C = A Bt^T with k-contiguous operands (the
+    // first and third write their result transposed for the next one), <r, z>
+    // partials into rz_out.  check: the PCG stopping test runs first, from
+    // n_rr partials in rr_[0].
+    void gemm_args(int it, bool check, int n_rr, const T* r, T* z, double* rz_out, MGemmArgs<T> g[4]) const {
+        MGemmArgs<T> b{};
+        b.st = st_;
+        b.iter = it;
+        b.M = ny_;
+        b.N = nx_;
+        // T1^T = (t Px)^T
+        g[0] = b;
+        g[0].K = nx_;
+        g[0].A = T2_;
+        g[0].Bt = PxT_;
+        g[0].C = T1_;
+        g[0].transC = 1;
+        g[0].check = check ? 1 : 0;
+        g[0].rr_part = rr_[0];
+        g[0].n_rr = n_rr;
+        // T2 = (Py^T T1) / mu
+        g[1] = b;
+        g[1].K = ny_;
+        g[1].A = PyT_;
+        g[1].Bt = T1_;
+        g[1].C = T2_;
+        g[1].epi = 1;
+        g[1].E1 = MuInv_;
+        // T3^T = (T2 Px^T)^T
+        g[2] = b;
+        g[2].K = nx_;
+        g[2].A = T2_;
+        g[2].Bt = Px_;
+        g[2].C = T1_;
+        g[2].transC = 1;
+        // z = s o (Py T3), <r, z> partials
+        g[3] = b;
+        g[3].K = ny_;
+        g[3].A = Py_;
+        g[3].Bt = T1_;
+        g[3].C = z;
+        g[3].epi = 2;
+        g[3].E1 = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
+        g[3].E2 = r;
+        g[3].part = rz_out;
+    }
+    int gemm_blocks() const { return ((ny_ + 31) / 32) * ((nx_ + 31) / 32); }
+
+    // Product form of one preconditioner application (see gemm_args), then
+    // w = K_x z if xp.
     void gemm_transform(int it, bool check, int n_rr, const T* r, T* z, double* rz_out, bool xp) {
-        MGemmArgs<T> g{};
-        g.st = st_;
-        g.iter = it;
-        g.M = ny_;
-        g.N = nx_;
-        auto run = [&]() {
+        MGemmArgs<T> g[4];
+        gemm_args(it, check, n_rr, r, z, rz_out, g);
+        for (int k = 0; k < 4; ++k) {
             int nb = 0;
             timer_.begin(KernelTimer::kGemm, s_);
-            TVD_HIP(launch_mgemm<T>(g, s_, &nb));
+            TVD_HIP(launch_mgemm<T>(g[k], s_, &nb));
             timer_.end(s_);
-            return nb;
-        };
-        // T1^T = (t Px)^T
-        g.K = nx_;
-        g.A = T2_;
-        g.Bt = PxT_;
-        g.C = T1_;
-        g.transC = 1;
-        g.check = check ? 1 : 0;
-        g.rr_part = rr_[0];
-        g.n_rr = n_rr;
-        run();
-        // T2 = (Py^T T1) / mu
-        g.check = 0;
-        g.K = ny_;
-        g.A = PyT_;
-        g.Bt = T1_;
-        g.C = T2_;
-        g.transC = 0;
-        g.epi = 1;
-        g.E1 = MuInv_;
-        run();
-        // T3^T = (T2 Px^T)^T
-        g.K = nx_;
-        g.A = T2_;
-        g.Bt = Px_;
-        g.C = T1_;
-        g.transC = 1;
-        g.epi = 0;
-        g.E1 = nullptr;
-        run();
-        // z = s o (Py T3), <r, z> partials
-        g.K = ny_;
-        g.A = Py_;
-        g.Bt = T1_;
-        g.C = z;
-        g.transC = 0;
-        g.epi = 2;
-        g.E1 = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
-        g.E2 = r;
-        g.part = rz_out;
-        nb_g4_ = run();
+            if (k == 3) nb_g4_ = nb;
+        }
         if (xp) xpass_launch(z);
     }
+
 
     // Line geometry of a batched launch whose blocks have `threads` threads,
     // FFT tables in LDS or not; false (nothing changed) if it does not fit.
@@ -1359,6 +1371,7 @@ class BatchBase {
 struct TuneChoice {
     int threads;
     bool tab_lds;
+    int mode = 0;  // 1: products on the matrix cores
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune_cache;
@@ -1389,6 +1402,8 @@ class BatchSolver final : public BatchBase {
                 key << ';' << d[i].ny << 'x' << d[i].nx << '/' << d[i].py << 'x' << d[i].px;
             }
             key_ = key.str();
+            gemm_ok_ = true;
+            for (auto& S : img_) gemm_ok_ = gemm_ok_ && S->gemm_ok_;
             st_ = static_cast<PcgState*>(arena_.alloc(B_ * sizeof(PcgState)));
             for (int i = 0; i < B_; ++i) img_[i]->st_ = st_ + i;
             alloc_tables();
@@ -1407,13 +1422,17 @@ class BatchSolver final : public BatchBase {
         // inputs were produced on the caller's stream
         TVD_HIP(hipEventRecord(ev_in_, user_));
         TVD_HIP(hipStreamWaitEvent(s_, ev_in_, 0));
+        const int mode = p.transform == TVD_TRANSFORM_FFT ? 0 : p.transform == TVD_TRANSFORM_GEMM ? 1 : tuned_mode_;
+        if (mode != bmode_) {
+            bmode_ = mode;
+            clear_graphs();
+        }
+        info_.transform = bmode_ == 1 ? TVD_TRANSFORM_GEMM : TVD_TRANSFORM_FFT;
         for (int i = 0; i < B_; ++i) {
             Solver<T>& S = *img_[i];
             S.alpha_ = p.alpha_host[i];
             S.beta_ = p.beta_host ? p.beta_host[i] : p.beta;
             S.variant_ = p.precond;
-            S.n_pq_ = ypass_blocks(S.ny_, S.nx_);
-            S.n_rz_ = S.gx_.blocks;
         }
         fill_tables();
         std::vector<int> frozen(B_, 0), broke(B_, 0), prev(B_, 8);
@@ -1529,6 +1548,17 @@ class BatchSolver final : public BatchBase {
         y_[1] = table<YPassArgs<T>>();
         fp_a_ = table<FpArgs<T>>();
         fin_a_ = table<FinArgs>();
+        upd0_ = table<UpdArgs<T>>();
+        upd_[0] = table<UpdArgs<T>>();
+        upd_[1] = table<UpdArgs<T>>();
+        gm1i_ = table<MGemmArgs<T>>();
+        gm1_ = table<MGemmArgs<T>>();
+        gm1n_ = table<MGemmArgs<T>>();
+        gm2_ = table<MGemmArgs<T>>();
+        gm3_ = table<MGemmArgs<T>>();
+        gm4_[0] = table<MGemmArgs<T>>();
+        gm4_[1] = table<MGemmArgs<T>>();
+        xp_ = table<XPassArgs<T>>();
         // setup GEMM work lists of all images, with and without the D term
         std::vector<GemmProblem> g1[2], g2[2];
         for (auto& S : img_) {
@@ -1576,6 +1606,13 @@ class BatchSolver final : public BatchBase {
     // Per-image argument blocks of every stage (after the per-image scalars
     // and the line geometry are set).
     void fill_tables() {
+        for (auto& P : img_) {
+            P->n_pq_ = ypass_blocks(P->ny_, P->nx_);
+            P->n_rz_ = bmode_ == 1 ? P->gemm_blocks() : P->gx_.blocks;
+        }
+        std::vector<UpdArgs<T>> u0, ue, uo;
+        std::vector<MGemmArgs<T>> m1i, m1, m1n, m2, m3, m4e, m4o;
+        std::vector<XPassArgs<T>> xa;
         std::vector<KappaArgs<T>> ka;
         std::vector<OperandArgs> oa;
         std::vector<MuArgs<T>> ma;
@@ -1587,6 +1624,9 @@ class BatchSolver final : public BatchBase {
         std::vector<FpArgs<T>> fa;
         std::vector<FinArgs> fi;
         g_rf_ = g_ri_ = g_col_ = BatchGrid{0, 1, B_, 0, line_threads_};
+        g_mg_ = BatchGrid{0, 0, B_, 0, 256};
+        g_upd_ = BatchGrid{0, 1, B_, 0, 256};
+        g_xp_ = BatchGrid{0, 1, B_, 0, 256};
         for (auto& P : img_) {
             Solver<T>& S = *P;
             const int N = int(S.N_);
@@ -1616,7 +1656,30 @@ class BatchSolver final : public BatchBase {
             yo.push_back(S.ypass_args(3));
             const int nfp = std::min(1024, (N + 255) / 256);
             fa.push_back(FpArgs<T>{N, nfp, S.X_, S.U_, S.fp_});
-            fi.push_back(FinArgs{S.st_, S.rr_[0], S.gx_.blocks, S.fp_, nfp, 0});
+            const int n_last_rr = bmode_ == 1 ? upd_block_count(N) : S.gx_.blocks;
+            fi.push_back(FinArgs{S.st_, S.rr_[0], n_last_rr, S.fp_, nfp, 0});
+            if (S.gemm_ok_) {
+                u0.push_back(S.upd_args(0, false, S.R_));
+                ue.push_back(S.upd_args(2, true, S.R_));
+                uo.push_back(S.upd_args(1, true, S.R_));
+                MGemmArgs<T> g[4];
+                S.gemm_args(0, true, S.nb_res_, S.R_, S.Z_, S.rz_[0], g);
+                m1i.push_back(g[0]);
+                m2.push_back(g[1]);
+                m3.push_back(g[2]);
+                m4e.push_back(g[3]);
+                S.gemm_args(0, false, 0, S.R_, S.Z_, S.rz_[0], g);
+                m1n.push_back(g[0]);
+                S.gemm_args(1, true, upd_block_count(N), S.R_, S.Z_, S.rz_[1], g);
+                m1.push_back(g[0]);
+                m4o.push_back(g[3]);
+                xa.push_back(S.xpass_args(S.Z_));
+                g_mg_.gx = std::max(g_mg_.gx, (S.nx_ + 31) / 32);
+                g_mg_.gy = std::max(g_mg_.gy, (S.ny_ + 31) / 32);
+                g_upd_.gx = std::max(g_upd_.gx, upd_block_count(N));
+                g_xp_.gx = std::max(g_xp_.gx, S.ny_);
+                g_xp_.lds = std::max(g_xp_.lds, size_t(S.nx_ + S.xband_len_) * sizeof(T));
+            }
             g_rf_.gx = std::max(g_rf_.gx, S.gx_.blocks);
             g_rf_.lds = std::max(g_rf_.lds, S.gx_.lds);
             g_ri_.gx = std::max(g_ri_.gx, S.gxi_.blocks);
@@ -1644,6 +1707,19 @@ class BatchSolver final : public BatchBase {
         put(fp_a_, fa);
         fin_host_ = fi;
         put(fin_a_, fi);
+        if (int(u0.size()) == B_) {
+            put(upd0_, u0);
+            put(upd_[0], ue);
+            put(upd_[1], uo);
+            put(gm1i_, m1i);
+            put(gm1_, m1);
+            put(gm1n_, m1n);
+            put(gm2_, m2);
+            put(gm3_, m3);
+            put(gm4_[0], m4e);
+            put(gm4_[1], m4o);
+            put(xp_, xa);
+        }
         TVD_HIP(hipStreamSynchronize(s_));
     }
 
@@ -1659,10 +1735,26 @@ class BatchSolver final : public BatchBase {
     // after the x, r update, as in the single-image loop).
     void iteration(int it, bool tail) {
         TVD_HIP(launch_ypass_b<T>(it == 1 ? y1_ : y_[it & 1], g_y_, s_));
+        if (bmode_ == 1) {
+            TVD_HIP(launch_upd_b<T>(upd_[it & 1], it, g_upd_, s_));
+            if (tail) return;
+            gemm_pass(gm1_, gm4_[it & 1], it);
+            return;
+        }
         TVD_HIP(launch_rowpass_b<T>(rf_[it & 1], it, tab_lds_, g_rf_, s_));
         if (tail) return;
         TVD_HIP(launch_colpass_b<T>(c_, it, tab_lds_, g_col_, s_));
         TVD_HIP(launch_rowpass_b<T>(ri_[it & 1], it, tab_lds_, g_ri_, s_));
+    }
+
+    // the four products of the product form and the row half of the next
+    // operator, for every image
+    void gemm_pass(const MGemmArgs<T>* first, const MGemmArgs<T>* last, int it) {
+        TVD_HIP(launch_mgemm_b<T>(first, it, g_mg_, s_));
+        TVD_HIP(launch_mgemm_b<T>(gm2_, it, g_mg_, s_));
+        TVD_HIP(launch_mgemm_b<T>(gm3_, it, g_mg_, s_));
+        TVD_HIP(launch_mgemm_b<T>(last, it, g_mg_, s_));
+        TVD_HIP(launch_xpass_b<T>(xp_, g_xp_, s_));
     }
 
     static constexpr int kChunk = 2;  // iterations per captured graph
@@ -1692,9 +1784,14 @@ class BatchSolver final : public BatchBase {
     void pcg_all(int maxit, int predicted, bool use_graph) {
         TVD_HIP(launch_copy_b<T>(cp_ux_, g_el_, s_));
         TVD_HIP((launch_band_b<T, T, double, T>(res_a_, g_res_, s_)));
-        TVD_HIP(launch_rowpass_b<T>(rf0_, 0, tab_lds_, g_rf_, s_));
-        TVD_HIP(launch_colpass_b<T>(c0_, 0, tab_lds_, g_col_, s_));
-        TVD_HIP(launch_rowpass_b<T>(ri_[0], 0, tab_lds_, g_ri_, s_));
+        if (bmode_ == 1) {
+            TVD_HIP(launch_upd_b<T>(upd0_, 0, g_upd_, s_));
+            gemm_pass(gm1i_, gm4_[0], 0);
+        } else {
+            TVD_HIP(launch_rowpass_b<T>(rf0_, 0, tab_lds_, g_rf_, s_));
+            TVD_HIP(launch_colpass_b<T>(c0_, 0, tab_lds_, g_col_, s_));
+            TVD_HIP(launch_rowpass_b<T>(ri_[0], 0, tab_lds_, g_ri_, s_));
+        }
         int next_poll = std::max(2, predicted - 1);
         int it = 1;
         while (it <= maxit) {
@@ -1732,6 +1829,7 @@ class BatchSolver final : public BatchBase {
             auto f = g_tune_cache.find(key_);
             if (f != g_tune_cache.end()) {
                 apply(f->second.threads, f->second.tab_lds);
+                tuned_mode_ = f->second.mode;
                 info_.from_cache = 1;
                 return;
             }
@@ -1749,7 +1847,7 @@ class BatchSolver final : public BatchBase {
         for (int i = 0; i < B_; ++i) init_host_[i] = InitArgs{st_ + i, 0.0, 0, 0};
         TVD_HIP(hipMemcpyAsync(init_a_, init_host_, B_ * sizeof(InitArgs), hipMemcpyHostToDevice, s_));
         TVD_HIP(launch_init_b(init_a_, B_, s_));
-        TuneChoice best{0, false};
+        TuneChoice best{0, false, 0};
         double best_us = 0.0;
         for (int threads : {256, 512, 1024}) {
             bool tab = true;
@@ -1785,6 +1883,29 @@ class BatchSolver final : public BatchBase {
         }
         if (best.threads == 0) throw ApiError{TVD_ESIZE, "no transform-pass geometry fits the batch"};
         apply(best.threads, best.tab_lds);
+        // the product form, against the best line-transform geometry; it must
+        // win by 5% (a near tie keeps the line transforms)
+        best.mode = 0;
+        if (gemm_ok_) {
+            bmode_ = 1;
+            fill_tables();
+            auto pass = [&]() {
+                TVD_HIP(launch_upd_b<T>(upd0_, 0, g_upd_, s_));
+                gemm_pass(gm1n_, gm4_[0], 0);
+            };
+            pass();
+            TVD_HIP(hipEventRecord(ev_a_, s_));
+            constexpr int kReps = 5;
+            for (int r = 0; r < kReps; ++r) pass();
+            TVD_HIP(hipEventRecord(ev_b_, s_));
+            TVD_HIP(hipEventSynchronize(ev_b_));
+            float ms = 0.f;
+            TVD_HIP(hipEventElapsedTime(&ms, ev_a_, ev_b_));
+            info_.gemm_us = 1e3 * ms / kReps;
+            if (info_.gemm_us < 0.95 * best_us) best.mode = 1;
+            bmode_ = 0;
+        }
+        tuned_mode_ = best.mode;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key_] = best;
     }
@@ -1803,9 +1924,13 @@ class BatchSolver final : public BatchBase {
         info_.count = B_;
         info_.line_threads = threads;
         info_.tables_in_lds = tab ? 1 : 0;
+        clear_graphs();
+        return true;
+    }
+
+    void clear_graphs() {
         for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
         graphs_.clear();
-        return true;
     }
 
     void release() {
@@ -1849,6 +1974,13 @@ class BatchSolver final : public BatchBase {
     FpArgs<T>* fp_a_ = nullptr;
     FinArgs* fin_a_ = nullptr;
     std::vector<FinArgs> fin_host_;
+    UpdArgs<T>*upd0_ = nullptr, *upd_[2] = {};
+    MGemmArgs<T>*gm1i_ = nullptr, *gm1_ = nullptr, *gm1n_ = nullptr, *gm2_ = nullptr, *gm3_ = nullptr,
+              *gm4_[2] = {};
+    XPassArgs<T>* xp_ = nullptr;
+    BatchGrid g_mg_{}, g_upd_{}, g_xp_{};
+    bool gemm_ok_ = false;
+    int bmode_ = 0, tuned_mode_ = 0;
     GemmProblem* g1_[2] = {};
     GemmProblem* g2_[2] = {};
     int n1_[2] = {}, n2_[2] = {};
@@ -2116,6 +2248,8 @@ int tvdeblur_batch_solve(tvdeblur_batch_t b, const void* const* v_dev_host, void
         return bfail(b, TVD_EINVAL, "bad inner_tol / max_inner / fp_tol");
     if (p->precond != TVD_PREC_X && p->precond != TVD_PREC_D_X && p->precond != TVD_PREC_X_D)
         return bfail(b, TVD_EINVAL, "batched solves take TVD_PREC_X, TVD_PREC_D_X or TVD_PREC_X_D");
+    if (p->transform != TVD_TRANSFORM_AUTO && p->transform != TVD_TRANSFORM_FFT && p->transform != TVD_TRANSFORM_GEMM)
+        return bfail(b, TVD_EINVAL, "bad transform");
     if (p->replay_host)
         for (size_t k = 0; k < size_t(b->count) * p->max_outer; ++k)
             if (p->replay_host[k] < 0 || p->replay_host[k] > 100000)

@@ -346,6 +346,14 @@ template <typename T>
 hipError_t launch_upd(const UpdArgs<T>& a, hipStream_t s, int* nblocks);
 template <typename T>
 hipError_t launch_xpass(const XPassArgs<T>& a, hipStream_t s);
+// Batched product-form kernels (image = blockIdx.z; see BatchGrid).
+template <typename T>
+hipError_t launch_mgemm_b(const MGemmArgs<T>* a, int it, BatchGrid g, hipStream_t s);
+template <typename T>
+hipError_t launch_upd_b(const UpdArgs<T>* a, int it, BatchGrid g, hipStream_t s);
+template <typename T>
+hipError_t launch_xpass_b(const XPassArgs<T>* a, BatchGrid g, hipStream_t s);
+int upd_block_count(int n);
 int ypass_blocks(int ny, int nx);
 template <typename T>
 hipError_t launch_colpass(const ColPassArgs<T>& a, hipStream_t s);

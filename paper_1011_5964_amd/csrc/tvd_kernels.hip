@@ -1078,13 +1078,16 @@ __device__ __forceinline__ void mma_slice(const T* As, const T* Bs, int lane, in
     for (int kk = 0; kk < Cfg::BK / 4; ++kk) acc = Cfg::mma(as[4 * kk], bs[4 * kk * Cfg::SB], acc);
 }
 
-// C = A Bt^T (MGemmArgs): a block owns a 32 x 32 tile of C, each wave a
-// 16 x 16 MFMA tile.  A and Bt are both k-contiguous, so every lane loads its
-// own fragments from global memory (L2) straight into registers, VEC
-// consecutive k per load: lane group g = lane / 16 supplies k = VEC j .. and
-// feeds VEC instructions from one load (a permutation of K, the same for A
-// and Bt).  Loads run a stage of kNtU such loads ahead of the MFMAs (register
-// ping-pong); no LDS and no barriers in the product.
+// C = A Bt^T (MGemmArgs): a block owns a 32 x 32 tile of C and splits K over
+// its four waves; each wave accumulates the whole tile (2 x 2 MFMA 16x16
+// tiles) over its quarter of K, and the four partial tiles are summed through
+// LDS before the epilogue.  A and Bt are both k-contiguous, so every lane
+// loads its own fragments from global memory (L2) straight into registers,
+// VEC consecutive k per 16-byte load: lane group g = lane / 16 supplies
+// k = STEP j + VEC g .. + VEC - 1 (a permutation of K, the same for A and Bt),
+// so one load feeds VEC instructions.  A round (STEP k) is four loads (two
+// row halves of A and of Bt) for 4 VEC instructions; loads run one stage of
+// kNtR rounds ahead of the MFMAs.
 template <typename T>
 struct NtCfg;
 template <>
@@ -1095,16 +1098,27 @@ template <>
 struct NtCfg<double> {
     static constexpr int VEC = 2;
 };
-constexpr int kNtU = 8;
+constexpr int kNtR = 2;  // rounds per stage
 
-// kFast: K is a multiple of two stages, so the stage loop has no branches
-// (its last prefetch re-reads the final stage) and the compiler can count
-// the loads in flight exactly; otherwise a general loop with masked tails.
+// The stage loop runs branch-free when each wave's quarter of K is a whole
+// number of stages.
+template <typename T>
+__host__ __device__ constexpr bool mgemm_fast_k(int K) {
+    return K % (4 * kNtR * 4 * NtCfg<T>::VEC) == 0;
+}
+
+// kFast: each wave's K range is a whole number of stages, so the stage-pair
+// loop has no branches (its last prefetch re-reads the final stage) and the
+// compiler can count the loads in flight exactly; otherwise a general loop
+// with masked tails.
 template <typename T, bool kFast>
 __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
     using Cfg = MfmaCfg<T>;
-    constexpr int VEC = NtCfg<T>::VEC, STEP = 4 * VEC;  // k consumed per load round
-    constexpr int SK = kNtU * STEP;                     // k per stage
+    using acc_t = typename Cfg::acc_t;
+    constexpr int VEC = NtCfg<T>::VEC, STEP = 4 * VEC;  // k consumed per round
+    constexpr int SK = kNtR * STEP;                     // k per stage
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    __shared__ T red_tile[4 * 16 * 64];                 // [wave][tile value][lane]
     __shared__ double red[17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int M = a.M, N = a.N, K = a.K;
@@ -1116,99 +1130,120 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         if (done) return;
         if (a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red)) return;
     }
-    const int wr = by * 32 + (wave >> 1) * 16, wc = bx * 32 + (wave & 1) * 16;
+    const int m0 = by * 32, n0 = bx * 32;
     const int g = lane >> 4, idx = lane & 15;
-    const int ra = wr + idx, rb = wc + idx;
-    const T* pa = a.A + size_t(ra < M ? ra : 0) * K;
-    const T* pb = a.Bt + size_t(rb < N ? rb : 0) * K;
-    const bool vec_ok = (K % VEC) == 0;  // uniform
-    const int kg = VEC * g;              // this lane's offset inside a round
-    typedef T vec_t __attribute__((ext_vector_type(VEC)));
-    typename Cfg::acc_t acc = {};
-    vec_t fa[2][kNtU], fb[2][kNtU];
-    // A row (Bt row) outside the matrix only feeds rows (columns) of C that
-    // are not stored, so its address is just clamped to row 0; only k beyond
-    // K must read as zero, which happens in the last stage alone.
-    auto load_stage = [&](int buf, int k0) {
-        if (vec_ok && k0 + SK <= K) {
-#pragma unroll
-            for (int u = 0; u < kNtU; ++u) {
-                const int k = k0 + u * STEP + kg;
-                fa[buf][u] = *reinterpret_cast<const vec_t*>(pa + k);
-                fb[buf][u] = *reinterpret_cast<const vec_t*>(pb + k);
-            }
-        } else if (vec_ok) {
-#pragma unroll
-            for (int u = 0; u < kNtU; ++u) {
-                const int k = k0 + u * STEP + kg;
-                const int kc = min(k, K - VEC);
-                const vec_t va = *reinterpret_cast<const vec_t*>(pa + kc);
-                const vec_t vb = *reinterpret_cast<const vec_t*>(pb + kc);
-                fa[buf][u] = k < K ? va : vec_t{};
-                fb[buf][u] = k < K ? vb : vec_t{};
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < kNtU; ++u) {
-                const int k = k0 + u * STEP + kg;
-#pragma unroll
-                for (int c = 0; c < VEC; ++c) {
-                    fa[buf][u][c] = k + c < K ? pa[k + c] : T(0);
-                    fb[buf][u][c] = k + c < K ? pb[k + c] : T(0);
-                }
-            }
-        }
-    };
+    // rows outside the matrix feed only rows / columns of C that are not
+    // stored: their addresses are clamped to row 0
+    const T* pa0 = a.A + size_t(m0 + idx < M ? m0 + idx : 0) * K;
+    const T* pa1 = a.A + size_t(m0 + 16 + idx < M ? m0 + 16 + idx : 0) * K;
+    const T* pb0 = a.Bt + size_t(n0 + idx < N ? n0 + idx : 0) * K;
+    const T* pb1 = a.Bt + size_t(n0 + 16 + idx < N ? n0 + 16 + idx : 0) * K;
+    const int kq = ((K + 4 * STEP - 1) / (4 * STEP)) * STEP;  // this wave's share of K
+    const int kbeg = wave * kq, kend = min(K, kbeg + kq);
+    const int kg = VEC * g;
+    acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
+    vec_t fa0[2][kNtR], fa1[2][kNtR], fb0[2][kNtR], fb1[2][kNtR];
     auto compute_stage = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < kNtU; ++u)
+        for (int u = 0; u < kNtR; ++u)
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) acc = Cfg::mma(fa[buf][u][e], fb[buf][u][e], acc);
+            for (int e = 0; e < VEC; ++e) {
+                c00 = Cfg::mma(fa0[buf][u][e], fb0[buf][u][e], c00);
+                c01 = Cfg::mma(fa0[buf][u][e], fb1[buf][u][e], c01);
+                c10 = Cfg::mma(fa1[buf][u][e], fb0[buf][u][e], c10);
+                c11 = Cfg::mma(fa1[buf][u][e], fb1[buf][u][e], c11);
+            }
     };
-    const int nst = (K + SK - 1) / SK;
     if constexpr (kFast) {
         auto load_full = [&](int buf, int k0) {
 #pragma unroll
-            for (int u = 0; u < kNtU; ++u) {
+            for (int u = 0; u < kNtR; ++u) {
                 const int k = k0 + u * STEP + kg;
-                fa[buf][u] = *reinterpret_cast<const vec_t*>(pa + k);
-                fb[buf][u] = *reinterpret_cast<const vec_t*>(pb + k);
+                fa0[buf][u] = *reinterpret_cast<const vec_t*>(pa0 + k);
+                fa1[buf][u] = *reinterpret_cast<const vec_t*>(pa1 + k);
+                fb0[buf][u] = *reinterpret_cast<const vec_t*>(pb0 + k);
+                fb1[buf][u] = *reinterpret_cast<const vec_t*>(pb1 + k);
             }
         };
         // scheduling barriers keep each stage's loads ahead of the previous
         // stage's MFMAs (the scheduler would otherwise pull every load next
-        // to its use and leave almost nothing in flight)
-        const int last = K - SK;
-        load_full(0, 0);
-        for (int st = 0; st < nst; st += 2) {
-            load_full(1, (st + 1) * SK);
-            __builtin_amdgcn_sched_barrier(0);
-            compute_stage(0);
-            __builtin_amdgcn_sched_barrier(0);
-            load_full(0, min((st + 2) * SK, last));
-            __builtin_amdgcn_sched_barrier(0);
-            compute_stage(1);
-            __builtin_amdgcn_sched_barrier(0);
+        // to its use and leave almost nothing in flight); an odd last stage
+        // is computed after the loop from the buffer it was loaded into
+        const int nst = (kend - kbeg) / SK;
+        const int last = kend - SK;
+        if (nst > 0) {
+            load_full(0, kbeg);
+            int st = 0;
+            for (; st + 2 <= nst; st += 2) {
+                load_full(1, kbeg + (st + 1) * SK);
+                __builtin_amdgcn_sched_barrier(0);
+                compute_stage(0);
+                __builtin_amdgcn_sched_barrier(0);
+                load_full(0, min(kbeg + (st + 2) * SK, last));
+                __builtin_amdgcn_sched_barrier(0);
+                compute_stage(1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (st < nst) compute_stage(0);
         }
     } else {
-        load_stage(0, 0);
-        int st = 0;
-        for (; st + 2 <= nst; st += 2) {
-            load_stage(1, (st + 1) * SK);
-            compute_stage(0);
-            if (st + 2 < nst) load_stage(0, (st + 2) * SK);
-            compute_stage(1);
-        }
-        if (st < nst) compute_stage(0);
-    }
-    double part = 0.0;
-    const int jc = wc + idx;
+        const bool vec_ok = (K % VEC) == 0;  // uniform
+        auto load_masked = [&](int buf, int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = wr + Cfg::orow(lane, r);
+            for (int u = 0; u < kNtR; ++u) {
+                const int k = k0 + u * STEP + kg;
+                if (vec_ok) {
+                    const int kc = min(k, K - VEC);
+                    const bool in = k < kend;
+                    const vec_t x0 = *reinterpret_cast<const vec_t*>(pa0 + kc);
+                    const vec_t x1 = *reinterpret_cast<const vec_t*>(pa1 + kc);
+                    const vec_t y0 = *reinterpret_cast<const vec_t*>(pb0 + kc);
+                    const vec_t y1 = *reinterpret_cast<const vec_t*>(pb1 + kc);
+                    fa0[buf][u] = in ? x0 : vec_t{};
+                    fa1[buf][u] = in ? x1 : vec_t{};
+                    fb0[buf][u] = in ? y0 : vec_t{};
+                    fb1[buf][u] = in ? y1 : vec_t{};
+                } else {
+#pragma unroll
+                    for (int c = 0; c < VEC; ++c) {
+                        const bool in = k + c < kend;
+                        fa0[buf][u][c] = in ? pa0[k + c] : T(0);
+                        fa1[buf][u][c] = in ? pa1[k + c] : T(0);
+                        fb0[buf][u][c] = in ? pb0[k + c] : T(0);
+                        fb1[buf][u][c] = in ? pb1[k + c] : T(0);
+                    }
+                }
+            }
+        };
+        for (int k0 = kbeg; k0 < kend; k0 += SK) {
+            load_masked(0, k0);
+            compute_stage(0);
+        }
+    }
+    // sum the four waves' partial tiles: wave w finishes tile (w / 2, w % 2)
+    {
+        T* mine = red_tile + wave * 16 * 64;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            mine[(0 * 4 + q) * 64 + lane] = c00[q];
+            mine[(1 * 4 + q) * 64 + lane] = c01[q];
+            mine[(2 * 4 + q) * 64 + lane] = c10[q];
+            mine[(3 * 4 + q) * 64 + lane] = c11[q];
+        }
+    }
+    __syncthreads();
+    const int ti = wave >> 1, tj = wave & 1;
+    double part = 0.0;
+    const int jc = n0 + 16 * tj + idx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rv = (wave * 4 + q) * 64 + lane;
+        const T v0 = red_tile[rv] + red_tile[16 * 64 + rv];
+        const T v1 = red_tile[2 * 16 * 64 + rv] + red_tile[3 * 16 * 64 + rv];
+        T v = v0 + v1;
+        const int i = m0 + 16 * ti + Cfg::orow(lane, q);
         if (i < M && jc < N) {
             const size_t gidx = size_t(i) * N + jc;
-            T v = acc[r];
             if (a.epi >= 1 && a.E1) v *= a.E1[gidx];
             if (a.transC) a.C[size_t(jc) * M + i] = v;
             else a.C[gidx] = v;
@@ -1225,6 +1260,20 @@ template <typename T, bool kFast>
 __global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
     const int b = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     mgemm_body<T, kFast>(a, b % gridDim.x, b / gridDim.x, gridDim.x);
+}
+
+// Batched product: image blockIdx.z, its own tile grid inside the launch
+// grid; images whose PCG has stopped skip their blocks.  it: PCG iteration.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mgemm_b(const MGemmArgs<T>* __restrict__ as, int it) {
+    MGemmArgs<T> a = as[blockIdx.z];
+    const int gx = (a.N + 31) / 32, gy = (a.M + 31) / 32;
+    const int b = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int bx = b % gridDim.x, by = b / gridDim.x;
+    if (bx >= gx || by >= gy || (a.st && a.st->done)) return;
+    a.iter = it;
+    if (mgemm_fast_k<T>(a.K)) mgemm_body<T, true>(a, bx, by, gx);
+    else mgemm_body<T, false>(a, bx, by, gx);
 }
 
 // FP64 sums of products C = sum_t coef_t op(A_t) B_t on the matrix cores
@@ -1311,10 +1360,10 @@ __global__ void __launch_bounds__(256) k_mgemm_multi(const GemmProblem* __restri
 // loads are issued before the scalar reductions.
 constexpr int kUpdE = 4;
 template <typename T>
-__global__ void __launch_bounds__(256) k_upd(UpdArgs<T> a) {
+__device__ __forceinline__ void upd_body(const UpdArgs<T>& a, int bx) {
     __shared__ double red[17];
     const int tid = threadIdx.x;
-    const int base = blockIdx.x * 256 * kUpdE + tid;
+    const int base = bx * 256 * kUpdE + tid;
     const int done = a.st->done;
     const double pq = a.do_update ? partial_issue(a.pq_part, a.n_pq, tid, 256) : 0.0;
     const double rzp = a.do_update ? partial_issue(a.rz_part, a.n_rz, tid, 256) : 0.0;
@@ -1337,7 +1386,7 @@ __global__ void __launch_bounds__(256) k_upd(UpdArgs<T> a) {
         const double g = block_sum(pq, red);
         const double rz = block_sum(rzp, red);
         if (!(g > 0.0)) {  // curvature <= 0 (or NaN): stop, keep x_{i-1}
-            if (blockIdx.x == 0 && tid == 0) {
+            if (bx == 0 && tid == 0) {
                 a.st->done = 2;
                 a.st->iters = a.iter - 1;
             }
@@ -1361,19 +1410,36 @@ __global__ void __launch_bounds__(256) k_upd(UpdArgs<T> a) {
     }
     if (a.do_update) {
         const double sm = block_sum(part, red);
-        if (tid == 0) a.rr_out[blockIdx.x] = sm;
+        if (tid == 0) a.rr_out[bx] = sm;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_upd(UpdArgs<T> a) {
+    upd_body(a, blockIdx.x);
+}
+
+__host__ __device__ constexpr int upd_blocks(int n) {
+    return (n + 256 * kUpdE - 1) / (256 * kUpdE);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_upd_b(const UpdArgs<T>* __restrict__ as, int it) {
+    UpdArgs<T> a = as[blockIdx.z];
+    if (int(blockIdx.x) >= upd_blocks(a.n) || a.st->done) return;
+    a.iter = it;
+    upd_body(a, blockIdx.x);
 }
 
 // w = (I (x) K_x) z, one row per block; the z row and the band's rows
 // (interior Toeplitz row, then the stored edge rows) are staged in LDS.
 template <typename T>
-__global__ void __launch_bounds__(256) k_xpass(XPassArgs<T> a) {
+__device__ __forceinline__ void xpass_body(const XPassArgs<T>& a, int i) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* zs = reinterpret_cast<T*>(smem_raw);
     const int nx = a.nx;
     T* cs = zs + nx;
-    const int i = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     if (a.st && a.st->done) return;
     const T* zr = a.z + size_t(i) * nx;
     for (int t = tid; t < nx; t += 256) zs[t] = zr[t];
@@ -1387,6 +1453,18 @@ __global__ void __launch_bounds__(256) k_xpass(XPassArgs<T> a) {
         for (int d = 0; d < bw; ++d) sacc += coef[d] * zs[min(max(t + d - a.kw, 0), nx - 1)];
         a.w[size_t(i) * nx + t] = sacc;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_xpass(XPassArgs<T> a) {
+    xpass_body(a, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_xpass_b(const XPassArgs<T>* __restrict__ as) {
+    const XPassArgs<T> a = as[blockIdx.z];
+    if (int(blockIdx.x) >= a.ny) return;
+    xpass_body(a, blockIdx.x);
 }
 
 // Diagonal / identity preconditioner iteration tail (no transform):
@@ -1835,15 +1913,34 @@ template <typename T>
 hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
     dim3 grid((a.N + 31) / 32, (a.M + 31) / 32);
     if (nblocks) *nblocks = int(grid.x * grid.y);
-    constexpr int two_stages = 2 * kNtU * 4 * NtCfg<T>::VEC;
-    if (a.K % two_stages == 0) tvd_launch(k_mgemm<T, true>, grid, dim3(256), 0, s, a);
+    if (mgemm_fast_k<T>(a.K)) tvd_launch(k_mgemm<T, true>, grid, dim3(256), 0, s, a);
     else tvd_launch(k_mgemm<T, false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
+hipError_t launch_mgemm_b(const MGemmArgs<T>* a, int it, BatchGrid g, hipStream_t s) {
+    tvd_launch(k_mgemm_b<T>, dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a, it);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_upd_b(const UpdArgs<T>* a, int it, BatchGrid g, hipStream_t s) {
+    tvd_launch(k_upd_b<T>, dim3(g.gx, 1, g.count), dim3(256), 0, s, a, it);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xpass_b(const XPassArgs<T>* a, BatchGrid g, hipStream_t s) {
+    tvd_launch(k_xpass_b<T>, dim3(g.gx, 1, g.count), dim3(256), g.lds, s, a);
+    return hipGetLastError();
+}
+
+int upd_block_count(int n) { return std::max(1, upd_blocks(n)); }
+
+template <typename T>
 hipError_t launch_upd(const UpdArgs<T>& a, hipStream_t s, int* nblocks) {
-    const int nb = std::max(1, (a.n + 256 * kUpdE - 1) / (256 * kUpdE));
+    const int nb = upd_block_count(a.n);
     if (nblocks) *nblocks = nb;
     tvd_launch(k_upd<T>, dim3(nb), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -2043,6 +2140,9 @@ hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
     template bool mgemm_supported<T>();                                                                       \
     template hipError_t launch_mgemm<T>(const MGemmArgs<T>&, hipStream_t, int*);                              \
     template hipError_t launch_upd<T>(const UpdArgs<T>&, hipStream_t, int*);                                  \
+    template hipError_t launch_mgemm_b<T>(const MGemmArgs<T>*, int, BatchGrid, hipStream_t);                  \
+    template hipError_t launch_upd_b<T>(const UpdArgs<T>*, int, BatchGrid, hipStream_t);                      \
+    template hipError_t launch_xpass_b<T>(const XPassArgs<T>*, BatchGrid, hipStream_t);                       \
     template hipError_t launch_xpass<T>(const XPassArgs<T>&, hipStream_t);                                    \
     template hipError_t launch_kappa_b<T>(const KappaArgs<T>*, BatchGrid, hipStream_t);                       \
     template hipError_t launch_mu_b<T>(const MuArgs<T>*, BatchGrid, hipStream_t);                             \

@@ -82,7 +82,8 @@ class BatchParams(ctypes.Structure):
     _fields_ = [("alpha_host", ctypes.POINTER(ctypes.c_double)), ("beta_host", ctypes.POINTER(ctypes.c_double)),
                 ("beta", ctypes.c_double), ("max_outer", ctypes.c_int), ("fp_tol", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("max_inner", ctypes.c_int), ("precond", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("replay_host", ctypes.POINTER(ctypes.c_int))]
+                ("use_graph", ctypes.c_int), ("replay_host", ctypes.POINTER(ctypes.c_int)),
+                ("transform", ctypes.c_int)]
 
 
 TUNE_MAX = 4
@@ -92,6 +93,7 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int), ("line_threads", ctypes.c_int), ("tables_in_lds", ctypes.c_int),
                 ("from_cache", ctypes.c_int), ("n_candidates", ctypes.c_int),
                 ("cand_threads", ctypes.c_int * TUNE_MAX), ("cand_us", ctypes.c_double * TUNE_MAX),
+                ("gemm_us", ctypes.c_double), ("transform", ctypes.c_int),
                 ("graph_launches", ctypes.c_longlong), ("time_setup_s", ctypes.c_double),
                 ("time_inner_s", ctypes.c_double)]
 
@@ -344,9 +346,10 @@ class TVDeblurBatch:
             pass
 
     def solve(self, vs, alphas, beta=0.05, betas=None, max_outer=10, inner_tol=1e-6, max_inner=100,
-              precond="x_d", fp_tol=0.0, use_graph=True, outs=None, replay=None):
+              precond="x_d", fp_tol=0.0, use_graph=True, outs=None, replay=None, transform="auto"):
         """Returns (list of restored images, list of per-image stats dicts).
-        replay: None, or per image a list of max_outer PCG iteration counts."""
+        replay: None, or per image a list of max_outer PCG iteration counts.
+        transform: 'auto' (the implementation picked at create), 'fft' or 'gemm'."""
         import torch
         if len(vs) != self.count or len(alphas) != self.count:
             raise ValueError("one v and one alpha per image")
@@ -367,6 +370,7 @@ class TVDeblurBatch:
         p.beta, p.max_outer, p.fp_tol = float(beta), int(max_outer), float(fp_tol)
         p.inner_tol, p.max_inner, p.precond = float(inner_tol), int(max_inner), PRECOND[precond]
         p.use_graph = 1 if use_graph else 0
+        p.transform = TRANSFORM[transform]
         rkeep = None
         if replay is not None:
             flat = [int(c) for r in replay for c in (list(r) + [0] * max_outer)[:max_outer]]
@@ -384,5 +388,7 @@ class TVDeblurBatch:
         n = bi.n_candidates
         return {"count": bi.count, "line_threads": bi.line_threads, "tables_in_lds": bool(bi.tables_in_lds),
                 "from_cache": bool(bi.from_cache), "candidates": list(bi.cand_threads[:n]),
-                "candidate_us": list(bi.cand_us[:n]), "graph_launches": int(bi.graph_launches),
+                "candidate_us": list(bi.cand_us[:n]), "gemm_us": bi.gemm_us,
+                "transform": {1: "fft", 2: "gemm"}.get(bi.transform, "none"),
+                "graph_launches": int(bi.graph_launches),
                 "time_setup_s": bi.time_setup_s, "time_inner_s": bi.time_inner_s}

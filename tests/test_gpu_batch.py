@@ -57,13 +57,13 @@ def ragged_problems(bc, n_outer=3):
     return out
 
 
-def batch_solve(probs, prec, variant="x_d", replay=None, use_graph=True, fp_tol=0.0, batch=None):
+def batch_solve(probs, prec, variant="x_d", replay=None, use_graph=True, fp_tol=0.0, batch=None, transform="auto"):
     from paper_1011_5964_amd.lib import TVDeblurBatch
     b = batch or TVDeblurBatch([p.v.shape for p in probs], [p.psf for p in probs], probs[0].bc, prec)
     vs = [dev(p.v, prec) for p in probs]
     us, st = b.solve(vs, [p.alpha for p in probs], betas=[p.beta for p in probs], max_outer=probs[0].n_outer,
                      inner_tol=probs[0].inner_tol, max_inner=probs[0].max_inner, precond=variant,
-                     fp_tol=fp_tol, use_graph=use_graph, replay=replay)
+                     fp_tol=fp_tol, use_graph=use_graph, replay=replay, transform=transform)
     return [host(u) for u in us], st, b
 
 
@@ -76,10 +76,13 @@ def oracle_solves(probs, prec, variant="x_d", fp_tol=0.0):
     return res
 
 
-def check_batch(probs, prec, variant="x_d", use_graph=True):
-    print(f"batch of {len(probs)}: {[p.v.shape for p in probs]} {prec} {variant} graph={use_graph}", flush=True)
+def check_batch(probs, prec, variant="x_d", use_graph=True, transform="auto"):
+    print(f"batch of {len(probs)}: {[p.v.shape for p in probs]} {prec} {variant} graph={use_graph} {transform}",
+          flush=True)
     ref = oracle_solves(probs, prec, variant)
-    ug, sg, b = batch_solve(probs, prec, variant, use_graph=use_graph)
+    ug, sg, b = batch_solve(probs, prec, variant, use_graph=use_graph, transform=transform)
+    if transform != "auto":
+        assert b.info()["transform"] == transform
     errs = [rel2(u, uo) for u, (uo, _) in zip(ug, ref)]
     same = [s["inner_iters"] == so["inner_iters"] for s, (_, so) in zip(sg, ref)]
     for k, (e, s, (_, so)) in enumerate(zip(errs, sg, ref)):
@@ -92,7 +95,7 @@ def check_batch(probs, prec, variant="x_d", use_graph=True):
         assert max(errs) <= BAR[prec]
         return errs, sg, b
     ur, sr, _ = batch_solve(probs, prec, variant, replay=[so["inner_iters"] for _, so in ref], use_graph=use_graph,
-                            batch=b)
+                            batch=b, transform=transform)
     rerrs = [rel2(u, uo) for u, (uo, _) in zip(ur, ref)]
     print(f"  replay errs {[f'{e:.2e}' for e in rerrs]}", flush=True)
     for s, (_, so) in zip(sr, ref):
@@ -104,29 +107,33 @@ def check_batch(probs, prec, variant="x_d", use_graph=True):
     return errs, sg, b
 
 
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
 @pytest.mark.parametrize("bc", [AR, R])
-def test_ragged_batch_matches_oracle(bc, prec):
+def test_ragged_batch_matches_oracle(bc, prec, transform):
     """Six images of different shapes, PSF widths, alphas and betas in one
-    batch; each against the oracle's solve of that image."""
-    errs, st, b = check_batch(ragged_problems(bc), prec)
+    batch, with either transform implementation; each against the oracle's
+    solve of that image."""
+    errs, st, b = check_batch(ragged_problems(bc), prec, transform=transform)
     info = b.info()
     print(f"  tuning {info}", flush=True)
     assert info["line_threads"] in (256, 512, 1024)
     assert all(s["outer_steps"] == 3 and s["all_converged"] for s in st)
 
 
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
 @pytest.mark.parametrize("variant", ["x", "d_x"])
-def test_batch_other_transform_variants(variant):
-    check_batch(ragged_problems(AR), "f64", variant)
+def test_batch_other_transform_variants(variant, transform):
+    check_batch(ragged_problems(AR), "f64", variant, transform=transform)
 
 
-def test_graph_replay_equals_stream_launches():
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
+def test_graph_replay_equals_stream_launches(transform):
     """The graph-captured PCG loop and plain stream launches run the same
     kernels in the same order: bitwise-identical results and counts."""
     probs = ragged_problems(AR)
-    ug, sg, b = batch_solve(probs, "f32_mixed", use_graph=True)
-    us, ss, _ = batch_solve(probs, "f32_mixed", use_graph=False, batch=b)
+    ug, sg, b = batch_solve(probs, "f32_mixed", use_graph=True, transform=transform)
+    us, ss, _ = batch_solve(probs, "f32_mixed", use_graph=False, batch=b, transform=transform)
     assert b.info()["graph_launches"] > 0
     for a, c, s1, s2 in zip(ug, us, sg, ss):
         assert np.array_equal(a, c)
@@ -142,13 +149,14 @@ def test_repeated_solves_are_deterministic():
     assert [s["inner_iters"] for s in s1] == [s["inner_iters"] for s in s2]
 
 
-def test_fp_tol_stops_each_image_on_its_own():
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
+def test_fp_tol_stops_each_image_on_its_own(transform):
     """With a fixed-point tolerance each image stops after its own number of
     steps, as the oracle does for that image alone."""
     probs = ragged_problems(AR, n_outer=12)
     fp_tol = 3e-3
     ref = oracle_solves(probs, "f64", fp_tol=fp_tol)
-    ug, sg, _ = batch_solve(probs, "f64", fp_tol=fp_tol)
+    ug, sg, _ = batch_solve(probs, "f64", fp_tol=fp_tol, transform=transform)
     steps = [s["outer_steps"] for s in sg]
     print(f"steps gpu {steps} oracle {[len(so['inner_iters']) for _, so in ref]}", flush=True)
     assert len(set(steps)) > 1          # the images really stop at different steps
@@ -173,7 +181,7 @@ def test_batch_matches_single_image_path():
     and agrees with it to rounding."""
     from paper_1011_5964_amd.lib import TVDeblur
     probs = ragged_problems(AR)
-    ug, sg, _ = batch_solve(probs, "f64")
+    ug, sg, _ = batch_solve(probs, "f64", transform="fft")
     for p, u, s in zip(probs, ug, sg):
         h = TVDeblur(*p.v.shape, "f64")
         h.set_psf(p.psf)
@@ -222,6 +230,10 @@ def test_c4_full_batch_sampled_against_oracle():
     ug, sg, b = batch_solve(probs, "f32_mixed")
     print(f"tuning {b.info()}", flush=True)
     assert all(s["outer_steps"] == 10 and s["all_converged"] for s in sg)
+    # the other implementation on the same batch gives the same images to the bar
+    other = "fft" if b.info()["transform"] == "gemm" else "gemm"
+    uo_, so_, _ = batch_solve(probs, "f32_mixed", batch=b, transform=other)
+    assert all(s["outer_steps"] == 10 and s["all_converged"] for s in so_)
     picked = {}
     for k, p in enumerate(probs):
         if p.v.shape[0] in (128, 192, 256) and p.v.shape[0] not in picked:
@@ -231,6 +243,7 @@ def test_c4_full_batch_sampled_against_oracle():
         uo, so = O.fp_solve(host(dev(p.v, "f32_mixed")), p.psf, p.bc, p.alpha, p.beta, p.n_outer, p.inner_tol,
                             p.max_inner, "x_d")
         e = rel2(ug[k], uo)
-        print(f"image {k} ({n}^2, psf {p.psf.shape[0]}, alpha {p.alpha:.2e}): err {e:.3e} "
+        e2 = rel2(uo_[k], uo)
+        print(f"image {k} ({n}^2, psf {p.psf.shape[0]}, alpha {p.alpha:.2e}): err {e:.3e} ({other}: {e2:.3e}) "
               f"gpu {sg[k]['inner_iters']} oracle {so['inner_iters']}", flush=True)
-        assert e <= BAR["f32_mixed"]
+        assert e <= BAR["f32_mixed"] and e2 <= BAR["f32_mixed"]
