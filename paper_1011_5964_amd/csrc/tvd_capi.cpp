@@ -460,7 +460,11 @@ class Solver final : public SolverBase {
         for (int rep = 0; rep < 3; ++rep) {
             for (int mode = 0; mode < 2; ++mode) {
                 tmode_ = mode;
-                auto pass = [&]() { precond_pass(R_, Z_, rz_[0], xsplit_); };
+                // a preconditioner application and the y-pass of the next operator
+                auto pass = [&]() {
+                    precond_pass(R_, Z_, rz_[0], xsplit_);
+                    if (xsplit_) ypass_update(1);
+                };
                 pass();
                 TVD_HIP(hipEventRecord(ev_a_, s_));
                 for (int r = 0; r < 5; ++r) pass();
@@ -1855,12 +1859,12 @@ class BatchSolver final : public BatchBase {
                 if (!apply(threads, false)) continue;
                 tab = false;
             }
-            for (auto& S : img_) S->n_rz_ = S->gx_.blocks;
             fill_tables();
             auto pass = [&]() {
                 TVD_HIP(launch_rowpass_b<T>(rf0_, 0, tab_lds_, g_rf_, s_));
                 TVD_HIP(launch_colpass_b<T>(cn_, 0, tab_lds_, g_col_, s_));
                 TVD_HIP(launch_rowpass_b<T>(ri_[0], 0, tab_lds_, g_ri_, s_));
+                TVD_HIP(launch_ypass_b<T>(y1_, g_y_, s_));
             };
             pass();
             TVD_HIP(hipEventRecord(ev_a_, s_));
@@ -1892,6 +1896,7 @@ class BatchSolver final : public BatchBase {
             auto pass = [&]() {
                 TVD_HIP(launch_upd_b<T>(upd0_, 0, g_upd_, s_));
                 gemm_pass(gm1n_, gm4_[0], 0);
+                TVD_HIP(launch_ypass_b<T>(y1_, g_y_, s_));
             };
             pass();
             TVD_HIP(hipEventRecord(ev_a_, s_));

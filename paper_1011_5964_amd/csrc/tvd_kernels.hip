@@ -1122,14 +1122,17 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     __shared__ double red[17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int M = a.M, N = a.N, K = a.K;
-    if (a.st) {
+    // PCG state (done flag, stopping test): evaluated after the first operand
+    // loads are in flight, so its latency overlaps theirs
+    auto state_stops = [&]() -> bool {
+        if (!a.st) return false;
         const int done = a.st->done;
         const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, 256) : 0.0;
         const double r0 = a.st->r0norm, tol = a.st->tol;
         const int cap = a.st->cap;
-        if (done) return;
-        if (a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red)) return;
-    }
+        if (done) return true;
+        return a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red);
+    };
     const int m0 = by * 32, n0 = bx * 32;
     const int g = lane >> 4, idx = lane & 15;
     // rows outside the matrix feed only rows / columns of C that are not
@@ -1171,8 +1174,9 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         // is computed after the loop from the buffer it was loaded into
         const int nst = (kend - kbeg) / SK;
         const int last = kend - SK;
+        if (nst > 0) load_full(0, kbeg);
+        if (state_stops()) return;
         if (nst > 0) {
-            load_full(0, kbeg);
             int st = 0;
             for (; st + 2 <= nst; st += 2) {
                 load_full(1, kbeg + (st + 1) * SK);
@@ -1187,6 +1191,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
             if (st < nst) compute_stage(0);
         }
     } else {
+        if (state_stops()) return;
         const bool vec_ok = (K % VEC) == 0;  // uniform
         auto load_masked = [&](int buf, int k0) {
 #pragma unroll
@@ -1440,10 +1445,10 @@ __device__ __forceinline__ void xpass_body(const XPassArgs<T>& a, int i) {
     const int nx = a.nx;
     T* cs = zs + nx;
     const int tid = threadIdx.x;
-    if (a.st && a.st->done) return;
     const T* zr = a.z + size_t(i) * nx;
     for (int t = tid; t < nx; t += 256) zs[t] = zr[t];
     for (int t = tid; t < a.xband_len; t += 256) cs[t] = a.xband[t];
+    if (a.st && a.st->done) return;  // after the loads: their latencies overlap
     __syncthreads();
     const int bw = 2 * a.kw + 1;
     for (int t = tid; t < nx; t += 256) {

@@ -131,6 +131,19 @@ def test_c2_both_bcs(prec):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("name", ["c3_gauss", "c3_disk"])
+def test_c3_precision_form_full_size(name):
+    """The 1024^2 precision-form workloads (256 shapes + ramp, alpha 1e-4,
+    beta 0.01; 31x31 Gaussian s=5, and the non-separable out-of-focus disk
+    r=5 that runs the 2D band kernel), FP32-mixed, at full size: the first 2
+    of the 20 fixed-point steps (the oracle's time budget) against the FP64
+    oracle within 1e-5."""
+    print(f"case {name} f32_mixed full size, 2 steps", flush=True)
+    err, so, sg = check_parity(synth.config(name), "f32_mixed", n_outer=2)
+    print(f"{name} rel err {err:.3e} iters {sg['inner_iters']}", flush=True)
+
+
+@pytest.mark.slow
 def test_m512_fp32_mixed_full():
     """The benchmark workload: 512^2, 21x21 Gaussian s=3, AR, X_D, 15 steps,
     FP32-mixed, against the FP64 oracle."""
