@@ -33,14 +33,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor peak
+MFMA_PEAK_TFLOPS = {"f32_mixed": 157.3, "f64": 78.6}   # dense matrix-core peaks
 
-# Algorithmic HBM words per pixel of each PCG-loop kernel (what that stage
-# of the method must read + write; w bytes per word):
+# Algorithmic HBM words per pixel of each HBM-bound PCG-loop kernel (what that
+# stage of the method must read + write; w bytes per word):
 #   band_normal  p_old, z, kappa read; p_new, q written            -> 5
 #   row_forward  x, r, p, q, s read; x, r, T1 written              -> 8
 #   column       T1, 1/mu read; T2 written                         -> 3
 #   row_inverse  T2, s, r read; z written                          -> 4
-ALGO_WORDS = {"band_normal": 5, "row_forward": 8, "column": 3, "row_inverse": 4}
+#   update       x, r, p, q, s read; x, r, t written               -> 8
+#   x_pass       z read; w written                                 -> 2
+ALGO_WORDS = {"band_normal": 5, "row_forward": 8, "column": 3, "row_inverse": 4, "update": 8, "x_pass": 2}
+# Products on the matrix cores (product form of the transforms): 2 n^3 flop
+# per launch (an n x n x n product), against the dense MFMA peak.
+MFMA_CLASSES = ("transform_gemm",)
 # Per PCG iteration the method moves x, r, p (R/W), q, z (W/R), kappa, s,
 # 1/mu (R): 13 words per pixel, plus 4 for the two transform intermediates.
 ITER_WORDS = 13
@@ -98,6 +104,7 @@ def headline(args, p, prec):
     h = TVDeblur(n, n, prec)
     h.set_psf(p.psf)
     h.set_bc(p.bc)
+    h.set_transform(args.transform)
     stats = []
 
     def solve():
@@ -130,17 +137,31 @@ def headline(args, p, prec):
         "achieved": round(ITER_WORDS * N * w / per_iter_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(ITER_WORDS * N * w / per_iter_s / 1e9 / HBM_PEAK_GBS, 4),
         "frac_with_transposes": round(ITER_WORDS_WITH_TRANSPOSES * N * w / per_iter_s / 1e9 / HBM_PEAK_GBS, 4)}
-    cls = {k: x for k, x in kt.items() if k in ALGO_WORDS and x["launches"] > 0}
-    dom = max(cls, key=lambda k: cls[k]["total_ms"])
-    avg_s = cls[dom]["total_ms"] * 1e-3 / cls[dom]["launches"]
-    algo = ALGO_WORDS[dom] * N * w
+    loop = {k: x for k, x in kt.items() if (k in ALGO_WORDS or k in MFMA_CLASSES) and x["launches"] > 0}
+    dom = max(loop, key=lambda k: loop[k]["total_ms"])
+    avg_s = loop[dom]["total_ms"] * 1e-3 / loop[dom]["launches"]
     traffic = None
     if TRAFFIC["source_sha256"] == kernel_source_sha() and prec == "f32_mixed":
         traffic = TRAFFIC["bytes_per_launch"].get(dom)
-    res["roofline"] = {"bound": "hbm", "achieved": round(algo / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": round(algo / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
-                       "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 3), "launches": cls[dom]["launches"],
-                       "algorithmic_bytes_per_launch": algo}
+    if dom in MFMA_CLASSES:
+        flops = 2.0 * n ** 3
+        achieved = flops / avg_s / 1e12
+        peak = MFMA_PEAK_TFLOPS[prec]
+        res["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                           "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": dom,
+                           "avg_launch_us": round(avg_s * 1e6, 3), "launches": loop[dom]["launches"],
+                           "algorithmic_flops_per_launch": flops,
+                           # the same launches seen as streams: A and the basis read, C written
+                           "hbm_view": {"algorithmic_bytes_per_launch": 3 * N * w,
+                                        "achieved_gbs": round(3 * N * w / avg_s / 1e9, 1),
+                                        "frac": round(3 * N * w / avg_s / 1e9 / HBM_PEAK_GBS, 4)}}
+    else:
+        algo = ALGO_WORDS[dom] * N * w
+        res["roofline"] = {"bound": "hbm", "achieved": round(algo / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(algo / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
+                           "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 3), "launches": loop[dom]["launches"],
+                           "algorithmic_bytes_per_launch": algo}
+    res["transform"] = "gemm" if "transform_gemm" in loop else "fft"
     res["kernel_classes"] = {k: {"launches": x["launches"], "avg_us": round(1e3 * x["total_ms"] / x["launches"], 3),
                                  "share_of_step": round(x["total_ms"] / (1e3 * total), 4)}
                              for k, x in kt.items() if x["launches"] > 0}
@@ -251,6 +272,9 @@ def main():
                     help="comma list of forms measured beside the headline: f64, batch, diff; 'all' or 'none'")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="fixed-point steps of the oracle CPU sample (0 = skip the oracle)")
+    ap.add_argument("--transform", choices=("auto", "fft", "gemm"), default="auto",
+                    help="preconditioner transforms of the headline and plain FP64 solves: timed choice (default), "
+                         "line transforms, or products on the matrix cores")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy (y = -x, float32) of this many MiB three times: "
                          "the reference kernel that scales hardware traffic counters")
@@ -284,6 +308,7 @@ def main():
                       "precond": "x_d", "fixed_point_steps": p.n_outer,
                       "pcg_iters_per_solve": r32["pcg_iters_per_solve"]},
            "roofline": r32["roofline"], "iteration_roofline": r32["iteration_roofline"],
+           "transform": r32["transform"],
            "pcg_iters_per_s_inner_loop": round(r32["pcg_iters_per_s_inner_loop"], 1),
            "setup_share": round(r32["setup_share"], 4), "kernel_classes": r32["kernel_classes"]}
 
@@ -298,7 +323,7 @@ def main():
         r64, u64 = headline(args, p, "f64")
         r64_time = r64["restore_time_s"]
         forms["plain_f64"] = {k: r64[k] for k in ("restore_time_s", "pcg_iters_per_s", "pcg_iters_per_s_inner_loop",
-                                                  "pcg_iters_per_solve", "setup_share")}
+                                                  "pcg_iters_per_solve", "setup_share", "transform", "roofline")}
         forms["plain_f64"]["iteration_roofline"] = r64["iteration_roofline"]
         forms["f32_mixed"] = {"restore_time_s": r32["restore_time_s"],
                               "speedup_vs_plain_f64": r64_time / r32["restore_time_s"]}

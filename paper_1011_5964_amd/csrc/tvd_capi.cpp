@@ -332,6 +332,10 @@ class Solver final : public SolverBase {
                 xpass_ = true;
             }
         }
+        // The product form takes the whole normal operator in its y-pass
+        // when both band half-widths fit the tile halo.
+        yfull_ = xsplit_ && 2 * my_ <= 32 && kw_ <= 32 &&
+                 ypass_full_lds_bytes(2 * my_, kw_, sizeof(T)) + kStaticLds <= max_lds_;
         // basis matrices for the eigenvalue setup
         make_basis(ny_, Wy_, Puy_, Puly_, Ply_);
         if (ny_ == nx_) {
@@ -441,7 +445,8 @@ class Solver final : public SolverBase {
         }
         const std::string key = std::to_string(sizeof(T)) + ":" + std::to_string(bc_) + ":" + std::to_string(ny_) +
                                 "x" + std::to_string(nx_) + ":" + std::to_string(my_) + "x" + std::to_string(mx_) +
-                                ":" + std::to_string(int(xsplit_)) + std::to_string(int(xpass_));
+                                ":" + std::to_string(int(xsplit_)) + std::to_string(int(xpass_)) +
+                                std::to_string(int(yfull_));
         {
             std::lock_guard<std::mutex> lk(g_transform_mu);
             auto f = g_transform_cache.find(key);
@@ -486,7 +491,7 @@ class Solver final : public SolverBase {
     void precond_pass(const T* r, T* z, double* rz_out, bool xp) {
         if (tmode_ == 1) {
             upd_launch(0, false, r);
-            gemm_transform(0, false, 0, r, z, rz_out, xp);
+            gemm_transform(0, false, 0, r, z, rz_out, xp && !yfull_);
         } else {
             rowpass(0, false, const_cast<T*>(r), nullptr, 0);
             colpass(0, false, 0);
@@ -784,10 +789,14 @@ class Solver final : public SolverBase {
         const YPassArgs<T> a = ypass_args(it);
         int nb = 0;
         timer_.begin(KernelTimer::kBand, s_);
-        TVD_HIP(launch_ypass<T>(a, s_, &nb));
+        if (full_y()) TVD_HIP(launch_ypass_full<T>(a, s_, &nb));
+        else TVD_HIP(launch_ypass<T>(a, s_, &nb));
         timer_.end(s_);
         n_pq_ = nb;
     }
+    // y-pass computing the whole normal operator (product form only: the
+    // line-transform form gets the row half from its inverse row pass)
+    bool full_y() const { return tmode_ == 1 && yfull_; }
     YPassArgs<T> ypass_args(int it) const {
         YPassArgs<T> a{};
         a.ny = ny_;
@@ -808,6 +817,10 @@ class Solver final : public SolverBase {
         a.q = Q_;
         a.pq_part = pq_;
         a.st = st_;
+        a.xband = xband_;
+        a.kw = kw_;
+        a.klo = klo_;
+        a.khi = khi_;
         return a;
     }
 
@@ -1042,7 +1055,7 @@ class Solver final : public SolverBase {
         const bool gm = transform && tmode_ == 1;
         if (gm) {
             upd_launch(0, false, R_);
-            gemm_transform(0, true, nb_res_, R_, Z_, rz_[0], xp);
+            gemm_transform(0, true, nb_res_, R_, Z_, rz_[0], xp && !yfull_);
             n_rz_ = nb_g4_;
         } else if (transform) {
             rowpass(0, false, R_, nullptr, 0);
@@ -1067,7 +1080,7 @@ class Solver final : public SolverBase {
                 upd_launch(it, true, R_);
                 last_rr = rr_[0];
                 last_rr_n = nb_upd_;
-                if (it < maxit) gemm_transform(it, true, nb_upd_, R_, Z_, rz_[it & 1], xp);
+                if (it < maxit) gemm_transform(it, true, nb_upd_, R_, Z_, rz_[it & 1], xp && !yfull_);
             } else if (transform) {
                 rowpass(it, true, R_, rr_[0], 0);
                 last_rr = rr_[0];
@@ -1323,6 +1336,7 @@ class Solver final : public SolverBase {
     int ty_res_ = 0, ty_h_hp_ = 0, ty_ht_hp_ = 0, nb_res_ = 0;
     bool xsplit_ = false;  // normal operator as row half (K_x) + y-pass
     bool xpass_ = false;   // row half fused into the inverse row transform
+    bool yfull_ = false;   // product form: whole normal operator in k_ypass_full
     const T* xband_ = nullptr;
     int xband_len_ = 0, kw_ = 0, klo_ = 0, khi_ = 0;
     LineGeom gxi_{};
@@ -1407,7 +1421,11 @@ class BatchSolver final : public BatchBase {
             }
             key_ = key.str();
             gemm_ok_ = true;
-            for (auto& S : img_) gemm_ok_ = gemm_ok_ && S->gemm_ok_;
+            yfull_ = true;
+            for (auto& S : img_) {
+                gemm_ok_ = gemm_ok_ && S->gemm_ok_;
+                yfull_ = yfull_ && S->yfull_;
+            }
             st_ = static_cast<PcgState*>(arena_.alloc(B_ * sizeof(PcgState)));
             for (int i = 0; i < B_; ++i) img_[i]->st_ = st_ + i;
             alloc_tables();
@@ -1603,6 +1621,7 @@ class BatchSolver final : public BatchBase {
             g_y_.gx = std::max(g_y_.gx, (S->nx_ + 63) / 64);
             g_y_.gy = std::max(g_y_.gy, (S->ny_ + 15) / 16);
             g_y_.lds = std::max(g_y_.lds, ypass_lds_bytes(2 * S->my_, sizeof(T)));
+            g_yf_lds_ = std::max(g_yf_lds_, ypass_full_lds_bytes(2 * S->my_, S->kw_, sizeof(T)));
         }
         TVD_HIP(hipStreamSynchronize(s_));
     }
@@ -1738,7 +1757,7 @@ class BatchSolver final : public BatchBase {
     // One PCG iteration of every image (the tail of iteration maxit stops
     // after the x, r update, as in the single-image loop).
     void iteration(int it, bool tail) {
-        TVD_HIP(launch_ypass_b<T>(it == 1 ? y1_ : y_[it & 1], g_y_, s_));
+        ypass_b(it == 1 ? y1_ : y_[it & 1]);
         if (bmode_ == 1) {
             TVD_HIP(launch_upd_b<T>(upd_[it & 1], it, g_upd_, s_));
             if (tail) return;
@@ -1758,7 +1777,21 @@ class BatchSolver final : public BatchBase {
         TVD_HIP(launch_mgemm_b<T>(gm2_, it, g_mg_, s_));
         TVD_HIP(launch_mgemm_b<T>(gm3_, it, g_mg_, s_));
         TVD_HIP(launch_mgemm_b<T>(last, it, g_mg_, s_));
-        TVD_HIP(launch_xpass_b<T>(xp_, g_xp_, s_));
+        if (!yfull_) TVD_HIP(launch_xpass_b<T>(xp_, g_xp_, s_));
+    }
+
+    // The y-pass of every image: in the product form the whole normal
+    // operator (k_ypass_full) when every image's band half-widths fit its
+    // halo, else the column half after the row half of gemm_pass / the
+    // inverse row pass.
+    void ypass_b(const YPassArgs<T>* a) {
+        if (bmode_ == 1 && yfull_) {
+            BatchGrid g = g_y_;
+            g.lds = g_yf_lds_;
+            TVD_HIP(launch_ypass_full_b<T>(a, g, s_));
+        } else {
+            TVD_HIP(launch_ypass_b<T>(a, g_y_, s_));
+        }
     }
 
     static constexpr int kChunk = 2;  // iterations per captured graph
@@ -1864,7 +1897,7 @@ class BatchSolver final : public BatchBase {
                 TVD_HIP(launch_rowpass_b<T>(rf0_, 0, tab_lds_, g_rf_, s_));
                 TVD_HIP(launch_colpass_b<T>(cn_, 0, tab_lds_, g_col_, s_));
                 TVD_HIP(launch_rowpass_b<T>(ri_[0], 0, tab_lds_, g_ri_, s_));
-                TVD_HIP(launch_ypass_b<T>(y1_, g_y_, s_));
+                ypass_b(y1_);
             };
             pass();
             TVD_HIP(hipEventRecord(ev_a_, s_));
@@ -1896,7 +1929,7 @@ class BatchSolver final : public BatchBase {
             auto pass = [&]() {
                 TVD_HIP(launch_upd_b<T>(upd0_, 0, g_upd_, s_));
                 gemm_pass(gm1n_, gm4_[0], 0);
-                TVD_HIP(launch_ypass_b<T>(y1_, g_y_, s_));
+                ypass_b(y1_);
             };
             pass();
             TVD_HIP(hipEventRecord(ev_a_, s_));
@@ -1985,6 +2018,8 @@ class BatchSolver final : public BatchBase {
     XPassArgs<T>* xp_ = nullptr;
     BatchGrid g_mg_{}, g_upd_{}, g_xp_{};
     bool gemm_ok_ = false;
+    bool yfull_ = false;     // product form: k_ypass_full for every image
+    size_t g_yf_lds_ = 0;
     int bmode_ = 0, tuned_mode_ = 0;
     GemmProblem* g1_[2] = {};
     GemmProblem* g2_[2] = {};

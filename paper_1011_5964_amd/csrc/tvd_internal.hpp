@@ -143,6 +143,10 @@ struct YPassArgs {
     T* q;
     double* pq_part;
     const PcgState* st;
+    // whole-operator form (k_ypass_full): the row band, Toeplitz-compressed
+    // (interior row, then rows 0..klo-1, then rows khi..nx-1), half-width kw
+    const T* xband;
+    int kw, klo, khi;
 };
 
 // Dense product on the matrix cores, C = A Bt^T: A is M x K and Bt is N x K,
@@ -313,11 +317,14 @@ template <typename T>
 hipError_t launch_colpass_b(const ColPassArgs<T>* a, int it, bool tab_lds, BatchGrid g, hipStream_t s);
 template <typename T>
 hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s);
+template <typename T>
+hipError_t launch_ypass_full_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s);
 // Line geometry for a batched pass whose blocks all have `threads` threads
 // (tpu = 0 if a line does not fit).
 template <typename T>
 LineGeom line_geom_block(int lines, int n, int M, int threads);
 size_t ypass_lds_bytes(int w, size_t elem);
+size_t ypass_full_lds_bytes(int wy, int wx, size_t elem);
 
 // Arm a start/stop event pair for the next kernel launch of this thread;
 // disarm returns whether a launch consumed them.
@@ -336,6 +343,8 @@ template <typename T>
 hipError_t launch_rowpass(const RowPassArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_ypass(const YPassArgs<T>& a, hipStream_t s, int* nblocks);
+template <typename T>
+hipError_t launch_ypass_full(const YPassArgs<T>& a, hipStream_t s, int* nblocks);
 // Matrix-core product; *nblocks = number of blocks (= partials of epi 2).
 // Only for element types whose MFMA layout is supported (mgemm_supported).
 template <typename T>

@@ -1036,6 +1036,135 @@ __global__ void __launch_bounds__(kYThreads) k_ypass_b(const YPassArgs<T>* __res
     ypass_body(a, blockIdx.x, blockIdx.y, gx);
 }
 
+// The whole normal operator in one tile pass (no row half elsewhere):
+// p = z + beta p_old over the 64 x 16 tile and a halo of the band half-widths
+// on all sides (columns clamped to the image, as the row band expects; rows
+// outside the image are zero), then K_y down the columns of the tile rows,
+// K_x along them (Toeplitz interior row, stored edge rows), the TV stencil and
+// <p, q> partials.  Both half-widths <= kYFMaxH.
+constexpr int kYFMaxH = 32;
+template <typename T>
+__device__ __forceinline__ T band_dot(const T* __restrict__ coef, const T* v, int bw) {
+    T s0 = T(0), s1 = T(0);
+    int d = 0;
+    for (; d + 2 <= bw; d += 2) {
+        s0 += coef[d] * v[d];
+        s1 += coef[d + 1] * v[d + 1];
+    }
+    if (d < bw) s0 += coef[d] * v[d];
+    return s0 + s1;
+}
+constexpr int kYFRegs = ((kYTY + 2 * kYFMaxH) * (kYTX + 2 * kYFMaxH) + kYThreads - 1) / kYThreads;
+template <typename T>
+__device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, int by, int gx) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[17];
+    const int tid = threadIdx.x, tx = tid & (kYTX - 1), ty = tid / kYTX;
+    const int tyu = __builtin_amdgcn_readfirstlane(ty);
+    const int i0 = by * kYTY, j0 = bx * kYTX;
+    const int ny = a.ny, nx = a.nx, wy = a.w, wx = a.kw;
+    const int hy = max(wy, 1), hx = max(wx, 1);
+    const int TH = kYTY + 2 * hy, TW = kYTX + 2 * hx, nreg = TH * TW;
+    T* pr = reinterpret_cast<T*>(smem_raw);  // [TH][TW] p_new, tile + halo
+    T* ar = pr + nreg;                       // [kYTY][TW] K_y p_new
+    const bool use_old = a.rz_old != nullptr;
+
+    // ---- one batch of global loads ----
+    const int done = a.st ? a.st->done : 0;
+    const double rzn = use_old ? partial_issue(a.rz_new, a.n_rz, tid, kYThreads) : 0.0;
+    const double rzo = use_old ? partial_issue(a.rz_old, a.n_rz, tid, kYThreads) : 0.0;
+    T zv[kYFRegs], po[kYFRegs];
+#pragma unroll
+    for (int k = 0; k < kYFRegs; ++k) {
+        const int e = tid + k * kYThreads;
+        const int r = e / TW, c = e - r * TW;
+        const int gi = i0 - hy + r, gj = min(max(j0 - hx + c, 0), nx - 1);
+        const bool in = e < nreg && gi >= 0 && gi < ny;
+        const size_t g = in ? size_t(gi) * nx + gj : 0;
+        zv[k] = in ? a.z[g] : T(0);
+        po[k] = (in && use_old) ? a.p_old[g] : T(0);
+    }
+    const int gi = i0 + ty, gj = j0 + tx;
+    const bool own = gi < ny && gj < nx;
+    const size_t g = own ? size_t(gi) * nx + gj : 0;
+    const T kc = own ? a.kap[g] : T(0);
+    const T ku = (own && gi > 0) ? a.kap[g - nx] : T(0);
+    const T kl = (own && gj > 0) ? a.kap[g - 1] : T(0);
+    if (done) return;
+
+    T beta = T(0);
+    if (use_old) {
+        const double n_ = block_sum(rzn, red);
+        const double o_ = block_sum(rzo, red);
+        beta = T(n_ / o_);
+    }
+#pragma unroll
+    for (int k = 0; k < kYFRegs; ++k) {
+        const int e = tid + k * kYThreads;
+        if (e < nreg) pr[e] = zv[k] + beta * po[k];
+    }
+    __syncthreads();
+
+    // K_y: tile row ty (wave-uniform band row), every column of the region
+    {
+        const int row = min(i0 + tyu, ny - 1);
+        const T* kyr = a.Ky + size_t(row) * (2 * wy + 1);
+        for (int c = tx; c < TW; c += kYTX) {
+            const T* col = pr + (ty + hy - wy) * TW + c;
+            T s0 = T(0), s1 = T(0);
+            int d = 0;
+            for (; d + 2 <= 2 * wy + 1; d += 2) {
+                s0 += kyr[d] * col[d * TW];
+                s1 += kyr[d + 1] * col[(d + 1) * TW];
+            }
+            if (d < 2 * wy + 1) s0 += kyr[d] * col[d * TW];
+            ar[ty * TW + c] = s0 + s1;
+        }
+    }
+    __syncthreads();
+
+    double dot = 0.0;
+    if (own) {
+        const T* prow = pr + (ty + hy) * TW + tx + hx;
+        const T pc = prow[0];
+        a.p_new[g] = pc;
+        // K_x along the row: interior tiles use the Toeplitz row (uniform
+        // coefficients), tiles that touch a stored edge row pick per column
+        const int bw = 2 * wx + 1;
+        const T* arow = ar + ty * TW + tx + hx - wx;
+        T kxp;
+        if (j0 >= a.klo && j0 + kYTX <= a.khi) {
+            kxp = band_dot(a.xband, arow, bw);
+        } else {
+            const int rr = gj < a.klo ? 1 + gj : (gj >= a.khi ? 1 + a.klo + (gj - a.khi) : 0);
+            kxp = band_dot(a.xband + size_t(rr) * bw, arow, bw);
+        }
+        T lp = T(0);
+        if (gi > 0) lp += ku * (pc - prow[-TW]);
+        if (gi < ny - 1) lp += kc * (pc - prow[TW]);
+        if (gj > 0) lp += kl * (pc - prow[-1]);
+        if (gj < nx - 1) lp += kc * (pc - prow[1]);
+        const T qv = kxp + T(a.alpha) * lp;
+        a.q[g] = qv;
+        dot = double(pc) * double(qv);
+    }
+    const double sm = block_sum(dot, red);
+    if (tid == 0) a.pq_part[by * gx + bx] = sm;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kYThreads) k_ypass_full(YPassArgs<T> a) {
+    ypass_full_body(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kYThreads) k_ypass_full_b(const YPassArgs<T>* __restrict__ as) {
+    const YPassArgs<T> a = as[blockIdx.z];
+    const int gx = (a.nx + kYTX - 1) / kYTX, gy = (a.ny + kYTY - 1) / kYTY;
+    if (int(blockIdx.x) >= gx || int(blockIdx.y) >= gy || a.st->done) return;
+    ypass_full_body(a, blockIdx.x, blockIdx.y, gx);
+}
+
 // ------------------------------------------------------------------------
 // Dense products on the matrix cores (MFMA 16x16x4, one 16 x 16 tile of C
 // per wave).  MfmaCfg holds the instruction and its lane layout per type.
@@ -1910,6 +2039,19 @@ hipError_t launch_ypass(const YPassArgs<T>& a, hipStream_t s, int* nblocks) {
 }
 
 template <typename T>
+hipError_t launch_ypass_full(const YPassArgs<T>& a, hipStream_t s, int* nblocks) {
+    if (a.w > kYFMaxH || a.kw > kYFMaxH || a.w < 0 || a.kw < 0) return hipErrorInvalidValue;
+    const size_t lds = ypass_full_lds_bytes(a.w, a.kw, sizeof(T));
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ypass_full<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    dim3 grid((a.nx + kYTX - 1) / kYTX, (a.ny + kYTY - 1) / kYTY);
+    if (nblocks) *nblocks = grid.x * grid.y;
+    tvd_launch(k_ypass_full<T>, grid, dim3(kYThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
 bool mgemm_supported() {
     return true;
 }
@@ -2077,6 +2219,10 @@ LineGeom line_geom_block(int lines, int n, int M, int threads) {
 size_t ypass_lds_bytes(int w, size_t elem) {
     return (size_t(kYTY + 2 * w) * kYTX + size_t(kYTY + 2) * (kYTX + 2)) * elem;
 }
+size_t ypass_full_lds_bytes(int wy, int wx, size_t elem) {
+    const size_t tw = kYTX + 2 * std::max(wx, 1);
+    return (size_t(kYTY + 2 * std::max(wy, 1)) * tw + size_t(kYTY) * tw) * elem;
+}
 
 static void allow_lds(const void* k, size_t lds) {
     if (lds > 64 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -2141,6 +2287,13 @@ hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_ypass_full_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
+    allow_lds(reinterpret_cast<const void*>(&k_ypass_full_b<T>), g.lds);
+    tvd_launch(k_ypass_full_b<T>, dim3(g.gx, g.gy, g.count), dim3(kYThreads), g.lds, s, a);
+    return hipGetLastError();
+}
+
 #define TVD_INSTANTIATE(T)                                                                                    \
     template bool mgemm_supported<T>();                                                                       \
     template hipError_t launch_mgemm<T>(const MGemmArgs<T>&, hipStream_t, int*);                              \
@@ -2158,6 +2311,7 @@ hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
     template hipError_t launch_rowpass_b<T>(const RowPassArgs<T>*, int, bool, BatchGrid, hipStream_t);        \
     template hipError_t launch_colpass_b<T>(const ColPassArgs<T>*, int, bool, BatchGrid, hipStream_t);        \
     template hipError_t launch_ypass_b<T>(const YPassArgs<T>*, BatchGrid, hipStream_t);                       \
+    template hipError_t launch_ypass_full_b<T>(const YPassArgs<T>*, BatchGrid, hipStream_t);                  \
     template LineGeom line_geom_block<T>(int, int, int, int);                                                 \
     template hipError_t launch_adj_accum<T>(int, int, const T*, const T*, const T*, const double*, double*,   \
                                             double*, double*, int*, hipStream_t);                             \
@@ -2170,6 +2324,7 @@ hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
     template size_t lds_table_bytes<T>(int);                                                                  \
     template hipError_t launch_rowpass<T>(const RowPassArgs<T>&, hipStream_t);                                \
     template hipError_t launch_ypass<T>(const YPassArgs<T>&, hipStream_t, int*);                              \
+    template hipError_t launch_ypass_full<T>(const YPassArgs<T>&, hipStream_t, int*);                         \
     template hipError_t launch_colpass<T>(const ColPassArgs<T>&, hipStream_t);                                \
     template hipError_t launch_diag_update<T>(int, T*, T*, const T*, const T*, const T*, T*, const double*,   \
                                               int, const double*, int, double*, double*, PcgState*, int, int, \

@@ -127,3 +127,36 @@ def test_restoration_product_form_512(prec):
     """The 512^2 anti-reflective workload (15 steps) with the product form."""
     print(f"case m512 gemm {prec}", flush=True)
     restore_parity(synth.config("m512"), "gemm", prec=prec)
+
+
+def separable_psf(py, px, sy, sx):
+    """py x px quadrantally symmetric Gaussian with its own width per axis."""
+    gy = np.exp(-np.arange(-(py // 2), py // 2 + 1) ** 2 / (2.0 * sy * sy))
+    gx = np.exp(-np.arange(-(px // 2), px // 2 + 1) ** 2 / (2.0 * sx * sx))
+    h = np.outer(gy, gx)
+    return h / h.sum()
+
+
+# Product-form restorations at sizes whose y-pass tiles include interior
+# tiles, edge tiles and ragged tails, with band half-widths from 2 to the
+# tile halo's limit of 32 (PSF 1x1: the stencil's unit halo only; 21x21: 20;
+# 9x17 / 33x5: unequal halos per axis).
+FULL_Y_CASES = {
+    "gauss21_60x200": ((60, 200), lambda: synth.gaussian_psf(21, 3.0)),
+    "rect9x17_97x180": ((97, 180), lambda: separable_psf(9, 17, 1.5, 2.5)),
+    "rect33x5_140x77": ((140, 77), lambda: separable_psf(33, 5, 4.0, 1.0)),
+    "delta_70x130": ((70, 130), lambda: np.ones((1, 1))),
+}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("case", sorted(FULL_Y_CASES))
+def test_restoration_product_form_whole_operator_ypass(case, bc, prec):
+    print(f"case full-y {case} {bc} {prec}", flush=True)
+    shape, mk = FULL_Y_CASES[case]
+    psf = mk()
+    side = max(shape) + psf.shape[0] + psf.shape[1]
+    p = synth.make_problem(case, side, 10, psf, bc, 2e-3, 0.1, 3, 0.01, 5)
+    p.v = np.ascontiguousarray(p.v[:shape[0], :shape[1]])
+    restore_parity(p, "gemm", "x_d", prec)
