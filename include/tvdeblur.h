@@ -236,6 +236,19 @@ int tvdeblur_set_profiling(tvdeblur_t h, int every);
 /* Copy the accumulated per-class counts and times into *out (host). */
 int tvdeblur_get_kernel_times(tvdeblur_t h, tvd_kernel_times* out);
 
+/* Average execution time of one PCG-loop kernel class, measured by a pair of
+ * marker events around `reps` back-to-back repetitions on the handle's stream
+ * (no events on the dispatches themselves), with the handle's current
+ * buffers and parameters; *avg_us (host) receives the time per kernel launch.
+ * kind is a class index of tvd_kernel_times: 0 band operator (the y-pass of
+ * the active transform form), 2 column transform, 8 transform products (the
+ * four products of one preconditioner application, averaged per product),
+ * 9 row half of the normal operator.  Needs a completed tvdeblur_solve on the
+ * handle (its parameters and preconditioner); overwrites the handle's work
+ * buffers, so call it between solves.  TVD_EINVAL for another kind, a kind
+ * the active form does not run, reps < 1, or no solve yet. */
+int tvdeblur_time_kernel(tvdeblur_t h, int kind, int reps, double* avg_us);
+
 /* ---- batching form: many independent images, one launch per PCG stage ----
  *
  * Each image is its own instance of the problem of eq. (fp) -- its own size,

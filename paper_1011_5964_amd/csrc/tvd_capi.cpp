@@ -13,6 +13,7 @@
 #include <sstream>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 #include <string>
@@ -92,6 +93,8 @@ class SolverBase {
     virtual void set_transform(int mode) = 0;
     virtual int transform() const = 0;
     virtual void get_times(tvd_kernel_times* out) = 0;
+    // average duration of one PCG-loop kernel class in a back-to-back burst
+    virtual double time_kernel(int kind, int reps) = 0;
 };
 
 // Per-class kernel timing with pairs of HIP events around launches.
@@ -212,6 +215,7 @@ class Solver final : public SolverBase {
     // ---------------------------------------------------------------- build
     void build(const std::vector<double>& psf, int py, int px, int bc) override {
         geo_.release();
+        solved_ = false;
         bc_ = bc;
         const PsfFactors f = factor_psf(psf.data(), py, px);
         my_ = f.my;
@@ -965,6 +969,7 @@ class Solver final : public SolverBase {
         st.time_setup_s = ms_setup * 1e-3;
         st.time_inner_s = ms_inner * 1e-3;
         st.time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        solved_ = st.outer_steps > 0;
         if (st.breakdown) throw ApiError{TVD_EBREAKDOWN, "PCG breakdown: p^T A p <= 0"};
     }
 
@@ -1243,6 +1248,53 @@ class Solver final : public SolverBase {
     void set_profiling(int every) override { timer_.enable(every); }
     void get_times(tvd_kernel_times* out) override { timer_.fill(out); }
 
+    // reps back-to-back launches of one kernel class between two marker
+    // events; the control block is reset (done = 0) so no launch exits early,
+    // and the state checks are off (the products skip the stopping test)
+    double time_kernel(int kind, int reps) override {
+        if (!solved_) throw ApiError{TVD_EINVAL, "time_kernel needs a completed solve on the handle"};
+        const bool transform = variant_ >= TVD_PREC_X;
+        const bool gm = transform && tmode_ == 1;
+        int per = 1;
+        std::function<void()> launch;
+        if (kind == KernelTimer::kBand && transform && xsplit_) {
+            const YPassArgs<T> a = ypass_args(2);
+            const bool full = full_y();
+            launch = [this, a, full]() {
+                int nb = 0;
+                if (full) TVD_HIP(launch_ypass_full<T>(a, s_, &nb));
+                else TVD_HIP(launch_ypass<T>(a, s_, &nb));
+            };
+        } else if (kind == KernelTimer::kGemm && gm) {
+            MGemmArgs<T> g[4];
+            gemm_args(1, false, 0, R_, Z_, rz_[1], g);
+            per = 4;
+            launch = [this, g]() {
+                for (int k = 0; k < 4; ++k) {
+                    int nb = 0;
+                    TVD_HIP(launch_mgemm<T>(g[k], s_, &nb));
+                }
+            };
+        } else if (kind == KernelTimer::kCol && transform && !gm) {
+            const ColPassArgs<T> a = col_args(1, false, 0, nullptr);
+            launch = [this, a]() { TVD_HIP(launch_colpass<T>(a, s_)); };
+        } else if (kind == KernelTimer::kXPass && transform && xsplit_ && (gm ? !yfull_ : !xpass_)) {
+            const XPassArgs<T> x = xpass_args(Z_);
+            launch = [this, x]() { TVD_HIP(launch_xpass<T>(x, s_)); };
+        } else {
+            throw ApiError{TVD_EINVAL, "kernel class not run by the active transform form"};
+        }
+        TVD_HIP(launch_init_state(st_, 0.0, s_));
+        launch();  // warm
+        TVD_HIP(hipEventRecord(ev_a_, s_));
+        for (int r = 0; r < reps; ++r) launch();
+        TVD_HIP(hipEventRecord(ev_b_, s_));
+        TVD_HIP(hipEventSynchronize(ev_b_));
+        float ms = 0.f;
+        TVD_HIP(hipEventElapsedTime(&ms, ev_a_, ev_b_));
+        return 1e3 * double(ms) / (double(reps) * per);
+    }
+
    private:
     KernelTimer timer_;
     static void append(std::vector<double>& dst, const std::vector<double>& src) {
@@ -1337,6 +1389,7 @@ class Solver final : public SolverBase {
     bool xsplit_ = false;  // normal operator as row half (K_x) + y-pass
     bool xpass_ = false;   // row half fused into the inverse row transform
     bool yfull_ = false;   // product form: whole normal operator in k_ypass_full
+    bool solved_ = false;  // a solve completed (time_kernel has parameters to use)
     const T* xband_ = nullptr;
     int xband_len_ = 0, kw_ = 0, klo_ = 0, khi_ = 0;
     LineGeom gxi_{};
@@ -2412,6 +2465,15 @@ int tvdeblur_get_transform(tvdeblur_t h, int* active) {
         int rc = ensure_built(h);
         if (rc) return rc;
         *active = h->solver->transform();
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_time_kernel(tvdeblur_t h, int kind, int reps, double* avg_us) {
+    if (!h || !avg_us) return fail(h, TVD_EINVAL, "NULL argument");
+    if (reps < 1) return fail(h, TVD_EINVAL, "reps must be >= 1");
+    return guarded(h, [&]() {
+        *avg_us = h->solver->time_kernel(kind, reps);
         return TVD_OK;
     });
 }

@@ -73,6 +73,37 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Global-address-space view of a device pointer.  Pointers that reach a
+// kernel through memory (the batched argument tables) are generic, and loads
+// through them would be flat loads, which count in both wait counters.
+template <typename T>
+using gmem_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ const gmem_t<T>* gmem(const T* p) {
+    return (const gmem_t<T>*)p;
+}
+template <typename T>
+__device__ __forceinline__ gmem_t<T>* gmem(T* p) {
+    return (gmem_t<T>*)p;
+}
+// 16 bytes of zeros and of ones, read in place of absent epilogue operands
+// (an address select instead of a branch or a select on a loaded value).
+// Plain device globals, so the selected addresses stay in the global address
+// space; no kernel writes them.
+__device__ __align__(16) double g_nt_zeros[2] = {0.0, 0.0};
+__device__ __align__(16) double g_nt_ones_d[2] = {1.0, 1.0};
+__device__ __align__(16) float g_nt_ones_f[4] = {1.f, 1.f, 1.f, 1.f};
+template <typename T>
+__device__ __forceinline__ const T* nt_ones();
+template <>
+__device__ __forceinline__ const float* nt_ones<float>() {
+    return g_nt_ones_f;
+}
+template <>
+__device__ __forceinline__ const double* nt_ones<double>() {
+    return g_nt_ones_d;
+}
+
 // Sum of v over the block; every thread gets the result.  red: >= 17 doubles.
 __device__ __forceinline__ double block_sum(double v, double* red) {
     v = wave_sum(v);
@@ -1266,15 +1297,35 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     const int g = lane >> 4, idx = lane & 15;
     // rows outside the matrix feed only rows / columns of C that are not
     // stored: their addresses are clamped to row 0
-    const T* pa0 = a.A + size_t(m0 + idx < M ? m0 + idx : 0) * K;
-    const T* pa1 = a.A + size_t(m0 + 16 + idx < M ? m0 + 16 + idx : 0) * K;
-    const T* pb0 = a.Bt + size_t(n0 + idx < N ? n0 + idx : 0) * K;
-    const T* pb1 = a.Bt + size_t(n0 + 16 + idx < N ? n0 + 16 + idx : 0) * K;
+    const gmem_t<T>* pa0 = gmem(a.A) + size_t(m0 + idx < M ? m0 + idx : 0) * K;
+    const gmem_t<T>* pa1 = gmem(a.A) + size_t(m0 + 16 + idx < M ? m0 + 16 + idx : 0) * K;
+    const gmem_t<T>* pb0 = gmem(a.Bt) + size_t(n0 + idx < N ? n0 + idx : 0) * K;
+    const gmem_t<T>* pb1 = gmem(a.Bt) + size_t(n0 + 16 + idx < N ? n0 + 16 + idx : 0) * K;
+    using gvec_t = const gmem_t<vec_t>;
     const int kq = ((K + 4 * STEP - 1) / (4 * STEP)) * STEP;  // this wave's share of K
     const int kbeg = wave * kq, kend = min(K, kbeg + kq);
     const int kg = VEC * g;
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
     vec_t fa0[2][kNtR], fa1[2][kNtR], fb0[2][kNtR], fb1[2][kNtR];
+    // epilogue operands of this lane's four outputs, loaded with the first
+    // operands rather than after the product (absent or outside C: ones for
+    // E1, zeros for E2)
+    const int ti = wave >> 1, tj = wave & 1;
+    const int jc = n0 + 16 * tj + idx;
+    T e1v[4], e2v[4];
+    {
+        const bool has1 = a.epi >= 1 && a.E1, has2 = a.epi == 2;
+        const gmem_t<T>* ones = gmem(nt_ones<T>());
+        const gmem_t<T>* zeros = gmem(reinterpret_cast<const T*>(g_nt_zeros));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = m0 + 16 * ti + Cfg::orow(lane, q);
+            const bool in = i < M && jc < N;
+            const size_t gidx = in ? size_t(i) * N + jc : 0;
+            e1v[q] = *((in && has1) ? gmem(a.E1) + gidx : ones);
+            e2v[q] = *((in && has2) ? gmem(a.E2) + gidx : zeros);
+        }
+    }
     auto compute_stage = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < kNtR; ++u)
@@ -1291,10 +1342,10 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
 #pragma unroll
             for (int u = 0; u < kNtR; ++u) {
                 const int k = k0 + u * STEP + kg;
-                fa0[buf][u] = *reinterpret_cast<const vec_t*>(pa0 + k);
-                fa1[buf][u] = *reinterpret_cast<const vec_t*>(pa1 + k);
-                fb0[buf][u] = *reinterpret_cast<const vec_t*>(pb0 + k);
-                fb1[buf][u] = *reinterpret_cast<const vec_t*>(pb1 + k);
+                fa0[buf][u] = *reinterpret_cast<gvec_t*>(pa0 + k);
+                fa1[buf][u] = *reinterpret_cast<gvec_t*>(pa1 + k);
+                fb0[buf][u] = *reinterpret_cast<gvec_t*>(pb0 + k);
+                fb1[buf][u] = *reinterpret_cast<gvec_t*>(pb1 + k);
             }
         };
         // scheduling barriers keep each stage's loads ahead of the previous
@@ -1329,10 +1380,10 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
                 if (vec_ok) {
                     const int kc = min(k, K - VEC);
                     const bool in = k < kend;
-                    const vec_t x0 = *reinterpret_cast<const vec_t*>(pa0 + kc);
-                    const vec_t x1 = *reinterpret_cast<const vec_t*>(pa1 + kc);
-                    const vec_t y0 = *reinterpret_cast<const vec_t*>(pb0 + kc);
-                    const vec_t y1 = *reinterpret_cast<const vec_t*>(pb1 + kc);
+                    const vec_t x0 = *reinterpret_cast<gvec_t*>(pa0 + kc);
+                    const vec_t x1 = *reinterpret_cast<gvec_t*>(pa1 + kc);
+                    const vec_t y0 = *reinterpret_cast<gvec_t*>(pb0 + kc);
+                    const vec_t y1 = *reinterpret_cast<gvec_t*>(pb1 + kc);
                     fa0[buf][u] = in ? x0 : vec_t{};
                     fa1[buf][u] = in ? x1 : vec_t{};
                     fb0[buf][u] = in ? y0 : vec_t{};
@@ -1366,27 +1417,24 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         }
     }
     __syncthreads();
-    const int ti = wave >> 1, tj = wave & 1;
     double part = 0.0;
-    const int jc = n0 + 16 * tj + idx;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int rv = (wave * 4 + q) * 64 + lane;
         const T v0 = red_tile[rv] + red_tile[16 * 64 + rv];
         const T v1 = red_tile[2 * 16 * 64 + rv] + red_tile[3 * 16 * 64 + rv];
-        T v = v0 + v1;
+        const T v = (v0 + v1) * e1v[q];  // e1v = 1 without a scale: exact
         const int i = m0 + 16 * ti + Cfg::orow(lane, q);
         if (i < M && jc < N) {
             const size_t gidx = size_t(i) * N + jc;
-            if (a.epi >= 1 && a.E1) v *= a.E1[gidx];
-            if (a.transC) a.C[size_t(jc) * M + i] = v;
-            else a.C[gidx] = v;
-            if (a.epi == 2) part += double(a.E2[gidx]) * double(v);
+            if (a.transC) gmem(a.C)[size_t(jc) * M + i] = v;
+            else gmem(a.C)[gidx] = v;
+            if (a.epi == 2) part += double(e2v[q]) * double(v);
         }
     }
     if (a.epi == 2) {
         const double sm = block_sum(part, red);
-        if (tid == 0) a.part[by * gx + bx] = sm;
+        if (tid == 0) gmem(a.part)[by * gx + bx] = sm;
     }
 }
 

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_op_normal", "tvdeblur_op_precond", "tvdeblur_op_export", "tvdeblur_set_profiling",
     "tvdeblur_get_kernel_times", "tvdeblur_solve_adjoint", "tvdeblur_batch_create", "tvdeblur_batch_solve",
     "tvdeblur_batch_get_info", "tvdeblur_batch_destroy", "tvdeblur_batch_last_error",
-    "tvdeblur_set_transform", "tvdeblur_get_transform",
+    "tvdeblur_set_transform", "tvdeblur_get_transform", "tvdeblur_time_kernel",
 )
 BATCH_PRECOND = ("x", "d_x", "x_d")
 
@@ -124,6 +124,7 @@ def load():
         "tvdeblur_op_export": [vp, i, vp],
         "tvdeblur_set_profiling": [vp, i],
         "tvdeblur_get_kernel_times": [vp, ctypes.POINTER(KernelTimes)],
+        "tvdeblur_time_kernel": [vp, i, i, ctypes.POINTER(ctypes.c_double)],
         "tvdeblur_solve_adjoint": [vp, vp, i, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d),
                                    ctypes.POINTER(Params), ctypes.POINTER(Stats)],
         "tvdeblur_batch_create": [ctypes.POINTER(vp), i, ctypes.POINTER(ImageDesc), i, i, vp],
@@ -265,6 +266,20 @@ class TVDeblur:
         self._check(self.lib.tvdeblur_get_kernel_times(self.h, ctypes.byref(kt)))
         return {kt.name[k].value.decode(): {"launches": int(kt.launches[k]), "total_ms": float(kt.total_ms[k])}
                 for k in range(kt.n_kinds)}
+
+    def time_kernel(self, kind, reps=50):
+        """Average duration in microseconds of one launch of a PCG-loop kernel
+        class ('band_normal', 'column', 'transform_gemm' or 'x_pass'), from a
+        back-to-back burst of reps launches with the parameters of the last
+        solve (see tvdeblur_time_kernel)."""
+        kinds = {"band_normal": 0, "column": 2, "transform_gemm": 8, "x_pass": 9}
+        if kind not in kinds:
+            raise ValueError(f"kind must be one of {sorted(kinds)}")
+        import torch
+        out = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            self._check(self.lib.tvdeblur_time_kernel(self.h, kinds[kind], int(reps), ctypes.byref(out)))
+        return out.value
 
     # single operators
     def _op(self, fn, x, name):

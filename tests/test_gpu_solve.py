@@ -264,3 +264,31 @@ def test_kernel_timing_sampling(transform):
     for cls in ("band_normal", "residual", "setup") + loop:
         assert k1[cls]["launches"] > 0 and k1[cls]["total_ms"] > 0, cls
         assert k4[cls]["launches"] == -(-k1[cls]["launches"] // 4), cls
+
+
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
+def test_time_kernel_burst(transform):
+    """tvdeblur_time_kernel: positive per-launch times for the classes the
+    active form runs, an error for the others and before any solve, and the
+    handle still solves correctly afterwards."""
+    from paper_1011_5964_amd.lib import TVDeblur, TvdError
+    print(f"case time_kernel {transform}", flush=True)
+    p = synth.small_problem(n=96, psf_size=9, sigma=1.5, n_outer=2)
+    h = TVDeblur(*p.v.shape, "f32_mixed")
+    h.set_psf(p.psf)
+    h.set_bc(p.bc)
+    h.set_transform(transform)
+    with pytest.raises(TvdError):
+        h.time_kernel("band_normal", 5)
+    v = torch.tensor(p.v, dtype=torch.float32, device="cuda")
+    u1, _ = h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+    runs = ("band_normal", "transform_gemm") if transform == "gemm" else ("band_normal", "column")
+    for k in runs:
+        t = h.time_kernel(k, 10)
+        print(f"  {k}: {t:.2f} us", flush=True)
+        assert 0.5 < t < 5000.0
+    other = "column" if transform == "gemm" else "transform_gemm"
+    with pytest.raises(TvdError):
+        h.time_kernel(other, 5)
+    u2, _ = h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+    assert torch.equal(u1, u2)
