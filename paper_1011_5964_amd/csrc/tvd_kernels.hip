@@ -858,6 +858,23 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * q + min(x, r) + j;
 }
 
+// Block -> 32 x 32 tile (bx, by) of a gx x gy product grid.  When the grid
+// splits into 4 x 2 equal sub-grids, the blocks of one XCD (b % 8) take one
+// sub-grid: its L2 then fetches gy/2 row slabs of A and gx/4 of Bt instead of
+// two row slabs and the whole of Bt (contiguous ranges of tiles).  Otherwise
+// contiguous ranges.  A bijection on the tiles.
+__device__ __forceinline__ void tile_of_block(int b, int gx, int gy, int& bx, int& by) {
+    if ((gx & 3) == 0 && (gy & 1) == 0) {
+        const int x = b & 7, j = b >> 3, sw = gx >> 2;
+        bx = (x & 3) * sw + j % sw;
+        by = (x >> 2) * (gy >> 1) + j / sw;
+    } else {
+        const int w = xcd_remap(b, gx * gy);
+        bx = w % gx;
+        by = w / gx;
+    }
+}
+
 // Column pass: convergence test, forward column transform, divide by mu,
 // inverse column transform.
 template <typename T, bool kTabLds>
@@ -1440,8 +1457,9 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
 
 template <typename T, bool kFast>
 __global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
-    const int b = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    mgemm_body<T, kFast>(a, b % gridDim.x, b / gridDim.x, gridDim.x);
+    int bx, by;
+    tile_of_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, bx, by);
+    mgemm_body<T, kFast>(a, bx, by, gridDim.x);
 }
 
 // Batched product: image blockIdx.z, its own tile grid inside the launch
