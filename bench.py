@@ -9,9 +9,11 @@ sigma 3, 1% noise, alpha 5e-4, beta 0.05, X_D preconditioner, 15 fixed-point
 steps, PCG tol 1e-6, at most 100 iterations) in FP32-mixed precision.
 `value` = PCG iterations per second of whole solves over the K timed steps;
 the restore time per solve (median) and the inner-loop-only rate sit beside
-it.  During the K timed solves one launch in PROFILE_EVERY of each PCG-loop
-kernel carries a start/stop event pair on its own dispatch (no marker
-packets); the dominant kernel's roofline comes from those durations.
+it.  The roofline of the dominant kernel class takes its duration from a
+burst of back-to-back launches between HIP events right after the timed
+solves (tvdeblur_time_kernel); a per-class breakdown comes from one more,
+untimed solve in which one launch in PROFILE_EVERY of each class carries a
+start/stop event pair on its own dispatch.
 
 Forms (default --forms all): the plain FP64 path on the same workload, the
 batching form on the 64-image ragged workload against 64 single-image solves,
@@ -62,8 +64,8 @@ ITER_WORDS_WITH_TRANSPOSES = 17
 TRAFFIC = {"source_sha256": "7b569d8400eeeda3",
            "bytes_per_launch": {"transform_gemm": 11094733, "band_normal": 8981205, "update": 8325874}}
 
-# Kernel durations are sampled on 1 launch in PROFILE_EVERY of each class
-# during the timed solves (a timed launch delays the next by ~9 us).
+# The per-class breakdown samples 1 launch in PROFILE_EVERY of each class
+# (a timed launch delays the next by ~9 us), in a solve outside the timing.
 PROFILE_EVERY = 32
 
 WORKLOAD = ("512x512 piecewise-constant phantom (64 rectangles/disks, seed 512), 21x21 Gaussian PSF "
@@ -118,10 +120,17 @@ def headline(args, p, prec):
         solve()
     torch.cuda.synchronize()
     stats.clear()
-    h.set_profiling(PROFILE_EVERY)
     times, u = time_calls(solve, args.steps, 0)
+    timed_stats = list(stats)
+    # per-class breakdown from one more, untimed solve with sampled kernel
+    # timing (which launches the iterations one by one instead of replaying
+    # them from HIP graphs)
+    h.set_profiling(PROFILE_EVERY)
+    solve()
+    torch.cuda.synchronize()
     kt = h.kernel_times()
     h.set_profiling(False)
+    stats[:] = timed_stats
     iters = sum(s["total_inner_iters"] for s in stats)
     inner = sum(s["time_inner_s"] for s in stats)
     total = sum(times)
