@@ -17,9 +17,10 @@ start/stop event pair on its own dispatch.
 
 Forms (default --forms all): the plain FP64 path on the same workload, the
 batching form on the 64-image ragged workload against 64 single-image solves,
-and the differentiation form (forward + adjoint against forward), each with
-its speedup over the plain GPU FP64 path and its error against the FP64
-oracle.  The oracle itself is timed on this host's cores on a bounded sample
+the differentiation form (forward + adjoint against forward), each with its
+speedup over the plain GPU FP64 path and its error against the FP64 oracle,
+and the alpha sweep of the headline image under both boundary conditions
+(one batched solve per BC: restoration error per alpha, the best alpha).  The oracle itself is timed on this host's cores on a bounded sample
 (cpu_baseline).
 """
 
@@ -249,6 +250,60 @@ def batch_form(args, p_ref_f64_restore_s):
     return res, probs, last
 
 
+SWEEP_ALPHAS = [5e-4 * 2.0 ** k for k in range(-5, 5)]   # 1.6e-5 .. 8e-3, the headline alpha included
+
+
+def sweep_form(args):
+    """Alpha sweep (one batched solve over SWEEP_ALPHAS for the headline image)
+    under both boundary conditions: the restoration error against the true
+    scene per alpha, the best alpha and its error, and the time against the
+    same restorations as one-by-one single-image solves (FP32-mixed)."""
+    import numpy as np
+    import torch
+    from paper_1011_5964_amd import synth
+    from paper_1011_5964_amd.lib import AlphaSweep, TVDeblur
+    p = synth.config("m512")
+    v = torch.tensor(p.v, dtype=torch.float32, device="cuda")
+    res = {"workload": "the headline 512x512 image, alpha = 5e-4 * 2^k for k = -5..4 (10 values), beta 0.05, "
+                       "15 fixed-point steps, X_D, FP32-mixed, one batched solve per boundary condition",
+           "alphas": SWEEP_ALPHAS}
+    slot = {}
+    for bc in ("antireflective", "reflective"):
+        sw = AlphaSweep(p.v.shape, p.psf, bc, SWEEP_ALPHAS, "f32_mixed")
+        last = {}
+
+        def run():
+            us, st = sw.solve(v, beta=p.beta, max_outer=p.n_outer, inner_tol=p.inner_tol, max_inner=p.max_inner)
+            last["u"], last["st"] = us, st
+            return us
+
+        times, _ = time_calls(run, max(2, args.steps // 2), 1)
+        t_sweep = statistics.median(times)
+        rre = [rel2(u.double().cpu().numpy(), p.u_true) for u in last["u"]]
+        k = int(np.argmin(rre))
+        h = TVDeblur(*p.v.shape, "f32_mixed")
+        h.set_psf(p.psf)
+        h.set_bc(bc)
+        h.solve(v, SWEEP_ALPHAS[0], p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for a in SWEEP_ALPHAS:
+            h.solve(v, a, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - s0
+        h.close()
+        res[bc] = {"sweep_s": t_sweep, "restorations_per_s": len(SWEEP_ALPHAS) / t_sweep,
+                   "sequential_single_s": t_seq, "speedup_vs_single_solves": t_seq / t_sweep,
+                   "transform": sw.info()["transform"],
+                   "pcg_iters": [int(st["total_inner_iters"]) for st in last["st"]],
+                   "restoration_error": [round(x, 6) for x in rre],
+                   "alpha_opt": SWEEP_ALPHAS[k], "restoration_error_at_alpha_opt": round(rre[k], 6)}
+        if bc == "antireflective":
+            slot["u"] = last["u"][SWEEP_ALPHAS.index(5e-4)].double().cpu().numpy()
+        sw.close()
+    return res, slot
+
+
 def diff_form(args, f64_restore_s):
     """Forward (with checkpoints) and forward + adjoint on the 512^2
     differentiation workload, FP32-mixed."""
@@ -293,7 +348,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="all",
-                    help="comma list of forms measured beside the headline: f64, batch, diff; 'all' or 'none'")
+                    help="comma list of forms measured beside the headline: f64, batch, diff, sweep; 'all' or 'none'")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="fixed-point steps of the oracle CPU sample (0 = skip the oracle)")
     ap.add_argument("--transform", choices=("auto", "fft", "gemm"), default="auto",
@@ -336,7 +391,7 @@ def main():
            "pcg_iters_per_s_inner_loop": round(r32["pcg_iters_per_s_inner_loop"], 1),
            "setup_share": round(r32["setup_share"], 4), "kernel_classes": r32["kernel_classes"]}
 
-    sel = {"all": {"f64", "batch", "diff"}, "none": set()}.get(args.forms, set(args.forms.split(",")))
+    sel = {"all": {"f64", "batch", "diff", "sweep"}, "none": set()}.get(args.forms, set(args.forms.split(",")))
     forms = {}
     u64 = None
     probs = None
@@ -358,6 +413,10 @@ def main():
     if "diff" in sel:
         print("[bench] differentiation form", file=sys.stderr, flush=True)
         forms["differentiation"] = diff_form(args, r64_time)
+    sweep_slot = None
+    if "sweep" in sel:
+        print("[bench] alpha sweep (both boundary conditions)", file=sys.stderr, flush=True)
+        forms["alpha_sweep"], sweep_slot = sweep_form(args)
 
     if args.cpu_steps > 0:
         import scipy.fft
@@ -393,6 +452,9 @@ def main():
             if u64 is not None:
                 forms["plain_f64"]["rel_err_vs_oracle"] = rel2(u64, uo)
             forms.setdefault("f32_mixed", {})["rel_err_vs_oracle"] = out["rel_err_vs_oracle"]
+            if sweep_slot is not None:
+                # the sweep's alpha = 5e-4 slot is the headline problem
+                forms["alpha_sweep"]["rel_err_vs_oracle_alpha_5e-4"] = rel2(sweep_slot["u"], uo)
         if probs is not None:
             # per-image error of the batch: one image of each of the three smallest sizes
             errs = {}

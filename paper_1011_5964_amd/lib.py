@@ -407,3 +407,34 @@ class TVDeblurBatch:
                 "transform": {1: "fft", 2: "gemm"}.get(bi.transform, "none"),
                 "graph_launches": int(bi.graph_launches),
                 "time_setup_s": bi.time_setup_s, "time_inner_s": bi.time_inner_s}
+
+
+class AlphaSweep:
+    """Restorations of one image for many regularisation parameters alpha in
+    one batched solve: the batching form with one slot per alpha, all slots
+    reading the same observed image (the batch never writes v).  This is the
+    alpha study behind the paper's restoration-error comparison of the
+    boundary conditions (Section 5: the best alpha and the error it reaches
+    under each BC); each restoration is the single-image solve of eq. (fp)
+    with that alpha."""
+
+    def __init__(self, shape, psf, bc, alphas, precision="f32_mixed", stream=None):
+        alphas = [float(a) for a in alphas]
+        if not alphas or not all(a > 0.0 and np.isfinite(a) for a in alphas):
+            raise ValueError("alphas must be a non-empty list of positive finite values")
+        self.alphas = alphas
+        self.shape = (int(shape[0]), int(shape[1]))
+        self.batch = TVDeblurBatch([self.shape] * len(alphas), [psf] * len(alphas), bc, precision, stream)
+
+    def solve(self, v, beta=0.05, max_outer=10, inner_tol=1e-6, max_inner=100, precond="x_d", fp_tol=0.0,
+              use_graph=True, outs=None, replay=None, transform="auto"):
+        """Returns (restorations, per-alpha stats), in the order of alphas."""
+        return self.batch.solve([v] * len(self.alphas), self.alphas, beta=beta, max_outer=max_outer,
+                                inner_tol=inner_tol, max_inner=max_inner, precond=precond, fp_tol=fp_tol,
+                                use_graph=use_graph, outs=outs, replay=replay, transform=transform)
+
+    def info(self):
+        return self.batch.info()
+
+    def close(self):
+        self.batch.close()

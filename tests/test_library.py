@@ -92,3 +92,10 @@ def test_batch_create_argument_errors_without_gpu():
     d[0].psf_host = hb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     assert lib.tvdeblur_batch_create(ctypes.byref(out), 1, d, 1, 2, None) == -2          # not symmetric
     assert b"image 0" in lib.tvdeblur_batch_last_error(None)
+
+
+def test_alpha_sweep_rejects_bad_alphas_without_gpu():
+    """The alpha list is checked before any device call."""
+    for bad in ([], [1e-3, 0.0], [1e-3, -1e-3], [float("nan")], [float("inf")]):
+        with pytest.raises(ValueError):
+            L.AlphaSweep((16, 16), [[1.0]], "antireflective", bad)
