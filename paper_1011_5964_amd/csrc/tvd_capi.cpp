@@ -204,8 +204,17 @@ class Solver final : public SolverBase {
         TVD_HIP(hipEventCreate(&ev_a_));
         TVD_HIP(hipEventCreate(&ev_b_));
         TVD_HIP(hipEventCreate(&ev_c_));
+        TVD_HIP(hipEventCreateWithFlags(&ev_poll_, hipEventDisableTiming));
+        for (int k = 0; k < 2; ++k) {
+            TVD_HIP(hipEventCreate(&ev_step_[k][0]));
+            TVD_HIP(hipEventCreate(&ev_step_[k][1]));
+            TVD_HIP(hipEventCreate(&ev_step_[k][2]));
+        }
     }
     ~Solver() override {
+        (void)hipEventDestroy(ev_poll_);
+        for (auto& e : ev_step_)
+            for (hipEvent_t x : e) (void)hipEventDestroy(x);
         if (host_st_) (void)hipHostFree(host_st_);
         (void)hipEventDestroy(ev_a_);
         (void)hipEventDestroy(ev_b_);
@@ -927,22 +936,40 @@ class Solver final : public SolverBase {
         TVD_HIP(hipMemcpyAsync(U_, p.u0_dev ? p.u0_dev : vv, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
         float ms_setup = 0, ms_inner = 0;
         int prev_iters = 8;
+        // Without an FP-change tolerance every step runs, so the next step's
+        // setup (which reads u^{k+1} and writes only the diffusivity and
+        // preconditioner arrays) is enqueued before the host waits for this
+        // step's state: the GPU does not idle at the step boundary.
+        const bool pipelined = !(p.fp_tol > 0.0) && !timer_.on();  // (timing: each step closed before the next)
+        auto enqueue_setup = [&](int k) {
+            hipEvent_t* e = ev_step_[k & 1];
+            TVD_HIP(hipEventRecord(e[0], s_));
+            setup(U_, p.alpha, p.beta, p.precond);
+            TVD_HIP(hipEventRecord(e[1], s_));
+        };
+        bool setup_done = false;
         for (int k = 0; k < p.max_outer; ++k) {
             if (iters_out)
                 TVD_HIP(hipMemcpyAsync(iters_out + size_t(k) * N_, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
-            TVD_HIP(hipEventRecord(ev_a_, s_));
-            setup(U_, p.alpha, p.beta, p.precond);
-            TVD_HIP(hipEventRecord(ev_b_, s_));
+            if (!setup_done) enqueue_setup(k);
+            setup_done = false;
+            hipEvent_t* e = ev_step_[k & 1];
             const int maxit = p.replay_host ? p.replay_host[k] : p.max_inner;
             const double tol = p.replay_host ? 0.0 : p.inner_tol;
             pcg(maxit, tol, prev_iters);
-            TVD_HIP(hipEventRecord(ev_c_, s_));
+            TVD_HIP(hipEventRecord(e[2], s_));
             TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
-            TVD_HIP(hipStreamSynchronize(s_));
+            TVD_HIP(hipEventRecord(ev_poll_, s_));
+            std::swap(U_, X_);
+            if (pipelined && k + 1 < p.max_outer) {
+                enqueue_setup(k + 1);
+                setup_done = true;
+            }
+            TVD_HIP(hipEventSynchronize(ev_poll_));
             timer_.harvest();
             float a = 0, b = 0;
-            TVD_HIP(hipEventElapsedTime(&a, ev_a_, ev_b_));
-            TVD_HIP(hipEventElapsedTime(&b, ev_b_, ev_c_));
+            TVD_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+            TVD_HIP(hipEventElapsedTime(&b, e[1], e[2]));
             ms_setup += a;
             ms_inner += b;
             const PcgState hs = *host_st_;
@@ -952,7 +979,6 @@ class Solver final : public SolverBase {
             st.total_inner_iters += hs.iters;
             st.outer_steps = k + 1;
             prev_iters = std::max(1, hs.iters);
-            std::swap(U_, X_);
             if (hs.done != 1 && hs.iters >= maxit && !p.replay_host) st.all_converged = 0;
             if (hs.done == 2) {
                 st.breakdown = 1;
@@ -1076,9 +1102,18 @@ class Solver final : public SolverBase {
             last_rr = rr_[1];
             last_rr_n = nb;
         }
-        // polling schedule: first look near the predicted count, then often
+        // polling schedule: first look near the predicted count, then often.
+        // With a transform preconditioner the host enqueues one more
+        // iteration before it waits for the polled state, so the GPU does not
+        // idle while the host reads it; if the PCG had already stopped, that
+        // iteration's kernels find the done flag and exit.
         int next_poll = std::max(2, predicted - 1);
+        bool ahead = false;  // iteration it was enqueued during the last poll
         for (int it = 1; it <= maxit; ++it) {
+            if (ahead) {
+                ahead = false;
+                continue;
+            }
             if (xp) ypass_update(it);
             else normal_apply_update(it);
             if (gm) {
@@ -1106,7 +1141,14 @@ class Solver final : public SolverBase {
             }
             if (it == next_poll && it < maxit) {
                 TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
-                TVD_HIP(hipStreamSynchronize(s_));
+                if (transform && !timer_.on()) {
+                    TVD_HIP(hipEventRecord(ev_poll_, s_));
+                    enqueue_iteration(it + 1, maxit, xp, gm);
+                    ahead = true;
+                    TVD_HIP(hipEventSynchronize(ev_poll_));
+                } else {
+                    TVD_HIP(hipStreamSynchronize(s_));
+                }
                 timer_.harvest();
                 if (host_st_->done) break;
                 next_poll = it + 2;
@@ -1115,6 +1157,24 @@ class Solver final : public SolverBase {
         int nfp = 0;
         TVD_HIP(launch_fpchange<T>(int(N_), X_, U_, fp_, &nfp, s_));
         TVD_HIP(launch_finalize<T>(st_, last_rr, last_rr_n, fp_, nfp, maxit, s_));
+    }
+
+    // The launches of transform-preconditioned PCG iteration it (as in pcg's
+    // loop; the partials they leave for the last test are rr_[0] either way).
+    void enqueue_iteration(int it, int maxit, bool xp, bool gm) {
+        if (xp) ypass_update(it);
+        else normal_apply_update(it);
+        if (gm) {
+            upd_launch(it, true, R_);
+            if (it < maxit) gemm_transform(it, true, nb_upd_, R_, Z_, rz_[it & 1], xp && !yfull_);
+        } else {
+            rowpass(it, true, R_, rr_[0], 0);
+            if (it < maxit) {
+                colpass(it, true, gx_.blocks, rr_[0]);
+                rowpass_inv(Z_, R_, rz_[it & 1], xp && xpass_);
+                if (xp && !xpass_) xpass_launch(Z_);
+            }
+        }
     }
 
     void rowpass(int it, bool update, T* r, double* part_out, int /*unused*/) {
@@ -1390,6 +1450,8 @@ class Solver final : public SolverBase {
     bool xpass_ = false;   // row half fused into the inverse row transform
     bool yfull_ = false;   // product form: whole normal operator in k_ypass_full
     bool solved_ = false;  // a solve completed (time_kernel has parameters to use)
+    hipEvent_t ev_poll_ = nullptr;       // after a polled state copy
+    hipEvent_t ev_step_[2][3] = {};      // per fixed-point step parity: setup start, setup end, PCG end
     const T* xband_ = nullptr;
     int xband_len_ = 0, kw_ = 0, klo_ = 0, khi_ = 0;
     LineGeom gxi_{};
