@@ -122,6 +122,35 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return red[16];
 }
 
+// Two block sums in one pass (each summed in block_sum's order, so each
+// equals block_sum of its value).  red: >= 34 doubles.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (lane == 0) {
+        red[w] = a;
+        red[16 + w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        double s = (threadIdx.x < nw) ? red[threadIdx.x] : 0.0;
+        double t = (threadIdx.x < nw) ? red[16 + threadIdx.x] : 0.0;
+        s = wave_sum(s);
+        t = wave_sum(t);
+        if (threadIdx.x == 0) {
+            red[32] = s;
+            red[33] = t;
+        }
+    }
+    __syncthreads();
+    a = red[32];
+    b = red[33];
+}
+
 // Deterministic sum of n per-block partials, computed redundantly per block.
 __device__ __forceinline__ double sum_partials(const double* p, int n, double* red) {
     double s = 0.0;
@@ -1103,12 +1132,13 @@ __device__ __forceinline__ T band_dot(const T* __restrict__ coef, const T* v, in
     return s0 + s1;
 }
 constexpr int kYFRegs = ((kYTY + 2 * kYFMaxH) * (kYTX + 2 * kYFMaxH) + kYThreads - 1) / kYThreads;
-template <typename T>
+// kRowPairs: the beta sums in one reduction and K_y two tile rows per
+// thread (the single-image kernel; measured slower in the batched one).
+template <typename T, bool kRowPairs>
 __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, int by, int gx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[17];
+    __shared__ double red[34];
     const int tid = threadIdx.x, tx = tid & (kYTX - 1), ty = tid / kYTX;
-    const int tyu = __builtin_amdgcn_readfirstlane(ty);
     const int i0 = by * kYTY, j0 = bx * kYTX;
     const int ny = a.ny, nx = a.nx, wy = a.w, wx = a.kw;
     const int hy = max(wy, 1), hx = max(wx, 1);
@@ -1142,8 +1172,13 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
 
     T beta = T(0);
     if (use_old) {
-        const double n_ = block_sum(rzn, red);
-        const double o_ = block_sum(rzo, red);
+        double n_ = rzn, o_ = rzo;
+        if constexpr (kRowPairs) {
+            block_sum2(n_, o_, red);
+        } else {
+            n_ = block_sum(n_, red);
+            o_ = block_sum(o_, red);
+        }
         beta = T(n_ / o_);
     }
 #pragma unroll
@@ -1153,9 +1188,9 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
     }
     __syncthreads();
 
-    // K_y: tile row ty (wave-uniform band row), every column of the region
-    {
-        const int row = min(i0 + tyu, ny - 1);
+    if constexpr (!kRowPairs) {
+        // K_y: tile row ty (wave-uniform band row), every column of the region
+        const int row = min(i0 + int(__builtin_amdgcn_readfirstlane(ty)), ny - 1);
         const T* kyr = a.Ky + size_t(row) * (2 * wy + 1);
         for (int c = tx; c < TW; c += kYTX) {
             const T* col = pr + (ty + hy - wy) * TW + c;
@@ -1167,6 +1202,40 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
             }
             if (d < 2 * wy + 1) s0 += kyr[d] * col[d * TW];
             ar[ty * TW + c] = s0 + s1;
+        }
+    } else {
+        // K_y: each wave takes a pair of tile rows (wave-uniform band rows) and
+        // half of the region's columns; a thread sums both rows of its column
+        // from one pass down it (the even and odd taps of each row in separate
+        // accumulators, as for a single row)
+        const int wv = __builtin_amdgcn_readfirstlane(ty);
+        const int r0 = 2 * (wv & 7), c = (wv >> 3) * kYTX + tx;
+        const gmem_t<T>* ky0 = gmem(a.Ky) + size_t(min(i0 + r0, ny - 1)) * (2 * wy + 1);
+        const gmem_t<T>* ky1 = gmem(a.Ky) + size_t(min(i0 + r0 + 1, ny - 1)) * (2 * wy + 1);
+        if (c < TW) {
+            const T* col = pr + (r0 + hy - wy) * TW + c;
+            T e0 = T(0), o0 = T(0), e1 = T(0), o1 = T(0);
+            e0 += ky0[0] * col[0];
+            int d = 1;
+            for (; d + 2 <= 2 * wy + 1; d += 2) {
+                const T v1 = col[d * TW], v2 = col[(d + 1) * TW];
+                o0 += ky0[d] * v1;
+                e1 += ky1[d - 1] * v1;
+                e0 += ky0[d + 1] * v2;
+                o1 += ky1[d] * v2;
+            }
+            if (d < 2 * wy + 1) {
+                const T v1 = col[d * TW];
+                o0 += ky0[d] * v1;
+                e1 += ky1[d - 1] * v1;
+                ++d;
+            }
+            // row r0 + 1's last tap (its d' = 2 wy, at d = 2 wy + 1)
+            const T vl = col[(2 * wy + 1) * TW];
+            if ((2 * wy) & 1) o1 += ky1[2 * wy] * vl;
+            else e1 += ky1[2 * wy] * vl;
+            ar[r0 * TW + c] = e0 + o0;
+            ar[(r0 + 1) * TW + c] = e1 + o1;
         }
     }
     __syncthreads();
@@ -1202,7 +1271,7 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
 
 template <typename T>
 __global__ void __launch_bounds__(kYThreads) k_ypass_full(YPassArgs<T> a) {
-    ypass_full_body(a, blockIdx.x, blockIdx.y, gridDim.x);
+    ypass_full_body<T, true>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename T>
@@ -1210,7 +1279,7 @@ __global__ void __launch_bounds__(kYThreads) k_ypass_full_b(const YPassArgs<T>* 
     const YPassArgs<T> a = as[blockIdx.z];
     const int gx = (a.nx + kYTX - 1) / kYTX, gy = (a.ny + kYTY - 1) / kYTY;
     if (int(blockIdx.x) >= gx || int(blockIdx.y) >= gy || a.st->done) return;
-    ypass_full_body(a, blockIdx.x, blockIdx.y, gx);
+    ypass_full_body<T, false>(a, blockIdx.x, blockIdx.y, gx);
 }
 
 // ------------------------------------------------------------------------
