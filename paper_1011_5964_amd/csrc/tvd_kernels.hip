@@ -1303,7 +1303,7 @@ struct MfmaCfg<float> {
 template <>
 struct MfmaCfg<double> {
     // K slice and LDS strides of the multi-term setup products (k_mgemm_multi)
-    static constexpr int BK = 16, SA = 17, SB = 32;
+    static constexpr int BK = 32, SA = 33, SB = 32;
     typedef double acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -1566,7 +1566,24 @@ __global__ void __launch_bounds__(256) k_mgemm_multi(const GemmProblem* __restri
     const int bk = tid / (TN / BE), bc = (tid % (TN / BE)) * BE;
     const int nkt = (K + BK - 1) / BK, total = pb.nterms * nkt;
     double ra[AE], rb[BE];
-    auto gload = [&](int step) {
+    // whole tiles and whole K slices (uniform): the loads need no masks
+    const bool whole = m0 + TM <= M && n0 + TN <= N && K % BK == 0;
+    auto gload_whole = [&](int step) {
+        const int term = step / nkt, k0 = (step - term * nkt) * BK;
+        const double* A = pb.t[term].A;
+        const double* B = pb.t[term].B;
+        const double cf = pb.t[term].coef;
+        if (trans) {
+#pragma unroll
+            for (int c = 0; c < AE; ++c) ra[c] = cf * A[size_t(k0 + kk) * M + m0 + rr + c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < AE; ++c) ra[c] = cf * A[size_t(m0 + ar) * K + k0 + ak + c];
+        }
+#pragma unroll
+        for (int c = 0; c < BE; ++c) rb[c] = B[size_t(k0 + bk) * N + n0 + bc + c];
+    };
+    auto gload_masked = [&](int step) {
         const int term = step / nkt, k0 = (step - term * nkt) * BK;
         const double* A = pb.t[term].A;
         const double* B = pb.t[term].B;
@@ -1592,6 +1609,10 @@ __global__ void __launch_bounds__(256) k_mgemm_multi(const GemmProblem* __restri
             const int gc = n0 + bc + c;
             rb[c] = (gk < K && gc < N) ? B[size_t(gk) * N + gc] : 0.0;
         }
+    };
+    auto gload = [&](int step) {
+        if (whole) gload_whole(step);
+        else gload_masked(step);
     };
     auto sstore = [&](int buf) {
         if (trans) {
