@@ -50,3 +50,19 @@ from .precond import (  # noqa: F401
 )
 from .solver import pcg, fp_solve  # noqa: F401
 from .adjoint import fp_adjoint, fp_adjoint_dense  # noqa: F401
+from .reblur import (  # noqa: F401
+    REBLUR_VARIANTS,
+    ar_transform_matrix,
+    ar_transform_inverse_matrix,
+    ar_coefficients_2d,
+    ar_synthesis_2d,
+    ar_projection,
+    ar_projection_level2,
+    ar_end_weights,
+    ar_extend_eigs,
+    reblur_apply,
+    reblur_precond_setup,
+    reblur_precond_apply,
+    pbicgstab,
+    fp_solve_reblur,
+)
