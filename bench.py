@@ -304,6 +304,53 @@ def sweep_form(args):
     return res, slot
 
 
+def reblur_form(args, pcg_iters_per_solve):
+    """The reblurring system eq. (fpp) on the headline 512^2 workload with
+    PBiCGstab and P_D, FP32-mixed and FP64: restore time, BiCGstab
+    iterations (two operator products and two preconditioner solves each)
+    and the restoration error against the true scene; the first three steps
+    are kept for the comparison with the oracle."""
+    import torch
+    from paper_1011_5964_amd import synth
+    from paper_1011_5964_amd.lib import TVDeblur
+    p = synth.config("m512")
+    res = {"workload": "the headline 512x512 image (21x21 Gaussian sigma 3, AR, alpha 5e-4, beta 0.05, 15 "
+                       "fixed-point steps, PBiCGstab tol 1e-6) on the reblurring system (H'H + alpha L) u = H'v "
+                       "with P_D"}
+    slot = {}
+    for prec in ("f32_mixed", "f64"):
+        dt = torch.float32 if prec == "f32_mixed" else torch.float64
+        v = torch.tensor(p.v, dtype=dt, device="cuda")
+        h = TVDeblur(*p.v.shape, prec)
+        h.set_psf(p.psf)
+        h.set_bc(p.bc)
+        last = {}
+
+        def run():
+            u, st = h.solve_reblur(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "p_d")
+            last["u"], last["st"] = u, st
+            return u
+
+        times, _ = time_calls(run, max(2, args.steps // 2), 1)
+        t = statistics.median(times)
+        st = last["st"]
+        its = int(st["total_inner_iters"])
+        res[prec] = {"restore_time_s": t, "bicgstab_iters_per_solve": its,
+                     "bicgstab_iters_per_s": its / t,
+                     "iters_per_step": st["inner_iters"][:st["outer_steps"]],
+                     "all_converged": bool(st["all_converged"]),
+                     "operator_products_per_solve": 2 * its,
+                     "restoration_error": rel2(last["u"].double().cpu().numpy(), p.u_true)}
+        if prec == "f32_mixed":
+            u3, s3 = h.solve_reblur(v, p.alpha, p.beta, 3, p.inner_tol, p.max_inner, "p_d")
+            slot["u3"] = u3.double().cpu().numpy()
+            slot["iters3"] = s3["inner_iters"][:3]
+        h.close()
+    if pcg_iters_per_solve:
+        res["normal_equations_pcg_iters_per_solve"] = pcg_iters_per_solve
+    return res, slot
+
+
 def diff_form(args, f64_restore_s):
     """Forward (with checkpoints) and forward + adjoint on the 512^2
     differentiation workload, FP32-mixed."""
@@ -391,7 +438,8 @@ def main():
            "pcg_iters_per_s_inner_loop": round(r32["pcg_iters_per_s_inner_loop"], 1),
            "setup_share": round(r32["setup_share"], 4), "kernel_classes": r32["kernel_classes"]}
 
-    sel = {"all": {"f64", "batch", "diff", "sweep"}, "none": set()}.get(args.forms, set(args.forms.split(",")))
+    sel = {"all": {"f64", "batch", "diff", "sweep", "reblur"}, "none": set()}.get(args.forms,
+                                                                                set(args.forms.split(",")))
     forms = {}
     u64 = None
     probs = None
@@ -417,6 +465,10 @@ def main():
     if "sweep" in sel:
         print("[bench] alpha sweep (both boundary conditions)", file=sys.stderr, flush=True)
         forms["alpha_sweep"], sweep_slot = sweep_form(args)
+    reblur_slot = None
+    if "reblur" in sel:
+        print("[bench] reblurring system (PBiCGstab)", file=sys.stderr, flush=True)
+        forms["reblur"], reblur_slot = reblur_form(args, r32.get("pcg_iters_per_solve"))
 
     if args.cpu_steps > 0:
         import scipy.fft
@@ -455,6 +507,15 @@ def main():
             if sweep_slot is not None:
                 # the sweep's alpha = 5e-4 slot is the headline problem
                 forms["alpha_sweep"]["rel_err_vs_oracle_alpha_5e-4"] = rel2(sweep_slot["u"], uo)
+        if reblur_slot is not None:
+            # reblurring system: the first three steps against the oracle's
+            from oracle import reblur as RB
+            vq = p.v.astype(np.float32).astype(np.float64)
+            with threadpoolctl.threadpool_limits(cores), scipy.fft.set_workers(cores):
+                ur, sr = RB.fp_solve_reblur(vq, p.psf, p.alpha, p.beta, 3, p.inner_tol, p.max_inner, "p_d")
+            forms["reblur"]["first_3_steps_vs_oracle"] = {
+                "rel_err": rel2(reblur_slot["u3"], ur), "gpu_iters": reblur_slot["iters3"],
+                "oracle_iters": sr["inner_iters"]}
         if probs is not None:
             # per-image error of the batch: one image of each of the three smallest sizes
             errs = {}

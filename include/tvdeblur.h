@@ -161,6 +161,46 @@ int tvdeblur_destroy(tvdeblur_t h);
  * NULL).  Valid until the next call on h. */
 const char* tvdeblur_last_error(tvdeblur_t h);
 
+/* ---- the reblurring system (Section 3, eq. (fpp)) ----
+ *
+ * Fixed-point steps (H'H + alpha L(u^k)) u^{k+1} = H'v with u^0 = v, where
+ * H' is the anti-reflective blur of the PSF rotated by 180 degrees (= H, the
+ * PSF being quadrantally symmetric) and L(u^k) the zero-Neumann TV operator.
+ * The system is not symmetric; each step runs preconditioned BiCGstab (van
+ * der Vorst 1992) warm-started at u^k, with the reblurring preconditioners of
+ * Section 3 / Section 3.2 in the algebra of T_n (x) T_n (Section 2):
+ *   precond TVD_PREC_X   -> P   = H'H + alpha AR_2(L(u^k))
+ *           TVD_PREC_D_X -> D_P = D^{1/2} P D^{1/2}
+ *           TVD_PREC_X_D -> P_D for the scaled system eq. (scalereb), applied
+ *                           to eq. (fpp) as D^{1/2} P_D D^{1/2}
+ * AR_2(.) takes the level-2 tau projection of the operator's inner block for
+ * the interior eigenvalues and the corner rule of AR(.) for the two y = 0
+ * frequencies of each axis.
+ * Arguments, layout and ownership as tvdeblur_solve (v_dev, u_dev: ny x nx
+ * row-major device images of the handle's precision; p, stats: host).  One
+ * iteration (stats.inner_iters) = two preconditioner solves and two operator
+ * products; the test ||r_i|| < inner_tol ||r_0|| runs once per iteration, on
+ * the updated residual.  p->replay_host runs exactly the given counts.
+ * Requirements: anti-reflective BC (set_bc), a separable PSF (h = g_y g_x^T)
+ * of half-widths <= 16, precond one of the three above.
+ * Errors: TVD_EINVAL (also for an unsupported BC / PSF / preconditioner),
+ * TVD_ESTATE, TVD_ESIZE, TVD_EDEVICE, TVD_ENOMEM, TVD_EBREAKDOWN (rho,
+ * <rhat, v> or omega became 0; u_dev then holds the last iterate). */
+int tvdeblur_solve_reblur(tvdeblur_t h, const void* v_dev, void* u_dev,
+                          const tvd_params* p, tvd_stats* stats);
+
+/* Setup of the reblurring preconditioner (P, D_P or P_D as above) from uk_dev;
+ * tvdeblur_op_export then returns its kappa, s, mu, lambda_H and D. */
+int tvdeblur_op_reblur_setup(tvdeblur_t h, const void* uk_dev, double alpha, double beta, int precond);
+
+/* y = (H'H + alpha L(u^k)) x with the state of the last op_reblur_setup
+ * (x, y device images; must not alias).  Errors: TVD_ESTATE before it. */
+int tvdeblur_op_reblur_normal(tvdeblur_t h, const void* x_dev, void* y_dev);
+
+/* z = M^{-1} r for the reblurring preconditioner of the last op_reblur_setup
+ * (r, z must not alias).  Errors: TVD_ESTATE before it. */
+int tvdeblur_op_reblur_precond(tvdeblur_t h, const void* r_dev, void* z_dev);
+
 /* ---- single operators, for verification of each step on its own ---- */
 
 /* y = H x, the blur under the handle's BC (Section 2). */

@@ -87,6 +87,11 @@ class SolverBase {
     virtual void op_normal(const void* x, void* y) = 0;
     virtual void op_precond(const void* r, void* z) = 0;
     virtual void op_export(int which, void* dst) = 0;
+    // reblurring system (eq. (fpp)) with PBiCGstab and P / D_P / P_D
+    virtual void solve_reblur(const void* v, void* u, const tvd_params& p, tvd_stats& st) = 0;
+    virtual void op_reblur_setup(const void* uk, double alpha, double beta, int variant) = 0;
+    virtual void op_reblur_normal(const void* x, void* y) = 0;
+    virtual void op_reblur_precond(const void* r, void* z) = 0;
     virtual void set_profiling(int every) = 0;
     // Transform implementation of the preconditioner: 0 = pick by timing at
     // build, 1 = FFT line passes, 2 = products on the matrix cores.
@@ -230,6 +235,9 @@ class Solver final : public SolverBase {
         my_ = f.my;
         mx_ = f.mx;
         rank_ = f.rank;
+        factors_ = f;
+        reblur_ready_ = false;
+        reblur_mode_ = false;
         // 1D blur matrices of each factor with the BC folded in, and bands
         std::vector<double> hy, hx, hty, htx, ky, kx;
         for (int r = 0; r < rank_; ++r) {
@@ -905,6 +913,11 @@ class Solver final : public SolverBase {
             const int use_d = variant == TVD_PREC_X_D;
             TVD_HIP(launch_gemm(gemm1_, use_d ? 7 : 6, ny_, nx_, s_));
             TVD_HIP(launch_gemm(gemm2_, use_d ? 3 : 2, ny_, nx_, s_));
+            // AR_2(.) of the reblurring preconditioners: the interior
+            // eigenvalues are those of the S^ projection just formed, the
+            // y = 0 ends follow from them
+            if (reblur_mode_)
+                TVD_HIP(launch_ar_extend(ny_, nx_, arwy_, arwx_, LamX_, LamY_, use_d ? LamD_ : nullptr, s_));
             TVD_HIP(launch_mu<T>(int(N_), lamh2_, LamX_, LamY_, LamD_, use_d, alpha, Mu_, MuInv_, s_));
         }
         have_setup_ = true;
@@ -925,6 +938,7 @@ class Solver final : public SolverBase {
 
     // -------------------------------------------------------------- solve
     void solve(const void* vv, void* uu, const tvd_params& p, tvd_stats& st) override {
+        reblur_mode_ = false;
         const auto t0 = std::chrono::steady_clock::now();
         const T* v = static_cast<const T*>(vv);
         T* uout = static_cast<T*>(uu);
@@ -1002,6 +1016,7 @@ class Solver final : public SolverBase {
     // Reverse sweep over the checkpointed iterates (differentiation form).
     void solve_adjoint(const void* itv, int K, const void* ubarv, void* vbarv, double* abar, double* bbar,
                        const tvd_params& p, tvd_stats& st) override {
+        reblur_mode_ = false;
         const auto t0 = std::chrono::steady_clock::now();
         const T* its = static_cast<const T*>(itv);
         std::memset(&st, 0, sizeof(st));
@@ -1068,6 +1083,317 @@ class Solver final : public SolverBase {
         st.time_inner_s = ms_inner * 1e-3;
         st.time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
+    // ------------------------------------------------- reblurring system
+    // (H'H + alpha L(u^k)) u^{k+1} = H'v, eq. (fpp), anti-reflective H and
+    // zero-Neumann L, by PBiCGstab with P, D_P or P_D in the algebra of
+    // T_n (x) T_n.  H' = H (the PSF is quadrantally symmetric).  The whole
+    // operator runs in the fused y-pass with the bands of H H, the
+    // preconditioner as four products with T^{-1} and T.
+    void ensure_reblur() {
+        if (bc_ != TVD_BC_ANTIREFLECTIVE)
+            throw ApiError{TVD_EINVAL, "the reblurring system needs anti-reflective BCs"};
+        if (rank_ != 1 || !yfull_ || !gemm_ok_)
+            throw ApiError{TVD_EINVAL, "the reblurring system needs a separable PSF of half-width <= 16"};
+        if (reblur_ready_) return;
+        const std::vector<double> Hy = blur_matrix_1d(factors_.gy[0], ny_, bc_);
+        const std::vector<double> Hx = blur_matrix_1d(factors_.gx[0], nx_, bc_);
+        // H'H = H H: matmul_tn(A, B) = A^T B
+        const std::vector<double> ky = band_of(matmul_tn(transpose(Hy, ny_), Hy, ny_), ny_, 2 * my_);
+        const std::vector<double> kx = band_of(matmul_tn(transpose(Hx, nx_), Hx, nx_), nx_, 2 * mx_);
+        KyR_ = geo_.upload<T>(ky, s_);
+        KyRD_ = geo_.upload<double>(ky, s_);
+        KxRD_ = geo_.upload<double>(kx, s_);
+        const ToeplitzBand tb = compress_band(kx, nx_, 2 * mx_);
+        if (tb.w != kw_) throw ApiError{TVD_EINVAL, "reblurring band wider than the normal one"};
+        std::vector<double> d = tb.data;
+        const size_t per16 = 16 / sizeof(T);
+        while (d.size() % per16) d.push_back(0.0);
+        xbandR_ = geo_.upload<T>(d, s_);
+        kloR_ = tb.lo;
+        khiR_ = tb.hi;
+        auto mats = [&](int n, const T*& Tm, const T*& Ti) {
+            std::vector<double> t, ti;
+            ar_transform_matrices(n, t, ti);
+            Tm = geo_.upload<T>(t, s_);
+            Ti = geo_.upload<T>(ti, s_);
+        };
+        mats(nx_, RTx_, RTxi_);
+        if (ny_ == nx_) {
+            RTy_ = RTx_;
+            RTyi_ = RTxi_;
+        } else {
+            mats(ny_, RTy_, RTyi_);
+        }
+        arwy_ = geo_.upload<double>(ar_end_weights(ny_), s_);
+        arwx_ = geo_.upload<double>(ar_end_weights(nx_), s_);
+        auto A = [&](size_t elems) { return static_cast<T*>(geo_.alloc(elems * sizeof(T))); };
+        auto D = [&](size_t elems) { return static_cast<double*>(geo_.alloc(elems * sizeof(double))); };
+        Rh_ = A(N_);
+        Vv_ = A(N_);
+        Sv_ = A(N_);
+        Tv_ = A(N_);
+        Ph_ = A(N_);
+        Sh_ = A(N_);
+        nb_bcg_ = bcg_block_count(int(N_));
+        nb_yb_ = ((nx_ + 63) / 64) * ((ny_ + 15) / 16);
+        bcg_rr_ = D(nb_bcg_);
+        bcg_rho_ = D(nb_bcg_);
+        y_sig_ = D(nb_yb_);
+        y_ts_ = D(nb_yb_);
+        y_tt_ = D(nb_yb_);
+        bcg_sc_ = static_cast<BcgScalars*>(geo_.alloc(sizeof(BcgScalars)));
+        TVD_HIP(hipStreamSynchronize(s_));
+        reblur_ready_ = true;
+    }
+
+    // b = H'v = H v in FP64 (into BD_).
+    void rhs_reblur(const T* v) {
+        BandArgsT<T, T, double, double> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.wy = my_;
+        a.wx = mx_;
+        a.nterms = 1;
+        a.By = HyD_;
+        a.Bx = HxD_;
+        a.X = v;
+        a.Y = BD_;
+        TVD_HIP(launch_band(a, pick_ty(a), s_, nullptr));
+    }
+    // r = b - A'x with FP64 coefficients and ||r||^2 partials (one per step).
+    void residual_reblur(const T* x, T* r, double* rr_out) {
+        BandArgsT<T, T, double, T> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.wy = 2 * my_;
+        a.wx = 2 * mx_;
+        a.nterms = 1;
+        a.By = KyRD_;
+        a.Bx = KxRD_;
+        a.X = x;
+        a.kap = Kapd_;
+        a.alpha = alpha_;
+        a.Bvec = BD_;
+        a.Y = r;
+        a.dot_part = rr_out;
+        a.dotmode = 2;
+        a.st = st_;
+        TVD_HIP(launch_band(a, ty_res_, s_, nullptr));
+    }
+    // q = A'z (H H in the fused y-pass, + alpha L z) with <dotw, q> partials
+    // (and <q, q> when qq is set).
+    void ypass_reblur(int it, const T* z, T* q, const T* dotw, double* pq, double* qq) {
+        YPassArgs<T> a{};
+        a.ny = ny_;
+        a.nx = nx_;
+        a.w = 2 * my_;
+        a.Ky = KyR_;
+        a.z = z;
+        a.kap = Kap_;
+        a.alpha = alpha_;
+        a.q = q;
+        a.pq_part = pq;
+        a.st = st_;
+        a.xband = xbandR_;
+        a.kw = kw_;
+        a.klo = kloR_;
+        a.khi = khiR_;
+        a.dotw = dotw;
+        a.qq_part = qq;
+        (void)it;
+        int nb = 0;
+        timer_.begin(KernelTimer::kBand, s_);
+        TVD_HIP(launch_ypass_full_bcg<T>(a, s_, &nb));
+        timer_.end(s_);
+    }
+    // out = sc o T2[(T2^{-1} in) / mu] with in = T2_ (= sc o vector), as the
+    // four products of gemm_args with T^{-1} forward and T inverse.
+    void products_reblur(int it, T* out) {
+        MGemmArgs<T> b{};
+        b.st = st_;
+        b.iter = it;
+        b.M = ny_;
+        b.N = nx_;
+        MGemmArgs<T> g[4] = {b, b, b, b};
+        g[0].K = nx_;
+        g[0].A = T2_;
+        g[0].Bt = RTxi_;
+        g[0].C = T1_;
+        g[0].transC = 1;
+        g[1].K = ny_;
+        g[1].A = RTyi_;
+        g[1].Bt = T1_;
+        g[1].C = T2_;
+        g[1].epi = 1;
+        g[1].E1 = MuInv_;
+        g[2].K = nx_;
+        g[2].A = T2_;
+        g[2].Bt = RTx_;
+        g[2].C = T1_;
+        g[2].transC = 1;
+        g[3].K = ny_;
+        g[3].A = RTy_;
+        g[3].Bt = T1_;
+        g[3].C = out;
+        g[3].epi = 1;
+        g[3].E1 = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
+        for (int k = 0; k < 4; ++k) {
+            int nb = 0;
+            timer_.begin(KernelTimer::kGemm, s_);
+            TVD_HIP(launch_mgemm<T>(g[k], s_, &nb));
+            timer_.end(s_);
+        }
+    }
+    BcgArgs<T> bcg_args(int it) const {
+        BcgArgs<T> a{};
+        a.n = int(N_);
+        a.iter = it;
+        a.x = X_;
+        a.r = R_;
+        a.rhat = Rh_;
+        a.p = Pb_[0];
+        a.v = Vv_;
+        a.s = Sv_;
+        a.t = Tv_;
+        a.phat = Ph_;
+        a.shat = Sh_;
+        a.sc = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
+        a.tin = T2_;
+        a.rr_in = bcg_rr_;
+        a.rho_in = bcg_rho_;
+        a.n_in = nb_bcg_;
+        a.sig_in = y_sig_;
+        a.ts_in = y_ts_;
+        a.tt_in = y_tt_;
+        a.n_y = nb_yb_;
+        a.rr_out = bcg_rr_;
+        a.rho_out = bcg_rho_;
+        a.sc_st = bcg_sc_;
+        a.st = st_;
+        return a;
+    }
+    void bcg_stage(int it, int stage) {
+        timer_.begin(KernelTimer::kUpdate, s_);
+        TVD_HIP(launch_bcg<T>(bcg_args(it), stage, s_, nullptr));
+        timer_.end(s_);
+    }
+    // One BiCGstab iteration: 2 preconditioner solves, 2 operator products.
+    void bcg_iteration(int it) {
+        bcg_stage(it, 1);
+        products_reblur(it, Ph_);
+        ypass_reblur(it, Ph_, Vv_, Rh_, y_sig_, nullptr);
+        bcg_stage(it, 2);
+        products_reblur(it, Sh_);
+        ypass_reblur(it, Sh_, Tv_, Sv_, y_ts_, y_tt_);
+        bcg_stage(it, 3);
+    }
+    // One PBiCGstab solve: x (X_) from u^k (U_) to u^{k+1}; the stopping
+    // test (||r_i|| < tol ||r_0||) runs at the start of iteration i + 1.
+    void bicgstab(int maxit, double tol, int predicted) {
+        TVD_HIP(launch_init_state(st_, tol, s_));
+        TVD_HIP(hipMemcpyAsync(X_, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        residual_reblur(X_, R_, rr_[0]);
+        bcg_stage(0, 0);
+        int next_poll = std::max(2, predicted);
+        for (int it = 1; it <= maxit; ++it) {
+            bcg_iteration(it);
+            if (it == next_poll && it < maxit) {
+                TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+                TVD_HIP(hipStreamSynchronize(s_));
+                timer_.harvest();
+                if (host_st_->done) break;
+                next_poll = it + 1;
+            }
+        }
+        int nfp = 0;
+        TVD_HIP(launch_fpchange<T>(int(N_), X_, U_, fp_, &nfp, s_));
+        TVD_HIP(launch_finalize<T>(st_, bcg_rr_, nb_bcg_, fp_, nfp, maxit, s_));
+    }
+    void reblur_setup(const T* uk, double alpha, double beta, int variant) {
+        reblur_mode_ = true;
+        setup(uk, alpha, beta, variant);
+    }
+    void solve_reblur(const void* vv, void* uu, const tvd_params& p, tvd_stats& st) override {
+        if (p.precond < TVD_PREC_X) throw ApiError{TVD_EINVAL, "the reblurring system takes P, D_P or P_D"};
+        ensure_reblur();
+        const auto t0 = std::chrono::steady_clock::now();
+        const T* v = static_cast<const T*>(vv);
+        std::memset(&st, 0, sizeof(st));
+        st.all_converged = 1;
+        T* iters_out = static_cast<T*>(p.iterates_dev);
+        rhs_reblur(v);
+        TVD_HIP(hipMemcpyAsync(U_, p.u0_dev ? p.u0_dev : vv, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        float ms_setup = 0, ms_inner = 0;
+        int prev_iters = 4;
+        for (int k = 0; k < p.max_outer; ++k) {
+            if (iters_out)
+                TVD_HIP(hipMemcpyAsync(iters_out + size_t(k) * N_, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+            TVD_HIP(hipEventRecord(ev_a_, s_));
+            reblur_setup(U_, p.alpha, p.beta, p.precond);
+            TVD_HIP(hipEventRecord(ev_b_, s_));
+            const int maxit = p.replay_host ? p.replay_host[k] : p.max_inner;
+            const double tol = p.replay_host ? 0.0 : p.inner_tol;
+            bicgstab(maxit, tol, prev_iters);
+            TVD_HIP(hipEventRecord(ev_c_, s_));
+            TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+            TVD_HIP(hipStreamSynchronize(s_));
+            timer_.harvest();
+            std::swap(U_, X_);
+            float a = 0, b = 0;
+            TVD_HIP(hipEventElapsedTime(&a, ev_a_, ev_b_));
+            TVD_HIP(hipEventElapsedTime(&b, ev_b_, ev_c_));
+            ms_setup += a;
+            ms_inner += b;
+            const PcgState hs = *host_st_;
+            st.inner_iters[k] = hs.iters;
+            st.relres[k] = hs.relres;
+            st.fp_change[k] = hs.fp_change;
+            st.total_inner_iters += hs.iters;
+            st.outer_steps = k + 1;
+            prev_iters = std::max(1, hs.iters);
+            if (hs.done != 1 && hs.iters >= maxit && !p.replay_host) st.all_converged = 0;
+            if (hs.done == 2) {
+                st.breakdown = 1;
+                st.all_converged = 0;
+                break;
+            }
+            if (p.fp_tol > 0.0 && hs.fp_change < p.fp_tol) break;
+        }
+        if (iters_out)
+            TVD_HIP(hipMemcpyAsync(iters_out + size_t(st.outer_steps) * N_, U_, N_ * sizeof(T),
+                                   hipMemcpyDeviceToDevice, s_));
+        TVD_HIP(hipMemcpyAsync(uu, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        TVD_HIP(hipStreamSynchronize(s_));
+        reblur_mode_ = false;
+        st.time_setup_s = ms_setup * 1e-3;
+        st.time_inner_s = ms_inner * 1e-3;
+        st.time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        solved_ = st.outer_steps > 0;
+        if (st.breakdown) throw ApiError{TVD_EBREAKDOWN, "BiCGstab breakdown: rho, <rhat, v> or omega = 0"};
+    }
+    void op_reblur_setup(const void* uk, double alpha, double beta, int variant) override {
+        if (variant < TVD_PREC_X) throw ApiError{TVD_EINVAL, "the reblurring system takes P, D_P or P_D"};
+        ensure_reblur();
+        reblur_setup(static_cast<const T*>(uk), alpha, beta, variant);
+        TVD_HIP(hipStreamSynchronize(s_));
+        timer_.harvest();
+    }
+    void op_reblur_normal(const void* x, void* y) override {
+        if (!have_setup_ || !reblur_mode_) throw ApiError{TVD_ESTATE, "op_reblur_normal before op_reblur_setup"};
+        TVD_HIP(launch_init_state(st_, 0.0, s_));
+        ypass_reblur(0, static_cast<const T*>(x), static_cast<T*>(y), static_cast<const T*>(x), y_sig_, nullptr);
+        TVD_HIP(hipStreamSynchronize(s_));
+        timer_.harvest();
+    }
+    void op_reblur_precond(const void* r, void* z) override {
+        if (!have_setup_ || !reblur_mode_) throw ApiError{TVD_ESTATE, "op_reblur_precond before op_reblur_setup"};
+        TVD_HIP(launch_init_state(st_, 0.0, s_));
+        upd_launch(0, false, static_cast<const T*>(r));
+        products_reblur(0, static_cast<T*>(z));
+        TVD_HIP(hipStreamSynchronize(s_));
+        timer_.harvest();
+    }
+
     hipError_t launch_add_vec(double* dst, const double* src) {
         return launch_add_to_double<double>(int(N_), src, dst, s_);
     }
@@ -1265,6 +1591,7 @@ class Solver final : public SolverBase {
         TVD_HIP(hipStreamSynchronize(s_));
     }
     void op_setup(const void* uk, double alpha, double beta, int variant) override {
+        reblur_mode_ = false;
         setup(static_cast<const T*>(uk), alpha, beta, variant);
         TVD_HIP(hipStreamSynchronize(s_));
         timer_.harvest();
@@ -1482,6 +1809,17 @@ class Solver final : public SolverBase {
     double alpha_ = 0, beta_ = 0;
     int variant_ = TVD_PREC_X_D;
     bool have_setup_ = false;
+    // reblurring system (built on first use)
+    PsfFactors factors_{};
+    bool reblur_ready_ = false, reblur_mode_ = false;
+    const T *KyR_ = nullptr, *xbandR_ = nullptr;
+    const double *KyRD_ = nullptr, *KxRD_ = nullptr, *arwy_ = nullptr, *arwx_ = nullptr;
+    int kloR_ = 0, khiR_ = 0;
+    const T *RTx_ = nullptr, *RTxi_ = nullptr, *RTy_ = nullptr, *RTyi_ = nullptr;
+    T *Rh_ = nullptr, *Vv_ = nullptr, *Sv_ = nullptr, *Tv_ = nullptr, *Ph_ = nullptr, *Sh_ = nullptr;
+    double *bcg_rr_ = nullptr, *bcg_rho_ = nullptr, *y_sig_ = nullptr, *y_ts_ = nullptr, *y_tt_ = nullptr;
+    int nb_bcg_ = 0, nb_yb_ = 0;
+    BcgScalars* bcg_sc_ = nullptr;
 };
 
 
@@ -2497,6 +2835,65 @@ int tvdeblur_op_precond(tvdeblur_t h, const void* r_dev, void* z_dev) {
         int rc = ensure_built(h);
         if (rc) return rc;
         h->solver->op_precond(r_dev, z_dev);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_solve_reblur(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_params* p, tvd_stats* stats) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (!v_dev || !u_dev || !p) return fail(h, TVD_EINVAL, "NULL argument");
+    if (v_dev == u_dev) return fail(h, TVD_EINVAL, "v and u must not alias");
+    if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || p->alpha < 0 || !(p->beta > 0))
+        return fail(h, TVD_EINVAL, "alpha must be >= 0 and beta > 0, both finite");
+    if (p->max_outer < 1 || p->max_outer > TVD_MAX_OUTER) return fail(h, TVD_EINVAL, "max_outer out of range");
+    if (p->max_inner < 1 || !(p->inner_tol >= 0) || !(p->fp_tol >= 0))
+        return fail(h, TVD_EINVAL, "bad inner_tol / max_inner / fp_tol");
+    if (p->precond < TVD_PREC_X || p->precond > TVD_PREC_X_D)
+        return fail(h, TVD_EINVAL, "the reblurring system takes TVD_PREC_X, TVD_PREC_D_X or TVD_PREC_X_D");
+    if (p->replay_host)
+        for (int k = 0; k < p->max_outer; ++k)
+            if (p->replay_host[k] < 0) return fail(h, TVD_EINVAL, "negative replay count");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        tvd_stats local;
+        h->solver->solve_reblur(v_dev, u_dev, *p, stats ? *stats : local);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_op_reblur_setup(tvdeblur_t h, const void* uk_dev, double alpha, double beta, int precond) {
+    if (!h || !uk_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    if (!std::isfinite(alpha) || alpha < 0 || !std::isfinite(beta) || !(beta > 0))
+        return fail(h, TVD_EINVAL, "alpha must be >= 0 and beta > 0, both finite");
+    if (precond < TVD_PREC_X || precond > TVD_PREC_X_D)
+        return fail(h, TVD_EINVAL, "the reblurring system takes TVD_PREC_X, TVD_PREC_D_X or TVD_PREC_X_D");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_reblur_setup(uk_dev, alpha, beta, precond);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_op_reblur_normal(tvdeblur_t h, const void* x_dev, void* y_dev) {
+    if (!h || !x_dev || !y_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    if (x_dev == y_dev) return fail(h, TVD_EINVAL, "x and y must not alias");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_reblur_normal(x_dev, y_dev);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_op_reblur_precond(tvdeblur_t h, const void* r_dev, void* z_dev) {
+    if (!h || !r_dev || !z_dev) return fail(h, TVD_EINVAL, "NULL argument");
+    if (r_dev == z_dev) return fail(h, TVD_EINVAL, "r and z must not alias");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        h->solver->op_reblur_precond(r_dev, z_dev);
         return TVD_OK;
     });
 }

@@ -147,6 +147,55 @@ struct YPassArgs {
     // (interior row, then rows 0..klo-1, then rows khi..nx-1), half-width kw
     const T* xband;
     int kw, klo, khi;
+    // BiCGstab form (k_ypass_full_bcg): beta = 0, no p copy; the partials
+    // are <dotw, q> into pq_part and, when qq_part is set, <q, q> into it
+    const T* dotw;
+    double* qq_part;
+};
+
+// Scalars of preconditioned BiCGstab carried between its launches: rho by
+// iteration parity (written by the direction stage of iteration i into
+// rho[i & 1], read as rho_old by iteration i + 1), alpha and omega of the
+// last completed stages.
+struct BcgScalars {
+    double rho[2];
+    double alpha;
+    double omega;
+};
+
+// Vector stages of BiCGstab on the reblurring system (k_bcg):
+//   0 init:      rhat = r, p = v = 0; partials ||r||^2, <rhat, r>; scalars 1
+//   1 direction: stopping test on ||r_{i-1}||, rho = <rhat, r_{i-1}>,
+//                p = r + beta (p - omega v), tin = sc o p
+//   2 s-update:  alpha = rho / <rhat, v>, s = r - alpha v, tin = sc o s
+//   3 x-update:  omega = <t, s> / <t, t>, x += alpha phat + omega shat,
+//                r = s - omega t; partials ||r||^2, <rhat, r>
+template <typename T>
+struct BcgArgs {
+    int n;
+    int iter;
+    T* x;
+    T* r;
+    T* rhat;
+    T* p;
+    T* v;
+    T* s;
+    const T* t;
+    const T* phat;
+    const T* shat;
+    const T* sc;            // D^{-1/2} of D_P / P_D; nullptr: ones
+    T* tin;                 // preconditioner input
+    const double* rr_in;    // stage 1: ||r||^2 and <rhat, r> partials
+    const double* rho_in;
+    int n_in;
+    const double* sig_in;   // stage 2: <rhat, v> partials
+    const double* ts_in;    // stage 3: <t, s> and <t, t> partials
+    const double* tt_in;
+    int n_y;                // partials of stages 2 and 3 (y-pass blocks)
+    double* rr_out;         // stages 0 and 3
+    double* rho_out;
+    BcgScalars* sc_st;
+    PcgState* st;
 };
 
 // Dense product on the matrix cores, C = A Bt^T: A is M x K and Bt is N x K,
@@ -345,6 +394,14 @@ template <typename T>
 hipError_t launch_ypass(const YPassArgs<T>& a, hipStream_t s, int* nblocks);
 template <typename T>
 hipError_t launch_ypass_full(const YPassArgs<T>& a, hipStream_t s, int* nblocks);
+template <typename T>
+hipError_t launch_ypass_full_bcg(const YPassArgs<T>& a, hipStream_t s, int* nblocks);
+template <typename T>
+hipError_t launch_bcg(const BcgArgs<T>& a, int stage, hipStream_t s, int* nblocks);
+// In place: end rows / columns of up to three ny x nx eigenvalue arrays
+// (nullptr skipped) from their interior with the end weights wy, wx.
+hipError_t launch_ar_extend(int ny, int nx, const double* wy, const double* wx, double* l0, double* l1,
+                            double* l2, hipStream_t s);
 // Matrix-core product; *nblocks = number of blocks (= partials of epi 2).
 // Only for element types whose MFMA layout is supported (mgemm_supported).
 template <typename T>
@@ -363,6 +420,7 @@ hipError_t launch_upd_b(const UpdArgs<T>* a, int it, BatchGrid g, hipStream_t s)
 template <typename T>
 hipError_t launch_xpass_b(const XPassArgs<T>* a, BatchGrid g, hipStream_t s);
 int upd_block_count(int n);
+int bcg_block_count(int n);
 int ypass_blocks(int ny, int nx);
 template <typename T>
 hipError_t launch_colpass(const ColPassArgs<T>& a, hipStream_t s);
@@ -436,6 +494,11 @@ std::vector<double> matmul_tn(const std::vector<double>& A, const std::vector<do
 std::vector<double> basis_matrix(int n, int bc);
 // lambda_H[k*nx + l] = h^(theta_k, theta_l) on the BC grid.
 std::vector<double> symbol_eigenvalues(const double* h, int py, int px, int ny, int nx, int bc);
+// T_n and T_n^{-1} of the anti-reflective algebra, row-major (n >= 3).
+void ar_transform_matrices(int n, std::vector<double>& T, std::vector<double>& Ti);
+// n - 2 weights w: the end eigenvalue of AR(A) is sum_j w_j mu_j over the
+// interior eigenvalues mu of s(A_in).
+std::vector<double> ar_end_weights(int n);
 
 struct AxisTables {
     int n, kind, L, M, log2M, bluestein;

@@ -1134,7 +1134,9 @@ __device__ __forceinline__ T band_dot(const T* __restrict__ coef, const T* v, in
 constexpr int kYFRegs = ((kYTY + 2 * kYFMaxH) * (kYTX + 2 * kYFMaxH) + kYThreads - 1) / kYThreads;
 // kRowPairs: the beta sums in one reduction and K_y two tile rows per
 // thread (the single-image kernel; measured slower in the batched one).
-template <typename T, bool kRowPairs>
+// kBcg: the BiCGstab form (see YPassArgs): q = A z with the partials of
+// <dotw, q> and <q, q>, no direction update.
+template <typename T, bool kRowPairs, bool kBcg = false>
 __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, int by, int gx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[34];
@@ -1168,6 +1170,8 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
     const T kc = own ? a.kap[g] : T(0);
     const T ku = (own && gi > 0) ? a.kap[g - nx] : T(0);
     const T kl = (own && gj > 0) ? a.kap[g - 1] : T(0);
+    T dw = T(0);
+    if constexpr (kBcg) dw = own ? a.dotw[g] : T(0);
     if (done) return;
 
     T beta = T(0);
@@ -1240,11 +1244,11 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
     }
     __syncthreads();
 
-    double dot = 0.0;
+    double dot = 0.0, dot2 = 0.0;
     if (own) {
         const T* prow = pr + (ty + hy) * TW + tx + hx;
         const T pc = prow[0];
-        a.p_new[g] = pc;
+        if constexpr (!kBcg) a.p_new[g] = pc;
         // K_x along the row: interior tiles use the Toeplitz row (uniform
         // coefficients), tiles that touch a stored edge row pick per column
         const int bw = 2 * wx + 1;
@@ -1263,15 +1267,33 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
         if (gj < nx - 1) lp += kc * (pc - prow[1]);
         const T qv = kxp + T(a.alpha) * lp;
         a.q[g] = qv;
-        dot = double(pc) * double(qv);
+        if constexpr (kBcg) {
+            dot = double(dw) * double(qv);
+            dot2 = double(qv) * double(qv);
+        } else {
+            dot = double(pc) * double(qv);
+        }
     }
-    const double sm = block_sum(dot, red);
-    if (tid == 0) a.pq_part[by * gx + bx] = sm;
+    if constexpr (kBcg) {
+        block_sum2(dot, dot2, red);
+        if (tid == 0) {
+            a.pq_part[by * gx + bx] = dot;
+            if (a.qq_part) a.qq_part[by * gx + bx] = dot2;
+        }
+    } else {
+        const double sm = block_sum(dot, red);
+        if (tid == 0) a.pq_part[by * gx + bx] = sm;
+    }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kYThreads) k_ypass_full(YPassArgs<T> a) {
     ypass_full_body<T, true>(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kYThreads) k_ypass_full_bcg(YPassArgs<T> a) {
+    ypass_full_body<T, true, true>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename T>
@@ -2249,6 +2271,226 @@ hipError_t launch_upd(const UpdArgs<T>& a, hipStream_t s, int* nblocks) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------
+// Preconditioned BiCGstab on the reblurring system (van der Vorst 1992):
+// the vector stages between the preconditioner solves and the operator
+// products (see BcgArgs).  Every block reduces the partials it needs itself
+// (the same sums in every block); one thread of the grid records the
+// scalars the later stages read.  Each thread owns kBcgE elements (stride
+// 256 inside its block's range); its loads are issued before the
+// reductions.
+// ------------------------------------------------------------------------
+constexpr int kBcgE = 4;
+
+int bcg_block_count(int n) { return std::max(1, (n + 256 * kBcgE - 1) / (256 * kBcgE)); }
+
+template <typename T, int kStage>
+__global__ void __launch_bounds__(256) k_bcg(BcgArgs<T> a) {
+    __shared__ double red[34];
+    const int tid = threadIdx.x, bx = blockIdx.x;
+    const int base = bx * 256 * kBcgE + tid;
+    const bool leader = bx == 0 && tid == 0;
+    const int done = a.st->done;
+    if constexpr (kStage == 0) {
+        double rr = 0.0;
+        for (int c = 0; c < kBcgE; ++c) {
+            const int k = base + 256 * c;
+            if (k >= a.n) continue;
+            const T r = a.r[k];
+            a.rhat[k] = r;
+            a.p[k] = T(0);
+            a.v[k] = T(0);
+            rr += double(r) * double(r);
+        }
+        rr = block_sum(rr, red);
+        if (tid == 0) {
+            a.rr_out[bx] = rr;
+            a.rho_out[bx] = rr;
+        }
+        if (leader) {
+            a.sc_st->rho[0] = a.sc_st->rho[1] = 1.0;
+            a.sc_st->alpha = a.sc_st->omega = 1.0;
+        }
+    } else if constexpr (kStage == 1) {
+        const double rrp = partial_issue(a.rr_in, a.n_in, tid, 256);
+        const double rhp = partial_issue(a.rho_in, a.n_in, tid, 256);
+        const double r0 = a.st->r0norm, tol = a.st->tol;
+        const int cap = a.st->cap;
+        const double rho_old = a.sc_st->rho[(a.iter - 1) & 1];
+        const double alpha = a.sc_st->alpha, omega = a.sc_st->omega;
+        T rv[kBcgE], pv[kBcgE], vv[kBcgE], sv[kBcgE];
+#pragma unroll
+        for (int c = 0; c < kBcgE; ++c) {
+            const int k = base + 256 * c;
+            const bool in = k < a.n;
+            rv[c] = in ? a.r[k] : T(0);
+            pv[c] = in ? a.p[k] : T(0);
+            vv[c] = in ? a.v[k] : T(0);
+            sv[c] = (in && a.sc) ? a.sc[k] : T(1);
+        }
+        if (done) return;
+        if (pcg_stop_test(a.st, rrp, a.iter - 1, r0, tol, cap, leader, red)) return;
+        const double rho = block_sum(rhp, red);
+        if (rho == 0.0 || omega == 0.0) {  // breakdown: keep x of iteration iter - 1
+            if (leader) {
+                a.st->done = 2;
+                a.st->iters = a.iter - 1;
+            }
+            return;
+        }
+        const T beta = T((rho / rho_old) * (alpha / omega));
+        const T om = T(omega);
+#pragma unroll
+        for (int c = 0; c < kBcgE; ++c) {
+            const int k = base + 256 * c;
+            if (k >= a.n) continue;
+            const T pn = rv[c] + beta * (pv[c] - om * vv[c]);
+            a.p[k] = pn;
+            a.tin[k] = sv[c] * pn;
+        }
+        if (leader) a.sc_st->rho[a.iter & 1] = rho;
+    } else if constexpr (kStage == 2) {
+        const double sgp = partial_issue(a.sig_in, a.n_y, tid, 256);
+        const double rho = a.sc_st->rho[a.iter & 1];
+        T rv[kBcgE], vv[kBcgE], sv[kBcgE];
+#pragma unroll
+        for (int c = 0; c < kBcgE; ++c) {
+            const int k = base + 256 * c;
+            const bool in = k < a.n;
+            rv[c] = in ? a.r[k] : T(0);
+            vv[c] = in ? a.v[k] : T(0);
+            sv[c] = (in && a.sc) ? a.sc[k] : T(1);
+        }
+        if (done) return;
+        const double sigma = block_sum(sgp, red);
+        if (sigma == 0.0) {
+            if (leader) {
+                a.st->done = 2;
+                a.st->iters = a.iter - 1;
+            }
+            return;
+        }
+        const double alpha = rho / sigma;
+        const T al = T(alpha);
+#pragma unroll
+        for (int c = 0; c < kBcgE; ++c) {
+            const int k = base + 256 * c;
+            if (k >= a.n) continue;
+            const T sn = rv[c] - al * vv[c];
+            a.s[k] = sn;
+            a.tin[k] = sv[c] * sn;
+        }
+        if (leader) a.sc_st->alpha = alpha;
+    } else {
+        double ts = partial_issue(a.ts_in, a.n_y, tid, 256);
+        double tt = partial_issue(a.tt_in, a.n_y, tid, 256);
+        const double alpha = a.sc_st->alpha;
+        T xv[kBcgE], sv[kBcgE], tv[kBcgE], ph[kBcgE], sh[kBcgE], rh[kBcgE];
+#pragma unroll
+        for (int c = 0; c < kBcgE; ++c) {
+            const int k = base + 256 * c;
+            const bool in = k < a.n;
+            xv[c] = in ? a.x[k] : T(0);
+            sv[c] = in ? a.s[k] : T(0);
+            tv[c] = in ? a.t[k] : T(0);
+            ph[c] = in ? a.phat[k] : T(0);
+            sh[c] = in ? a.shat[k] : T(0);
+            rh[c] = in ? a.rhat[k] : T(0);
+        }
+        if (done) return;
+        block_sum2(ts, tt, red);
+        const double omega = tt > 0.0 ? ts / tt : 0.0;
+        const T al = T(alpha), om = T(omega);
+        double rr = 0.0, rhr = 0.0;
+#pragma unroll
+        for (int c = 0; c < kBcgE; ++c) {
+            const int k = base + 256 * c;
+            if (k >= a.n) continue;
+            a.x[k] = xv[c] + (al * ph[c] + om * sh[c]);
+            const T rn = sv[c] - om * tv[c];
+            a.r[k] = rn;
+            rr += double(rn) * double(rn);
+            rhr += double(rh[c]) * double(rn);
+        }
+        block_sum2(rr, rhr, red);
+        if (tid == 0) {
+            a.rr_out[bx] = rr;
+            a.rho_out[bx] = rhr;
+        }
+        if (leader) a.sc_st->omega = omega;
+    }
+}
+
+template <typename T>
+hipError_t launch_bcg(const BcgArgs<T>& a, int stage, hipStream_t s, int* nblocks) {
+    const int nb = bcg_block_count(a.n);
+    if (nblocks) *nblocks = nb;
+    switch (stage) {
+        case 0: tvd_launch(k_bcg<T, 0>, dim3(nb), dim3(256), 0, s, a); break;
+        case 1: tvd_launch(k_bcg<T, 1>, dim3(nb), dim3(256), 0, s, a); break;
+        case 2: tvd_launch(k_bcg<T, 2>, dim3(nb), dim3(256), 0, s, a); break;
+        case 3: tvd_launch(k_bcg<T, 3>, dim3(nb), dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ypass_full_bcg(const YPassArgs<T>& a, hipStream_t s, int* nblocks) {
+    if (a.w > kYFMaxH || a.kw > kYFMaxH || a.w < 0 || a.kw < 0 || !a.dotw || !a.pq_part)
+        return hipErrorInvalidValue;
+    const size_t lds = ypass_full_lds_bytes(a.w, a.kw, sizeof(T));
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ypass_full_bcg<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    dim3 grid((a.nx + kYTX - 1) / kYTX, (a.ny + kYTY - 1) / kYTY);
+    if (nblocks) *nblocks = grid.x * grid.y;
+    tvd_launch(k_ypass_full_bcg<T>, grid, dim3(kYThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+// Eigenvalues of AR_2(.) at the two y = 0 frequencies of each axis (first
+// and last row and column of the grid) from the interior ones, the end
+// eigenvalue of AR(.) being sum_j w_j mu_j (Section 3; level 2 of Section
+// 3.2).  The column pass fills the end columns of the interior rows; the row
+// pass then fills the end rows over all columns, end columns included, so a
+// corner is sum_i wy_i sum_j wx_j lam_ij.  In place: the column pass reads
+// only interior entries and the row pass only interior rows.
+__global__ void __launch_bounds__(256) k_ar_ext_cols(int ny, int nx, const double* __restrict__ wx, double* l0,
+                                                     double* l1, double* l2) {
+    __shared__ double red[17];
+    double* lam = blockIdx.y == 0 ? l0 : (blockIdx.y == 1 ? l1 : l2);
+    if (!lam) return;
+    const int i = blockIdx.x + 1;
+    double* row = lam + size_t(i) * nx;
+    double acc = 0.0;
+    for (int j = 1 + int(threadIdx.x); j < nx - 1; j += 256) acc += wx[j - 1] * row[j];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        row[0] = acc;
+        row[nx - 1] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_ar_ext_rows(int ny, int nx, const double* __restrict__ wy, double* l0,
+                                                     double* l1, double* l2) {
+    double* lam = blockIdx.y == 0 ? l0 : (blockIdx.y == 1 ? l1 : l2);
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (!lam || j >= nx) return;
+    double acc = 0.0;
+    for (int i = 1; i < ny - 1; ++i) acc += wy[i - 1] * lam[size_t(i) * nx + j];
+    lam[j] = acc;
+    lam[size_t(ny - 1) * nx + j] = acc;
+}
+
+hipError_t launch_ar_extend(int ny, int nx, const double* wy, const double* wx, double* l0, double* l1,
+                            double* l2, hipStream_t s) {
+    if (ny < 3 || nx < 3) return hipErrorInvalidValue;
+    tvd_launch(k_ar_ext_cols, dim3(ny - 2, 3), dim3(256), 0, s, ny, nx, wx, l0, l1, l2);
+    tvd_launch(k_ar_ext_rows, dim3((nx + 255) / 256, 3), dim3(256), 0, s, ny, nx, wy, l0, l1, l2);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_xpass(const XPassArgs<T>& a, hipStream_t s) {
     tvd_launch(k_xpass<T>, dim3(a.ny), dim3(256), size_t(a.nx + a.xband_len) * sizeof(T), s, a);
@@ -2454,6 +2696,8 @@ hipError_t launch_ypass_full_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s
     template bool mgemm_supported<T>();                                                                       \
     template hipError_t launch_mgemm<T>(const MGemmArgs<T>&, hipStream_t, int*);                              \
     template hipError_t launch_upd<T>(const UpdArgs<T>&, hipStream_t, int*);                                  \
+    template hipError_t launch_bcg<T>(const BcgArgs<T>&, int, hipStream_t, int*);                             \
+    template hipError_t launch_ypass_full_bcg<T>(const YPassArgs<T>&, hipStream_t, int*);                     \
     template hipError_t launch_mgemm_b<T>(const MGemmArgs<T>*, int, BatchGrid, hipStream_t);                  \
     template hipError_t launch_upd_b<T>(const UpdArgs<T>*, int, BatchGrid, hipStream_t);                      \
     template hipError_t launch_xpass_b<T>(const XPassArgs<T>*, BatchGrid, hipStream_t);                       \

@@ -281,6 +281,56 @@ std::vector<double> matmul_tn(const std::vector<double>& A, const std::vector<do
     return C;
 }
 
+// T_n of the anti-reflective algebra (Section 2): columns (1, p, 0),
+// (0, S_{n-2}, 0), (0, Jp, 1) with p_j = 1 - j/(n-1), j = 1..n-2; and its
+// inverse with interior rows (-S p, S, -S J p).
+void ar_transform_matrices(int n, std::vector<double>& T, std::vector<double>& Ti) {
+    const int m = n - 2;
+    const double sc = std::sqrt(2.0 / (m + 1));
+    std::vector<double> S(size_t(m) * m), p(m), sp(m, 0.0), sjp(m, 0.0);
+    for (int i = 0; i < m; ++i) {
+        p[i] = 1.0 - double(i + 1) / double(n - 1);
+        for (int j = 0; j < m; ++j) S[size_t(i) * m + j] = sc * sin_pi_frac((long long)(i + 1) * (j + 1), m + 1);
+    }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            sp[i] += S[size_t(i) * m + j] * p[j];
+            sjp[i] += S[size_t(i) * m + j] * p[m - 1 - j];
+        }
+    T.assign(size_t(n) * n, 0.0);
+    Ti.assign(size_t(n) * n, 0.0);
+    T[0] = Ti[0] = 1.0;
+    T[size_t(n) * n - 1] = Ti[size_t(n) * n - 1] = 1.0;
+    for (int i = 1; i <= m; ++i) {
+        double* t = &T[size_t(i) * n];
+        double* ti = &Ti[size_t(i) * n];
+        t[0] = p[i - 1];
+        t[n - 1] = p[m - i];
+        ti[0] = -sp[i - 1];
+        ti[n - 1] = -sjp[i - 1];
+        for (int j = 1; j <= m; ++j) t[j] = ti[j] = S[size_t(i - 1) * m + j - 1];
+    }
+}
+
+// End eigenvalue of AR(A) (Section 3): the corner entry z_1 + 2 sum_{k>=2} z_k,
+// with z the generator of the tau matrix s(A_in) = S diag(mu) S, is linear in
+// mu.  For mu = e_j the first column of S diag(e_j) S is c_k = S_kj S_1j, and
+// c_k = z_k - z_{k+2} gives z from the last entry up.
+std::vector<double> ar_end_weights(int n) {
+    const int m = n - 2;
+    const double sc = std::sqrt(2.0 / (m + 1));
+    std::vector<double> w(m), z(m + 2);
+    for (int j = 0; j < m; ++j) {
+        const double s1 = sc * sin_pi_frac(j + 1, m + 1);
+        z[m] = z[m + 1] = 0.0;
+        for (int k = m - 1; k >= 0; --k) z[k] = sc * sin_pi_frac((long long)(k + 1) * (j + 1), m + 1) * s1 + z[k + 2];
+        double acc = 0.0;
+        for (int k = 1; k < m; ++k) acc += z[k];
+        w[j] = z[0] + 2.0 * acc;
+    }
+    return w;
+}
+
 std::vector<double> basis_matrix(int n, int bc) {
     std::vector<double> P(size_t(n) * n, 0.0);
     if (bc == 1) {  // DCT-II: phi_k(i) = sqrt((2 - [k=0])/n) cos(pi k (2i+1) / (2n))

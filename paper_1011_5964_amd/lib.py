@@ -21,6 +21,8 @@ ERRORS = {-1: "TVD_EINVAL", -2: "TVD_ENOTSYM", -3: "TVD_ENORM", -4: "TVD_ESIZE",
 PRECISION = {"f64": 0, "f32_mixed": 1}
 BC = {"reflective": 1, "antireflective": 2}
 PRECOND = {"none": 0, "diag": 1, "x": 2, "d_x": 3, "x_d": 4}
+# reblurring preconditioners P, D_P, P_D (Section 3) on the same enum slots
+REBLUR_PRECOND = {"p": 2, "d_p": 3, "p_d": 4}
 EXPORT = {"kappa": 0, "s": 1, "mu": 2, "lambda_h": 3, "d": 4}
 MAX_OUTER = 256
 KTIME_KINDS = 12
@@ -34,6 +36,8 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_get_kernel_times", "tvdeblur_solve_adjoint", "tvdeblur_batch_create", "tvdeblur_batch_solve",
     "tvdeblur_batch_get_info", "tvdeblur_batch_destroy", "tvdeblur_batch_last_error",
     "tvdeblur_set_transform", "tvdeblur_get_transform", "tvdeblur_time_kernel",
+    "tvdeblur_solve_reblur", "tvdeblur_op_reblur_setup", "tvdeblur_op_reblur_normal",
+    "tvdeblur_op_reblur_precond",
 )
 BATCH_PRECOND = ("x", "d_x", "x_d")
 
@@ -121,6 +125,10 @@ def load():
         "tvdeblur_op_setup": [vp, vp, d, d, i],
         "tvdeblur_op_normal": [vp, vp, vp],
         "tvdeblur_op_precond": [vp, vp, vp],
+        "tvdeblur_solve_reblur": [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Stats)],
+        "tvdeblur_op_reblur_setup": [vp, vp, d, d, i],
+        "tvdeblur_op_reblur_normal": [vp, vp, vp],
+        "tvdeblur_op_reblur_precond": [vp, vp, vp],
         "tvdeblur_op_export": [vp, i, vp],
         "tvdeblur_set_profiling": [vp, i],
         "tvdeblur_get_kernel_times": [vp, ctypes.POINTER(KernelTimes)],
@@ -200,15 +208,11 @@ class TVDeblur:
     def set_bc(self, bc):
         self._check(self.lib.tvdeblur_set_bc(self.h, BC[bc]))
 
-    def solve(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="x_d", fp_tol=0.0,
-              u0=None, replay=None, iterates=None, out=None):
-        import torch
-        self._img(v, "v")
-        u = out if out is not None else torch.empty_like(v)
+    def _params(self, alpha, beta, max_outer, inner_tol, max_inner, precond_code, fp_tol, u0, replay, iterates):
         p = Params()
         p.alpha, p.beta, p.max_outer = float(alpha), float(beta), int(max_outer)
         p.fp_tol, p.inner_tol, p.max_inner = float(fp_tol), float(inner_tol), int(max_inner)
-        p.precond = PRECOND[precond]
+        p.precond = precond_code
         p.u0_dev = None if u0 is None else self._img(u0, "u0").data_ptr()
         keep = None
         if replay is not None:
@@ -218,9 +222,38 @@ class TVDeblur:
             if iterates.dtype != self.dtype or iterates.numel() < (max_outer + 1) * self.ny * self.nx:
                 raise ValueError("iterates buffer too small")
             p.iterates_dev = iterates.data_ptr()
+        return p, keep
+
+    def solve(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="x_d", fp_tol=0.0,
+              u0=None, replay=None, iterates=None, out=None):
+        import torch
+        self._img(v, "v")
+        u = out if out is not None else torch.empty_like(v)
+        p, keep = self._params(alpha, beta, max_outer, inner_tol, max_inner, PRECOND[precond], fp_tol, u0,
+                               replay, iterates)
         st = Stats()
         with torch.cuda.device(self.device):
             rc = self.lib.tvdeblur_solve(self.h, _ptr(v), _ptr(u), ctypes.byref(p), ctypes.byref(st))
+        del keep
+        self._check(rc)
+        return u, st.to_dict()
+
+    def solve_reblur(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="p_d", fp_tol=0.0,
+                     u0=None, replay=None, iterates=None, out=None):
+        """The reblurring system (H'H + alpha L(u^k)) u^{k+1} = H'v by
+        PBiCGstab with P, D_P or P_D ('p', 'd_p', 'p_d'); see
+        tvdeblur_solve_reblur.  inner_iters counts BiCGstab iterations."""
+        import torch
+        self._img(v, "v")
+        if precond not in REBLUR_PRECOND:
+            raise ValueError(f"precond must be one of {sorted(REBLUR_PRECOND)}")
+        u = out if out is not None else torch.empty_like(v)
+        p, keep = self._params(alpha, beta, max_outer, inner_tol, max_inner, REBLUR_PRECOND[precond], fp_tol, u0,
+                               replay, iterates)
+        st = Stats()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_solve_reblur(self.h, _ptr(v), _ptr(u), ctypes.byref(p), ctypes.byref(st))
+        del keep
         self._check(rc)
         return u, st.to_dict()
 
@@ -304,6 +337,21 @@ class TVDeblur:
 
     def normal(self, x):
         return self._op(self.lib.tvdeblur_op_normal, x, "x")
+
+    def reblur_setup(self, uk, alpha, beta, precond="p_d"):
+        import torch
+        self._img(uk, "uk")
+        if precond not in REBLUR_PRECOND:
+            raise ValueError(f"precond must be one of {sorted(REBLUR_PRECOND)}")
+        with torch.cuda.device(self.device):
+            self._check(self.lib.tvdeblur_op_reblur_setup(self.h, _ptr(uk), float(alpha), float(beta),
+                                                          REBLUR_PRECOND[precond]))
+
+    def reblur_normal(self, x):
+        return self._op(self.lib.tvdeblur_op_reblur_normal, x, "x")
+
+    def reblur_precond(self, r):
+        return self._op(self.lib.tvdeblur_op_reblur_precond, r, "r")
 
     def precond(self, r):
         return self._op(self.lib.tvdeblur_op_precond, r, "r")

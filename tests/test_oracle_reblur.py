@@ -138,6 +138,18 @@ def test_AR_lies_in_the_algebra(sym, n):
     np.testing.assert_allclose(B[0, 0], end, atol=1e-13)
 
 
+@pytest.mark.parametrize("n", [5, 9, 40, 130])
+def test_end_weights_reproduce_constants(n):
+    """AR(.) of the identity is the identity (the identity is in the algebra),
+    so the end eigenvalue of mu = 1 is 1: the weights sum to 1.  They
+    extrapolate to y = 0 and alternate, with absolute sum n - 2."""
+    w = RB.ar_end_weights(n)
+    assert abs(w.sum() - 1.0) < 1e-12
+    # the generator recursion and the corner sum accumulate O(n^2) roundings
+    np.testing.assert_allclose(RB.ar_projection(np.eye(n)), np.eye(n), atol=2 * n * n * np.finfo(float).eps)
+    assert abs(np.abs(w).sum() - (n - 2)) < 1e-9 * n
+
+
 def test_level2_projection_is_in_the_2d_algebra():
     """AR_2(L) = Q AR_1(Q^T AR_1(L) Q) Q^T (Section 3.2) is diagonalised by
     T2, with the eigenvalues of ar_extend_eigs on the interior S^-projection."""
