@@ -337,10 +337,21 @@ def reblur_form(args, pcg_iters_per_solve):
         its = int(st["total_inner_iters"])
         res[prec] = {"restore_time_s": t, "bicgstab_iters_per_solve": its,
                      "bicgstab_iters_per_s": its / t,
+                     "per_iteration_us": 1e6 * st["time_inner_s"] / max(its, 1),
+                     "setup_share": st["time_setup_s"] / max(st["time_total_s"], 1e-12),
                      "iters_per_step": st["inner_iters"][:st["outer_steps"]],
                      "all_converged": bool(st["all_converged"]),
                      "operator_products_per_solve": 2 * its,
                      "restoration_error": rel2(last["u"].double().cpu().numpy(), p.u_true)}
+        # per-class launch durations from one more, untimed solve with sampled kernel timing
+        h.set_profiling(PROFILE_EVERY)
+        run()
+        torch.cuda.synchronize()
+        kt = h.kernel_times()
+        h.set_profiling(False)
+        res[prec]["kernel_classes"] = {k: {"launches_sampled": v["launches"],
+                                           "avg_us": 1e3 * v["total_ms"] / v["launches"]}
+                                       for k, v in kt.items() if v["launches"] > 0}
         if prec == "f32_mixed":
             u3, s3 = h.solve_reblur(v, p.alpha, p.beta, 3, p.inner_tol, p.max_inner, "p_d")
             slot["u3"] = u3.double().cpu().numpy()

@@ -1302,7 +1302,7 @@ class Solver final : public SolverBase {
                 TVD_HIP(hipStreamSynchronize(s_));
                 timer_.harvest();
                 if (host_st_->done) break;
-                next_poll = it + 1;
+                next_poll = it + 2;
             }
         }
         int nfp = 0;

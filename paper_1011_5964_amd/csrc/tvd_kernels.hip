@@ -2472,22 +2472,37 @@ __global__ void __launch_bounds__(256) k_ar_ext_cols(int ny, int nx, const doubl
     }
 }
 
+// Row pass: a block takes 16 columns; its 16 row groups each sum every 16th
+// interior row (independent loads), then one group adds the 16 partials.
+constexpr int kArCols = 16, kArGroups = 16;
 __global__ void __launch_bounds__(256) k_ar_ext_rows(int ny, int nx, const double* __restrict__ wy, double* l0,
                                                      double* l1, double* l2) {
+    __shared__ double part[kArGroups][kArCols + 1];
     double* lam = blockIdx.y == 0 ? l0 : (blockIdx.y == 1 ? l1 : l2);
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (!lam || j >= nx) return;
+    if (!lam) return;
+    const int c = threadIdx.x % kArCols, g = threadIdx.x / kArCols;
+    const int j = blockIdx.x * kArCols + c;
     double acc = 0.0;
-    for (int i = 1; i < ny - 1; ++i) acc += wy[i - 1] * lam[size_t(i) * nx + j];
-    lam[j] = acc;
-    lam[size_t(ny - 1) * nx + j] = acc;
+    if (j < nx) {
+#pragma unroll 8
+        for (int i = 1 + g; i < ny - 1; i += kArGroups) acc += wy[i - 1] * lam[size_t(i) * nx + j];
+    }
+    part[g][c] = acc;
+    __syncthreads();
+    if (g == 0 && j < nx) {
+        double sum = 0.0;
+        for (int k = 0; k < kArGroups; ++k) sum += part[k][c];
+        lam[j] = sum;
+        lam[size_t(ny - 1) * nx + j] = sum;
+    }
 }
 
 hipError_t launch_ar_extend(int ny, int nx, const double* wy, const double* wx, double* l0, double* l1,
                             double* l2, hipStream_t s) {
     if (ny < 3 || nx < 3) return hipErrorInvalidValue;
     tvd_launch(k_ar_ext_cols, dim3(ny - 2, 3), dim3(256), 0, s, ny, nx, wx, l0, l1, l2);
-    tvd_launch(k_ar_ext_rows, dim3((nx + 255) / 256, 3), dim3(256), 0, s, ny, nx, wy, l0, l1, l2);
+    tvd_launch(k_ar_ext_rows, dim3((nx + kArCols - 1) / kArCols, 3), dim3(kArCols * kArGroups), 0, s, ny, nx, wy,
+               l0, l1, l2);
     return hipGetLastError();
 }
 
