@@ -182,7 +182,9 @@ const char* tvdeblur_last_error(tvdeblur_t h);
  * products; the test ||r_i|| < inner_tol ||r_0|| runs once per iteration, on
  * the updated residual.  p->replay_host runs exactly the given counts.
  * Requirements: anti-reflective BC (set_bc), a separable PSF (h = g_y g_x^T)
- * of half-widths <= 16, precond one of the three above.
+ * of half-widths <= 16, precond one of the three above.  The preconditioner
+ * always runs as matrix-core products with T^{-1} and T (the handle's
+ * transform setting applies to tvdeblur_solve only).
  * Errors: TVD_EINVAL (also for an unsupported BC / PSF / preconditioner),
  * TVD_ESTATE, TVD_ESIZE, TVD_EDEVICE, TVD_ENOMEM, TVD_EBREAKDOWN (rho,
  * <rhat, v> or omega became 0; u_dev then holds the last iterate). */
