@@ -182,3 +182,53 @@ def test_reblur_full_size(prec):
     u, st = h.solve_reblur(dev(vq, prec), p.alpha, p.beta, 1, p.inner_tol, p.max_inner, "p_d",
                            replay=so["inner_iters"])
     assert rel2(host(u), uo) < TOL_SOLVE[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("shape", [(3, 5), (4, 4), (5, 3), (6, 17)])
+def test_reblur_smallest_images(shape, prec):
+    """The smallest images a handle takes (n >= 3; one interior frequency when
+    n = 3), 3 x 3 PSF: replayed solve against the oracle."""
+    print(f"case reblur small {shape} {prec}", flush=True)
+    rng = np.random.default_rng(sum(shape))
+    psf = synth.gaussian_psf(3, 0.8)
+    v = O.blur(rng.random(shape), psf, AR) + 0.01 * rng.standard_normal(shape)
+    vq = host(dev(v, prec))
+    uo, so = RB.fp_solve_reblur(vq, psf, 1e-2, 0.1, 3, 1e-6, 50, "p_d")
+    h = make(shape, psf, prec)
+    u, st = h.solve_reblur(dev(vq, prec), 1e-2, 0.1, 3, 1e-6, 50, "p_d", replay=so["inner_iters"])
+    assert st["inner_iters"][:3] == so["inner_iters"]
+    assert rel2(host(u), uo) < TOL_SOLVE[prec]
+
+
+def test_reblur_zero_counts_and_zero_residual():
+    """A replayed count of 0 leaves u^k; alpha = 0 with the identity PSF makes
+    u^0 = v the exact solution (zero initial residual, no iteration)."""
+    rng = np.random.default_rng(4)
+    shape = (20, 24)
+    v = dev(rng.random(shape), "f64")
+    h = make(shape, synth.gaussian_psf(5, 1.0), "f64")
+    u, st = h.solve_reblur(v, 1e-3, 0.1, 2, replay=[0, 0])
+    assert st["inner_iters"][:2] == [0, 0]
+    np.testing.assert_array_equal(host(u), host(v))
+    h1 = make(shape, np.ones((1, 1)), "f64")
+    u1, st1 = h1.solve_reblur(v, 0.0, 0.1, 2)
+    assert st1["inner_iters"][:2] == [0, 0] and st1["all_converged"]
+    np.testing.assert_array_equal(host(u1), host(v))
+
+
+def test_reblur_and_normal_solves_share_a_handle():
+    """A handle alternates between the two systems: each solve matches a
+    fresh handle's (the reblurring setup must not leak into the normal one)."""
+    p = synth.small_problem(n=40, psf_size=7, sigma=1.2, n_outer=3)
+    v = dev(p.v, "f64")
+    h = make(p.v.shape, p.psf, "f64")
+    un, sn = h.solve(v, p.alpha, p.beta, 3, p.inner_tol, p.max_inner, "x_d")
+    ur, sr = h.solve_reblur(v, p.alpha, p.beta, 3, p.inner_tol, p.max_inner, "p_d")
+    un2, sn2 = h.solve(v, p.alpha, p.beta, 3, p.inner_tol, p.max_inner, "x_d")
+    assert sn2["inner_iters"] == sn["inner_iters"]
+    np.testing.assert_array_equal(host(un2), host(un))
+    fresh = make(p.v.shape, p.psf, "f64")
+    ur2, sr2 = fresh.solve_reblur(v, p.alpha, p.beta, 3, p.inner_tol, p.max_inner, "p_d")
+    assert sr2["inner_iters"] == sr["inner_iters"]
+    np.testing.assert_array_equal(host(ur2), host(ur))
