@@ -362,6 +362,51 @@ def reblur_form(args, pcg_iters_per_solve):
     return res, slot
 
 
+TABLE_ALPHAS = [1.0, 1e-1, 1e-2, 1e-3, 1e-4]
+
+
+def tables_form(args):
+    """The paper's 2D iteration table on a synthetic image: for each alpha the
+    number of fixed-point steps N (stop at a relative change below 1e-4, at
+    most 100 steps, beta = 0.01) and the average Krylov iterations per step,
+    for PCG on the normal equations under reflective BCs (I, D_R, R_D) and
+    anti-reflective BCs (I, D_M, M_D), and PBiCGstab on the reblurring system
+    (I, D_P, P_D); FP64.  '*' marks a column where a step hit max_inner."""
+    import torch
+    from paper_1011_5964_amd import synth
+    from paper_1011_5964_amd.lib import TVDeblur
+    res = {"workload": "256x256 piecewise-constant phantom (32 shapes, seed of c2), 15x15 Gaussian PSF sigma 2.5, "
+                       "1% noise, beta 0.01, FP stop ||u^k - u^{k-1}|| / ||u^k|| < 1e-4, at most 100 FP steps, "
+                       "inner tol 1e-6, max_inner 2000, FP64",
+           "alphas": TABLE_ALPHAS}
+    columns = [("pcg_reflective", "reflective", "solve", ("none", "d_x", "x_d")),
+               ("pcg_antireflective", "antireflective", "solve", ("none", "d_x", "x_d")),
+               ("pbicgstab_reblur", "antireflective", "solve_reblur", ("none", "d_p", "p_d"))]
+    t0 = time.perf_counter()
+    for name, bc, fn, precs in columns:
+        p = synth.config("c2_r" if bc == "reflective" else "c2_ar")
+        v = torch.tensor(p.v, dtype=torch.float64, device="cuda")
+        h = TVDeblur(*p.v.shape, "f64")
+        h.set_psf(p.psf)
+        h.set_bc(bc)
+        rows = []
+        for a in TABLE_ALPHAS:
+            row = {}
+            for pc in precs:
+                try:
+                    _, st = getattr(h, fn)(v, a, 0.01, 100, 1e-6, 2000, pc, fp_tol=1e-4)
+                    n = st["outer_steps"]
+                    row[pc] = {"N": n, "avg_iters": round(st["total_inner_iters"] / max(n, 1), 1),
+                               "converged": bool(st["all_converged"])}
+                except Exception as e:  # a breakdown is reported, not fatal
+                    row[pc] = {"error": str(e)[:80]}
+            rows.append(row)
+        res[name] = rows
+        h.close()
+    res["wall_s"] = time.perf_counter() - t0
+    return res
+
+
 def diff_form(args, f64_restore_s):
     """Forward (with checkpoints) and forward + adjoint on the 512^2
     differentiation workload, FP32-mixed."""
@@ -406,7 +451,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="all",
-                    help="comma list of forms measured beside the headline: f64, batch, diff, sweep; 'all' or 'none'")
+                    help="comma list of forms measured beside the headline: f64, batch, diff, sweep, reblur "
+                         "('all' = these five), tables (iteration tables, only when named); or 'none'")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="fixed-point steps of the oracle CPU sample (0 = skip the oracle)")
     ap.add_argument("--transform", choices=("auto", "fft", "gemm"), default="auto",
@@ -476,6 +522,9 @@ def main():
     if "sweep" in sel:
         print("[bench] alpha sweep (both boundary conditions)", file=sys.stderr, flush=True)
         forms["alpha_sweep"], sweep_slot = sweep_form(args)
+    if "tables" in sel:
+        print("[bench] iteration tables (normal equations and reblurring system)", file=sys.stderr, flush=True)
+        forms["tables"] = tables_form(args)
     reblur_slot = None
     if "reblur" in sel:
         print("[bench] reblurring system (PBiCGstab)", file=sys.stderr, flush=True)

@@ -168,8 +168,11 @@ const char* tvdeblur_last_error(tvdeblur_t h);
  * PSF being quadrantally symmetric) and L(u^k) the zero-Neumann TV operator.
  * The system is not symmetric; each step runs preconditioned BiCGstab (van
  * der Vorst 1992) warm-started at u^k, with the reblurring preconditioners of
- * Section 3 / Section 3.2 in the algebra of T_n (x) T_n (Section 2):
- *   precond TVD_PREC_X   -> P   = H'H + alpha AR_2(L(u^k))
+ * Section 3 / Section 3.2 in the algebra of T_n (x) T_n (Section 2), or the
+ * plain ones of the paper's tables:
+ *   precond TVD_PREC_NONE -> I (no preconditioner)
+ *           TVD_PREC_DIAG -> D = I + alpha diag(L(u^k)) (eq. (D))
+ *           TVD_PREC_X   -> P   = H'H + alpha AR_2(L(u^k))
  *           TVD_PREC_D_X -> D_P = D^{1/2} P D^{1/2}
  *           TVD_PREC_X_D -> P_D for the scaled system eq. (scalereb), applied
  *                           to eq. (fpp) as D^{1/2} P_D D^{1/2}
@@ -182,8 +185,7 @@ const char* tvdeblur_last_error(tvdeblur_t h);
  * products; the test ||r_i|| < inner_tol ||r_0|| runs once per iteration, on
  * the updated residual.  p->replay_host runs exactly the given counts.
  * Requirements: anti-reflective BC (set_bc), a separable PSF (h = g_y g_x^T)
- * of half-widths <= 16, precond one of the three above.  The preconditioner
- * always runs as matrix-core products with T^{-1} and T (the handle's
+ * of half-widths <= 16.  The P / D_P / P_D solves always run as matrix-core products with T^{-1} and T (the handle's
  * transform setting applies to tvdeblur_solve only).
  * Errors: TVD_EINVAL (also for an unsupported BC / PSF / preconditioner),
  * TVD_ESTATE, TVD_ESIZE, TVD_EDEVICE, TVD_ENOMEM, TVD_EBREAKDOWN (rho,
@@ -191,7 +193,7 @@ const char* tvdeblur_last_error(tvdeblur_t h);
 int tvdeblur_solve_reblur(tvdeblur_t h, const void* v_dev, void* u_dev,
                           const tvd_params* p, tvd_stats* stats);
 
-/* Setup of the reblurring preconditioner (P, D_P or P_D as above) from uk_dev;
+/* Setup of the reblurring preconditioner (any of the five above) from uk_dev;
  * tvdeblur_op_export then returns its kappa, s, mu, lambda_H and D. */
 int tvdeblur_op_reblur_setup(tvdeblur_t h, const void* uk_dev, double alpha, double beta, int precond);
 

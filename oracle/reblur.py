@@ -25,6 +25,8 @@ from .precond import diagonal_eigs, weighted_laplacian_eigs
 from .transforms import psf_symbol_eigenvalues
 
 REBLUR_VARIANTS = ("p", "d_p", "p_d")
+# with the plain preconditioners of the paper's tables (I and D)
+REBLUR_ALL_VARIANTS = ("none", "diag") + REBLUR_VARIANTS
 
 
 def _sine_matrix(m):
@@ -210,8 +212,10 @@ def reblur_apply(p, h, kap, alpha):
 
 
 def reblur_precond_setup(kap, alpha, lam_h, variant="p_d"):
-    """Scaling s and eigenvalues mu of P, D_P or P_D (Section 3 and the end
-    of Section 3.2), all in the algebra of T2:
+    """Setup of the preconditioner: 'none' (I) and 'diag' (D = I + alpha
+    diag(L), eq. (D)) as in the paper's tables, or the scaling s and
+    eigenvalues mu of P, D_P or P_D (Section 3 and the end of Section 3.2),
+    all in the algebra of T2:
       'p'    P   = H'H + alpha AR_2(L):            s = 1,      mu = lam_H^2 + alpha lam_L
       'd_p'  D_P = D^{1/2} P D^{1/2}:              s = D^{-1/2}, mu as P
       'p_d'  P_D for the scaled system (scalereb): s = D^{-1/2},
@@ -221,12 +225,16 @@ def reblur_precond_setup(kap, alpha, lam_h, variant="p_d"):
     The interior eigenvalues of AR_2(.) are those of the level-2 tau
     projection of the operator's inner block, which equal the interior
     entries of the S^-projection (S^ is zero off the interior there)."""
-    if variant not in REBLUR_VARIANTS:
+    if variant not in REBLUR_ALL_VARIANTS:
         raise ValueError(f"unknown reblurring preconditioner {variant!r}")
     kap = np.asarray(kap, dtype=np.float64)
     ny, nx = kap.shape
     D = 1.0 + alpha * tv_diagonal(kap)
     ones = np.ones_like(kap)
+    if variant == "none":                     # I
+        return {"variant": variant}
+    if variant == "diag":                     # D = I + alpha diag(L), eq. (D)
+        return {"variant": variant, "d": D}
 
     def ar2(lam_hat):
         return ar_extend_eigs(lam_hat[1:ny - 1, 1:nx - 1], ny, nx)
@@ -268,7 +276,11 @@ def reblur_precond_setup_dense(kap, alpha, h, variant="p_d"):
 
 
 def reblur_precond_apply(r, setup):
-    """z = M^{-1} r = s o T2[(T2^{-1}(s o r)) / mu]."""
+    """z = M^{-1} r: r (I), r / D (D), or s o T2[(T2^{-1}(s o r)) / mu]."""
+    if setup["variant"] == "none":
+        return np.array(r, dtype=np.float64, copy=True)
+    if setup["variant"] == "diag":
+        return np.asarray(r, dtype=np.float64) / setup["d"]
     s = setup["s"]
     return s * ar_synthesis_2d(ar_coefficients_2d(s * np.asarray(r, dtype=np.float64)) / setup["mu"])
 

@@ -1244,7 +1244,10 @@ class Solver final : public SolverBase {
             timer_.end(s_);
         }
     }
-    BcgArgs<T> bcg_args(int it) const {
+    // I, D (no transform): the stages write M^{-1} p and M^{-1} s straight
+    // into p^ and s^; P, D_P, P_D: into the products' input.
+    bool reblur_transform() const { return variant_ >= TVD_PREC_X; }
+    BcgArgs<T> bcg_args(int it, int stage) const {
         BcgArgs<T> a{};
         a.n = int(N_);
         a.iter = it;
@@ -1257,8 +1260,9 @@ class Solver final : public SolverBase {
         a.t = Tv_;
         a.phat = Ph_;
         a.shat = Sh_;
-        a.sc = (variant_ == TVD_PREC_X) ? nullptr : Sap_;
-        a.tin = T2_;
+        // scaling: 1/D for D, D^{-1/2} for D_P and P_D, none for I and P
+        a.sc = (variant_ == TVD_PREC_X || variant_ == TVD_PREC_NONE) ? nullptr : Sap_;
+        a.tin = reblur_transform() ? T2_ : (stage == 1 ? Ph_ : Sh_);
         a.rr_in = bcg_rr_;
         a.rho_in = bcg_rho_;
         a.n_in = nb_bcg_;
@@ -1274,16 +1278,17 @@ class Solver final : public SolverBase {
     }
     void bcg_stage(int it, int stage) {
         timer_.begin(KernelTimer::kUpdate, s_);
-        TVD_HIP(launch_bcg<T>(bcg_args(it), stage, s_, nullptr));
+        TVD_HIP(launch_bcg<T>(bcg_args(it, stage), stage, s_, nullptr));
         timer_.end(s_);
     }
     // One BiCGstab iteration: 2 preconditioner solves, 2 operator products.
     void bcg_iteration(int it) {
+        const bool tr = reblur_transform();
         bcg_stage(it, 1);
-        products_reblur(it, Ph_);
+        if (tr) products_reblur(it, Ph_);
         ypass_reblur(it, Ph_, Vv_, Rh_, y_sig_, nullptr);
         bcg_stage(it, 2);
-        products_reblur(it, Sh_);
+        if (tr) products_reblur(it, Sh_);
         ypass_reblur(it, Sh_, Tv_, Sv_, y_ts_, y_tt_);
         bcg_stage(it, 3);
     }
@@ -1314,7 +1319,6 @@ class Solver final : public SolverBase {
         setup(uk, alpha, beta, variant);
     }
     void solve_reblur(const void* vv, void* uu, const tvd_params& p, tvd_stats& st) override {
-        if (p.precond < TVD_PREC_X) throw ApiError{TVD_EINVAL, "the reblurring system takes P, D_P or P_D"};
         ensure_reblur();
         const auto t0 = std::chrono::steady_clock::now();
         const T* v = static_cast<const T*>(vv);
@@ -1372,7 +1376,6 @@ class Solver final : public SolverBase {
         if (st.breakdown) throw ApiError{TVD_EBREAKDOWN, "BiCGstab breakdown: rho, <rhat, v> or omega = 0"};
     }
     void op_reblur_setup(const void* uk, double alpha, double beta, int variant) override {
-        if (variant < TVD_PREC_X) throw ApiError{TVD_EINVAL, "the reblurring system takes P, D_P or P_D"};
         ensure_reblur();
         reblur_setup(static_cast<const T*>(uk), alpha, beta, variant);
         TVD_HIP(hipStreamSynchronize(s_));
@@ -1388,8 +1391,13 @@ class Solver final : public SolverBase {
     void op_reblur_precond(const void* r, void* z) override {
         if (!have_setup_ || !reblur_mode_) throw ApiError{TVD_ESTATE, "op_reblur_precond before op_reblur_setup"};
         TVD_HIP(launch_init_state(st_, 0.0, s_));
-        upd_launch(0, false, static_cast<const T*>(r));
-        products_reblur(0, static_cast<T*>(z));
+        if (variant_ == TVD_PREC_NONE) {
+            TVD_HIP(hipMemcpyAsync(z, r, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        } else {
+            upd_launch(0, false, static_cast<const T*>(r));  // T2_ = s o r (s = 1/D for D)
+            if (reblur_transform()) products_reblur(0, static_cast<T*>(z));
+            else TVD_HIP(hipMemcpyAsync(z, T2_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        }
         TVD_HIP(hipStreamSynchronize(s_));
         timer_.harvest();
     }
@@ -2848,8 +2856,7 @@ int tvdeblur_solve_reblur(tvdeblur_t h, const void* v_dev, void* u_dev, const tv
     if (p->max_outer < 1 || p->max_outer > TVD_MAX_OUTER) return fail(h, TVD_EINVAL, "max_outer out of range");
     if (p->max_inner < 1 || !(p->inner_tol >= 0) || !(p->fp_tol >= 0))
         return fail(h, TVD_EINVAL, "bad inner_tol / max_inner / fp_tol");
-    if (p->precond < TVD_PREC_X || p->precond > TVD_PREC_X_D)
-        return fail(h, TVD_EINVAL, "the reblurring system takes TVD_PREC_X, TVD_PREC_D_X or TVD_PREC_X_D");
+    if (p->precond < TVD_PREC_NONE || p->precond > TVD_PREC_X_D) return fail(h, TVD_EINVAL, "bad preconditioner");
     if (p->replay_host)
         for (int k = 0; k < p->max_outer; ++k)
             if (p->replay_host[k] < 0) return fail(h, TVD_EINVAL, "negative replay count");
@@ -2866,8 +2873,7 @@ int tvdeblur_op_reblur_setup(tvdeblur_t h, const void* uk_dev, double alpha, dou
     if (!h || !uk_dev) return fail(h, TVD_EINVAL, "NULL argument");
     if (!std::isfinite(alpha) || alpha < 0 || !std::isfinite(beta) || !(beta > 0))
         return fail(h, TVD_EINVAL, "alpha must be >= 0 and beta > 0, both finite");
-    if (precond < TVD_PREC_X || precond > TVD_PREC_X_D)
-        return fail(h, TVD_EINVAL, "the reblurring system takes TVD_PREC_X, TVD_PREC_D_X or TVD_PREC_X_D");
+    if (precond < TVD_PREC_NONE || precond > TVD_PREC_X_D) return fail(h, TVD_EINVAL, "bad preconditioner");
     return guarded(h, [&]() {
         int rc = ensure_built(h);
         if (rc) return rc;

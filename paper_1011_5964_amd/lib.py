@@ -21,8 +21,9 @@ ERRORS = {-1: "TVD_EINVAL", -2: "TVD_ENOTSYM", -3: "TVD_ENORM", -4: "TVD_ESIZE",
 PRECISION = {"f64": 0, "f32_mixed": 1}
 BC = {"reflective": 1, "antireflective": 2}
 PRECOND = {"none": 0, "diag": 1, "x": 2, "d_x": 3, "x_d": 4}
-# reblurring preconditioners P, D_P, P_D (Section 3) on the same enum slots
-REBLUR_PRECOND = {"p": 2, "d_p": 3, "p_d": 4}
+# preconditioners of the reblurring system: I, D and P, D_P, P_D (Section 3)
+# on the same enum slots
+REBLUR_PRECOND = {"none": 0, "diag": 1, "p": 2, "d_p": 3, "p_d": 4}
 EXPORT = {"kappa": 0, "s": 1, "mu": 2, "lambda_h": 3, "d": 4}
 MAX_OUTER = 256
 KTIME_KINDS = 12
@@ -241,7 +242,8 @@ class TVDeblur:
     def solve_reblur(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="p_d", fp_tol=0.0,
                      u0=None, replay=None, iterates=None, out=None):
         """The reblurring system (H'H + alpha L(u^k)) u^{k+1} = H'v by
-        PBiCGstab with P, D_P or P_D ('p', 'd_p', 'p_d'); see
+        PBiCGstab with I, D, P, D_P or P_D ('none', 'diag', 'p', 'd_p',
+        'p_d'); see
         tvdeblur_solve_reblur.  inner_iters counts BiCGstab iterations."""
         import torch
         self._img(v, "v")

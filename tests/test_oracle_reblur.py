@@ -302,3 +302,28 @@ def test_reblur_fixed_point_steps_solve_their_systems():
     r_end = np.linalg.norm(b - RB.reblur_apply(u2, h, kap, alpha))
     r_start = np.linalg.norm(b - RB.reblur_apply(u1, h, kap, alpha))
     assert st2["inner_iters"][1] > 0 and r_end < tol * r_start
+
+
+def test_plain_preconditioners_of_the_tables():
+    """I and D of the tables: I leaves r, D divides by 1 + alpha diag(L)
+    (diag(L) from the dense operator); PBiCGstab with D on the reblurring
+    system matches a direct solve."""
+    rng = np.random.default_rng(15)
+    ny, nx = 6, 7
+    kap = O.kappa(rng.random((ny, nx)), 0.1)
+    alpha = 0.05
+    r = rng.standard_normal((ny, nx))
+    st_i = RB.reblur_precond_setup(kap, alpha, None, "none")
+    np.testing.assert_array_equal(RB.reblur_precond_apply(r, st_i), r)
+    st_d = RB.reblur_precond_setup(kap, alpha, None, "diag")
+    Ld = O.dense_matrix(lambda x: O.tv_apply(kap, x), (ny, nx))
+    np.testing.assert_allclose(RB.reblur_precond_apply(r, st_d), r / (1 + alpha * np.diag(Ld).reshape(ny, nx)),
+                               rtol=1e-14)
+    h = quad_sym_psf(1, 1, rng)
+    A = O.dense_matrix(lambda p: RB.reblur_apply(p, h, kap, alpha), (ny, nx))
+    b = rng.standard_normal(ny * nx)
+    x, info = RB.pbicgstab(lambda p: RB.reblur_apply(p, h, kap, alpha),
+                           lambda q: RB.reblur_precond_apply(q, st_d), b.reshape(ny, nx), np.zeros((ny, nx)),
+                           1e-12, 200)
+    assert info["converged"]
+    np.testing.assert_allclose(x.ravel(), np.linalg.solve(A, b), atol=1e-10)
