@@ -1182,7 +1182,7 @@ class Solver final : public SolverBase {
     }
     // q = A'z (H H in the fused y-pass, + alpha L z) with <dotw, q> partials
     // (and <q, q> when qq is set).
-    void ypass_reblur(int it, const T* z, T* q, const T* dotw, double* pq, double* qq) {
+    void ypass_reblur(const T* z, T* q, const T* dotw, double* pq, double* qq) {
         YPassArgs<T> a{};
         a.ny = ny_;
         a.nx = nx_;
@@ -1200,7 +1200,6 @@ class Solver final : public SolverBase {
         a.khi = khiR_;
         a.dotw = dotw;
         a.qq_part = qq;
-        (void)it;
         int nb = 0;
         timer_.begin(KernelTimer::kBand, s_);
         TVD_HIP(launch_ypass_full_bcg<T>(a, s_, &nb));
@@ -1286,10 +1285,10 @@ class Solver final : public SolverBase {
         const bool tr = reblur_transform();
         bcg_stage(it, 1);
         if (tr) products_reblur(it, Ph_);
-        ypass_reblur(it, Ph_, Vv_, Rh_, y_sig_, nullptr);
+        ypass_reblur(Ph_, Vv_, Rh_, y_sig_, nullptr);
         bcg_stage(it, 2);
         if (tr) products_reblur(it, Sh_);
-        ypass_reblur(it, Sh_, Tv_, Sv_, y_ts_, y_tt_);
+        ypass_reblur(Sh_, Tv_, Sv_, y_ts_, y_tt_);
         bcg_stage(it, 3);
     }
     // One PBiCGstab solve: x (X_) from u^k (U_) to u^{k+1}; the stopping
@@ -1384,7 +1383,7 @@ class Solver final : public SolverBase {
     void op_reblur_normal(const void* x, void* y) override {
         if (!have_setup_ || !reblur_mode_) throw ApiError{TVD_ESTATE, "op_reblur_normal before op_reblur_setup"};
         TVD_HIP(launch_init_state(st_, 0.0, s_));
-        ypass_reblur(0, static_cast<const T*>(x), static_cast<T*>(y), static_cast<const T*>(x), y_sig_, nullptr);
+        ypass_reblur(static_cast<const T*>(x), static_cast<T*>(y), static_cast<const T*>(x), y_sig_, nullptr);
         TVD_HIP(hipStreamSynchronize(s_));
         timer_.harvest();
     }
