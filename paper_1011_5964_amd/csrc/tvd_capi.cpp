@@ -1298,12 +1298,27 @@ class Solver final : public SolverBase {
         TVD_HIP(hipMemcpyAsync(X_, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
         residual_reblur(X_, R_, rr_[0]);
         bcg_stage(0, 0);
+        // As in pcg: at a poll the host enqueues one more iteration before it
+        // waits for the state, so the GPU does not idle during the read; if
+        // the solve had already stopped, that iteration's kernels exit.
         int next_poll = std::max(2, predicted);
+        bool ahead = false;
         for (int it = 1; it <= maxit; ++it) {
-            bcg_iteration(it);
+            if (ahead) {
+                ahead = false;
+            } else {
+                bcg_iteration(it);
+            }
             if (it == next_poll && it < maxit) {
                 TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
-                TVD_HIP(hipStreamSynchronize(s_));
+                if (!timer_.on()) {
+                    TVD_HIP(hipEventRecord(ev_poll_, s_));
+                    bcg_iteration(it + 1);
+                    ahead = true;
+                    TVD_HIP(hipEventSynchronize(ev_poll_));
+                } else {
+                    TVD_HIP(hipStreamSynchronize(s_));
+                }
                 timer_.harvest();
                 if (host_st_->done) break;
                 next_poll = it + 2;
