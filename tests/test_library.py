@@ -99,3 +99,25 @@ def test_alpha_sweep_rejects_bad_alphas_without_gpu():
     for bad in ([], [1e-3, 0.0], [1e-3, -1e-3], [float("nan")], [float("inf")]):
         with pytest.raises(ValueError):
             L.AlphaSweep((16, 16), [[1.0]], "antireflective", bad)
+
+
+def test_preconditioner_maps_match_header():
+    """The binding's names map onto the header's TVD_PREC_* values (the
+    reblurring names reuse the same slots: I, D, P, D_P, P_D)."""
+    with open(os.path.join(ROOT, "include", "tvdeblur.h")) as f:
+        defs = dict(re.findall(r"#define (TVD_PREC_[A-Z_]+)\s+(\d+)", f.read()))
+    c = {k: int(v) for k, v in defs.items()}
+    assert L.PRECOND == {"none": c["TVD_PREC_NONE"], "diag": c["TVD_PREC_DIAG"], "x": c["TVD_PREC_X"],
+                         "d_x": c["TVD_PREC_D_X"], "x_d": c["TVD_PREC_X_D"]}
+    assert L.REBLUR_PRECOND == {"none": c["TVD_PREC_NONE"], "diag": c["TVD_PREC_DIAG"], "p": c["TVD_PREC_X"],
+                                "d_p": c["TVD_PREC_D_X"], "p_d": c["TVD_PREC_X_D"]}
+
+
+@pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="library not built")
+def test_reblur_entry_points_reject_null_without_gpu():
+    lib = L.load()
+    assert lib.tvdeblur_solve_reblur(None, None, None, None, None) == -1
+    assert lib.tvdeblur_op_reblur_setup(None, None, 1e-3, 0.1, 4) == -1
+    assert lib.tvdeblur_op_reblur_normal(None, None, None) == -1
+    assert lib.tvdeblur_op_reblur_precond(None, None, None) == -1
+    assert b"NULL" in lib.tvdeblur_last_error(None)
