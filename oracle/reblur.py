@@ -353,8 +353,8 @@ def fp_solve_reblur(v, h, alpha, beta, n_outer, inner_tol=1e-6, max_inner=100,
                     variant="p_d", fp_tol=0.0, u0=None, replay=None):
     """Lagged-diffusivity fixed point on the reblurring system, eq. (fpp):
         (H'H + alpha L(u^k)) u^{k+1} = H' v,   u^0 = v,
-    each step by PBiCGstab warm-started at u^k with P, D_P or P_D built from
-    kappa(u^k).  Stopping and replay as fp_solve."""
+    each step by PBiCGstab warm-started at u^k with I, D, P, D_P or P_D built
+    from kappa(u^k).  Stopping and replay as fp_solve."""
     v = np.asarray(v, dtype=np.float64)
     ny, nx = v.shape
     lam_h = psf_symbol_eigenvalues(h, ny, nx, BC_ANTIREFLECTIVE)
