@@ -327,3 +327,22 @@ def test_plain_preconditioners_of_the_tables():
                            1e-12, 200)
     assert info["converged"]
     np.testing.assert_allclose(x.ravel(), np.linalg.solve(A, b), atol=1e-10)
+
+
+@pytest.mark.parametrize("variant", RB.REBLUR_ALL_VARIANTS)
+def test_one_reblur_step_equals_a_dense_solve(variant):
+    """One fixed-point step (tight tolerance) equals the direct solution of
+    the dense system (H'H + alpha L(v)) u = H'v built from the blur and the
+    TV operator, for every preconditioner."""
+    rng = np.random.default_rng(16)
+    ny, nx = 7, 9
+    h = quad_sym_psf(1, 1, rng)
+    v = O.blur(rng.random((ny, nx)), h, AR) + 0.01 * rng.standard_normal((ny, nx))
+    alpha, beta = 0.03, 0.1
+    u, st = RB.fp_solve_reblur(v, h, alpha, beta, 1, inner_tol=1e-13, max_inner=500, variant=variant)
+    kap = O.kappa(v, beta)
+    Hd = O.dense_matrix(lambda x: O.blur(x, h, AR), (ny, nx))
+    Ld = O.dense_matrix(lambda x: O.tv_apply(kap, x), (ny, nx))
+    ref = np.linalg.solve(Hd @ Hd + alpha * Ld, (Hd @ v.ravel()))
+    assert st["inner_iters"][0] > 0
+    np.testing.assert_allclose(u.ravel(), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
