@@ -199,6 +199,46 @@ def ar_extend_eigs(lam_in, ny, nx):
     return ext(ny) @ np.asarray(lam_in, dtype=np.float64) @ ext(nx).T
 
 
+def ar_extend_rows_cols(u):
+    """u on [-1, ny] x [-1, nx]: one ghost line on every side by the
+    anti-reflection of Section 2 (u_{-1} = 2u_0 - u_1, u_n = 2u_{n-1} - u_{n-2}),
+    rows first, then columns (the tensor-product order of the 2D extension)."""
+    u = np.asarray(u, dtype=np.float64)
+    r = np.vstack([2 * u[:1] - u[1:2], u, 2 * u[-1:] - u[-2:-1]])
+    return np.hstack([2 * r[:, :1] - r[:, 1:2], r, 2 * r[:, -1:] - r[:, -2:-1]])
+
+
+def kappa_ar(u, beta):
+    """Diffusivity of L(u^k) under anti-reflective BCs (reading, not written out
+    in the paper): the forward differences of the anti-reflectively extended
+    u^k on every face of the image, the ghost faces included.  Returns
+    (kx, ky): kx[i+1, j] sits on the face between rows i and i+1 (i = -1..ny-1),
+    ky[i, j+1] on the face between columns j and j+1 (j = -1..nx-1)."""
+    e = ar_extend_rows_cols(u)
+    ny, nx = np.asarray(u).shape
+    gx = e[1:, 1:-1] - e[:-1, 1:-1]            # (ny+1) x nx, row faces
+    gy = e[1:-1, 1:] - e[1:-1, :-1]            # ny x (nx+1), column faces
+    # the other component on each face: the forward difference of the cell
+    # below / left of the face along the other axis (as the Neumann kappa)
+    gy_on_x = e[:-1, 2:] - e[:-1, 1:-1]        # row faces: d/dy of the upper cell
+    gx_on_y = e[2:, :-1] - e[1:-1, :-1]        # column faces: d/dx of the left cell
+    gy_on_x = gy_on_x[:, :nx]
+    gx_on_y = gx_on_y[:ny, :]
+    kx = 1.0 / np.sqrt(gx * gx + gy_on_x * gy_on_x + beta * beta)
+    ky = 1.0 / np.sqrt(gy * gy + gx_on_y * gx_on_y + beta * beta)
+    return kx, ky
+
+
+def tv_apply_ar(kx, ky, y):
+    """L(u^k) y under anti-reflective BCs (reading): the flux divergence over
+    all faces of every pixel, y extended by the anti-reflection on the ghost
+    side of the boundary faces.  Not symmetric."""
+    e = ar_extend_rows_cols(y)
+    fx = kx * (e[1:, 1:-1] - e[:-1, 1:-1])     # fluxes on row faces
+    fy = ky * (e[1:-1, 1:] - e[1:-1, :-1])     # fluxes on column faces
+    return -(fx[1:] - fx[:-1]) - (fy[:, 1:] - fy[:, :-1])
+
+
 def reblur(w, h):
     """H' w: blur with the PSF rotated by 180 degrees under anti-reflective
     BCs (Section 3, the reblurring matrix)."""
@@ -350,11 +390,20 @@ def pbicgstab(apply_a, apply_pinv, b, x0, tol, max_iter, replay_iters=None):
 
 
 def fp_solve_reblur(v, h, alpha, beta, n_outer, inner_tol=1e-6, max_inner=100,
-                    variant="p_d", fp_tol=0.0, u0=None, replay=None):
+                    variant="p_d", fp_tol=0.0, u0=None, replay=None, l_bc="neumann"):
     """Lagged-diffusivity fixed point on the reblurring system, eq. (fpp):
         (H'H + alpha L(u^k)) u^{k+1} = H' v,   u^0 = v,
     each step by PBiCGstab warm-started at u^k with I, D, P, D_P or P_D built
-    from kappa(u^k).  Stopping and replay as fp_solve."""
+    from kappa(u^k).  Stopping and replay as fp_solve.
+
+    l_bc = 'antireflective' takes L(u^k) under anti-reflective BCs
+    (kappa_ar / tv_apply_ar, a reading).  Its inner block equals the Neumann
+    operator's, so AR_2(L) and the eigenvalues of P, D_P, P_D are unchanged;
+    D keeps eq. (D) with the Neumann diagonal (the anti-reflective diagonal
+    is a difference of face diffusivities at the edges and need not be
+    positive)."""
+    if l_bc not in ("neumann", "antireflective"):
+        raise ValueError(f"unknown BC for L: {l_bc!r}")
     v = np.asarray(v, dtype=np.float64)
     ny, nx = v.shape
     lam_h = psf_symbol_eigenvalues(h, ny, nx, BC_ANTIREFLECTIVE)
@@ -364,9 +413,14 @@ def fp_solve_reblur(v, h, alpha, beta, n_outer, inner_tol=1e-6, max_inner=100,
     for k in range(n_outer):
         kap = kappa(u, beta)
         setup = reblur_precond_setup(kap, alpha, lam_h, variant)
+        if l_bc == "antireflective":
+            kx, ky = kappa_ar(u, beta)
 
-        def apply_a(p, kap=kap):
-            return reblur_apply(p, h, kap, alpha)
+            def apply_a(p, kx=kx, ky=ky):
+                return reblur(blur(p, h, BC_ANTIREFLECTIVE), h) + alpha * tv_apply_ar(kx, ky, p)
+        else:
+            def apply_a(p, kap=kap):
+                return reblur_apply(p, h, kap, alpha)
 
         def apply_pinv(r, setup=setup):
             return reblur_precond_apply(r, setup)

@@ -346,3 +346,69 @@ def test_one_reblur_step_equals_a_dense_solve(variant):
     ref = np.linalg.solve(Hd @ Hd + alpha * Ld, (Hd @ v.ravel()))
     assert st["inner_iters"][0] > 0
     np.testing.assert_allclose(u.ravel(), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+
+
+def test_ar_bc_operator_constant_diffusivity_in_the_algebra():
+    """With constant diffusivity, L under anti-reflective BCs lies in the
+    algebra of T_n (x) T_n with symbol (2 - 2cos y) + (2 - 2cos z): a linear
+    extension has zero second difference, so the edge rows carry no extra
+    term (the corner 0 of AR(.) for the Laplacian)."""
+    ny, nx = 6, 7
+    kx, ky = np.ones((ny + 1, nx)), np.ones((ny, nx + 1))
+    L = O.dense_matrix(lambda y: RB.tv_apply_ar(kx, ky, y), (ny, nx))
+    T2 = np.kron(RB.ar_transform_matrix(ny), RB.ar_transform_matrix(nx))
+    T2i = np.kron(RB.ar_transform_inverse_matrix(ny), RB.ar_transform_inverse_matrix(nx))
+    D = T2i @ L @ T2
+    np.testing.assert_allclose(D - np.diag(np.diag(D)), 0.0, atol=1e-13)
+    sym = (2 - 2 * np.cos(O.symbol_grid(ny, AR)))[:, None] + (2 - 2 * np.cos(O.symbol_grid(nx, AR)))[None, :]
+    np.testing.assert_allclose(np.diag(D).reshape(ny, nx), sym, atol=1e-13)
+
+
+def test_ar_bc_operator_inner_block_and_projection_equal_neumann():
+    """Variable diffusivity: the anti-reflective L annihilates constants, is
+    not symmetric, and differs from the Neumann L only in the rows and columns
+    of edge pixels, so AR_2 of the two operators coincide (the reblurring
+    preconditioners do not change); its face diffusivities equal the Neumann
+    kappa wherever the Neumann differences are not cut at the far edges."""
+    rng = np.random.default_rng(17)
+    ny, nx = 6, 7
+    u = rng.random((ny, nx))
+    beta = 0.2
+    kx, ky = RB.kappa_ar(u, beta)
+    kap = O.kappa(u, beta)
+    np.testing.assert_allclose(kx[1:ny, :nx - 1], kap[:ny - 1, :nx - 1], rtol=1e-14)
+    np.testing.assert_allclose(ky[:ny - 1, 1:nx], kap[:ny - 1, :nx - 1], rtol=1e-14)
+    Lar = O.dense_matrix(lambda y: RB.tv_apply_ar(kx, ky, y), (ny, nx))
+    Ln = O.dense_matrix(lambda y: O.tv_apply(kap, y), (ny, nx))
+    np.testing.assert_allclose(Lar @ np.ones(ny * nx), 0.0, atol=1e-12)
+    assert np.abs(Lar - Lar.T).max() > 1e-3
+    inner = np.zeros((ny, nx), bool)
+    inner[1:-1, 1:-1] = True
+    k = np.flatnonzero(inner.ravel())
+    np.testing.assert_allclose(Lar[np.ix_(k, k)], Ln[np.ix_(k, k)], atol=1e-13)
+    np.testing.assert_allclose(RB.ar_projection_level2(Lar, ny, nx), RB.ar_projection_level2(Ln, ny, nx),
+                               atol=1e-12)
+
+
+def test_reblur_with_ar_bc_operator_solves_its_systems():
+    """The fixed point with L under anti-reflective BCs: each step solves its
+    (nonsymmetric) system to the tolerance; the preconditioner still helps."""
+    rng = np.random.default_rng(18)
+    ny, nx = 12, 13
+    h = quad_sym_psf(1, 1, rng)
+    v = O.blur(rng.random((ny, nx)), h, AR) + 0.01 * rng.standard_normal((ny, nx))
+    alpha, beta, tol = 0.02, 0.1, 1e-8
+    u1, _ = RB.fp_solve_reblur(v, h, alpha, beta, 1, tol, 400, "p_d", l_bc="antireflective")
+    u2, st = RB.fp_solve_reblur(v, h, alpha, beta, 2, tol, 400, "p_d", l_bc="antireflective")
+    kx, ky = RB.kappa_ar(u1, beta)
+    b = RB.reblur(v, h)
+
+    def A(p):
+        return RB.reblur(O.blur(p, h, AR), h) + alpha * RB.tv_apply_ar(kx, ky, p)
+
+    assert np.linalg.norm(b - A(u2)) < tol * np.linalg.norm(b - A(u1))
+    _, st_none = RB.fp_solve_reblur(v, h, alpha, beta, 2, 1e-6, 400, "none", l_bc="antireflective")
+    _, st_pd = RB.fp_solve_reblur(v, h, alpha, beta, 2, 1e-6, 400, "p_d", l_bc="antireflective")
+    assert sum(st_pd["inner_iters"]) < sum(st_none["inner_iters"])
+    with pytest.raises(ValueError):
+        RB.fp_solve_reblur(v, h, alpha, beta, 1, l_bc="dirichlet")
