@@ -68,6 +68,14 @@ int main() {
         std::snprintf(what, sizeof what, "end weights: sum 1, absolute sum n - 2, n = %d", n);
         const double e = std::fmax(std::fabs(s - 1.0), std::fabs(sa - (n - 2)) / n);
         check(int(w.size()) == n - 2 && e < 1e-9, what, e);
+        // closed form: w_j = (-1)^(j+1) (1 + cos(j pi / (n - 1))), j = 1..n-2
+        double ec = 0.0;
+        for (int j = 1; j <= n - 2; ++j) {
+            const double c = ((j & 1) ? 1.0 : -1.0) * (1.0 + std::cos(3.14159265358979323846 * j / (n - 1)));
+            ec = std::fmax(ec, std::fabs(w[j - 1] - c));
+        }
+        std::snprintf(what, sizeof what, "end weights = (-1)^(j+1) (1 + cos theta_j), n = %d", n);
+        check(ec < 2.0 * n * n * eps, what, ec);
     }
     // T_n^{-1} H T_n = diag(symbol on the y = 0 grid) for anti-reflective blurs (Section 2)
     for (int n : {7, 12, 33}) {

@@ -150,6 +150,19 @@ def test_end_weights_reproduce_constants(n):
     assert abs(np.abs(w).sum() - (n - 2)) < 1e-9 * n
 
 
+@pytest.mark.parametrize("n", [3, 4, 9, 40, 130, 300])
+def test_end_weights_closed_form(n):
+    """The corner of AR(.) counts each entry c_k of the tau matrix's first
+    column k times (z_k = sum_t c_{k+2t}, corner z_1 + 2 sum_{k>=2} z_k), so
+    w_j = S_1j sum_k k S_kj; summing the series at theta_j = j pi/(n-1) gives
+    w_j = (-1)^(j+1) (1 + cos theta_j).  The recursion of the definition
+    rounds at O(n^2) eps."""
+    m = n - 2
+    j = np.arange(1, m + 1)
+    closed = (-1.0) ** (j + 1) * (1.0 + np.cos(j * np.pi / (m + 1)))
+    np.testing.assert_allclose(RB.ar_end_weights(n), closed, rtol=0, atol=2 * n * n * np.finfo(float).eps)
+
+
 def test_level2_projection_is_in_the_2d_algebra():
     """AR_2(L) = Q AR_1(Q^T AR_1(L) Q) Q^T (Section 3.2) is diagonalised by
     T2, with the eigenvalues of ar_extend_eigs on the interior S^-projection."""
