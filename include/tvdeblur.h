@@ -148,7 +148,9 @@ int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev,
  * alpha and beta must equal the forward call's.  The result is the
  * derivative of the exact fixed-point map, so gradient checks use a tight
  * inner_tol in both calls.  stats (nullable) reports the adjoint PCG
- * iterations per step (index K-1-k for step k).
+ * iterations per step (index K-1-k for step k).  The derivative assumes
+ * u^0 = v (it adds dl/du^0 to dl/dv): if the handle's last tvdeblur_solve
+ * started from tvd_params.u0_dev, the call fails with TVD_EINVAL.
  * Errors: as tvdeblur_solve. */
 int tvdeblur_solve_adjoint(tvdeblur_t h, const void* iterates_dev, int K, const void* ubar_dev,
                            void* vbar_dev, double* abar_host, double* bbar_host,
@@ -285,9 +287,11 @@ int tvdeblur_get_kernel_times(tvdeblur_t h, tvd_kernel_times* out);
  * (no events on the dispatches themselves), with the handle's current
  * buffers and parameters; *avg_us (host) receives the time per kernel launch.
  * kind is a class index of tvd_kernel_times: 0 band operator (the y-pass of
- * the active transform form), 2 column transform, 8 transform products (the
- * four products of one preconditioner application, averaged per product),
- * 9 row half of the normal operator.  Needs a completed tvdeblur_solve on the
+ * the active transform form; for a PSF that is not split into row and column
+ * passes, the band launch(es) of one operator application, averaged per
+ * launch), 2 column transform, 7 PCG update (product form), 8 transform
+ * products (the four products of one preconditioner application, averaged
+ * per product), 9 row half of the normal operator.  Needs a completed tvdeblur_solve on the
  * handle (its parameters and preconditioner); overwrites the handle's work
  * buffers, so call it between solves.  TVD_EINVAL for another kind, a kind
  * the active form does not run, reps < 1, or no solve yet. */

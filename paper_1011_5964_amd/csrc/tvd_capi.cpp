@@ -1690,6 +1690,18 @@ class Solver final : public SolverBase {
         } else if (kind == KernelTimer::kXPass && transform && xsplit_ && (gm ? !yfull_ : !xpass_)) {
             const XPassArgs<T> x = xpass_args(Z_);
             launch = [this, x]() { TVD_HIP(launch_xpass<T>(x, s_)); };
+        } else if (kind == KernelTimer::kBand && transform) {
+            // operator without the split y-pass: the fused band launch, or
+            // the two band launches (H, then H^T with the stencil) of a
+            // PSF of rank > 1, averaged per launch
+            per = fused_ ? 1 : 2;
+            launch = [this]() { normal_apply_update(2); };
+        } else if (kind == KernelTimer::kUpdate && gm) {
+            const UpdArgs<T> u = upd_args(2, true, R_);
+            launch = [this, u]() {
+                int nb = 0;
+                TVD_HIP(launch_upd<T>(u, s_, &nb));
+            };
         } else {
             throw ApiError{TVD_EINVAL, "kernel class not run by the active transform form"};
         }
@@ -2519,6 +2531,7 @@ struct tvdeblur_handle {
     int py = 0, px = 0;
     int bc = 0;
     bool built = false;
+    bool last_u0_given = false;  // the last tvdeblur_solve started from u0_dev, not from v
     std::unique_ptr<tvd::SolverBase> solver;
 };
 
@@ -2638,6 +2651,7 @@ int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_param
         int rc = ensure_built(h);
         if (rc) return rc;
         tvd_stats local;
+        h->last_u0_given = p->u0_dev != nullptr;
         h->solver->solve(v_dev, u_dev, *p, stats ? *stats : local);
         return TVD_OK;
     });
@@ -2649,6 +2663,8 @@ int tvdeblur_solve_adjoint(tvdeblur_t h, const void* iterates_dev, int K, const 
     if (!iterates_dev || !ubar_dev || !vbar_dev || !abar_host || !bbar_host || !p)
         return fail(h, TVD_EINVAL, "NULL argument");
     if (K < 1 || K > TVD_MAX_OUTER) return fail(h, TVD_EINVAL, "K out of range");
+    if (h->last_u0_given)
+        return fail(h, TVD_EINVAL, "the adjoint assumes u^0 = v, but the last solve started from u0_dev");
     if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || p->alpha < 0 || !(p->beta > 0))
         return fail(h, TVD_EINVAL, "alpha must be >= 0 and beta > 0, both finite");
     if (p->max_inner < 1 || !(p->inner_tol >= 0)) return fail(h, TVD_EINVAL, "bad inner_tol / max_inner");

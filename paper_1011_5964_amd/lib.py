@@ -217,11 +217,16 @@ class TVDeblur:
         p.u0_dev = None if u0 is None else self._img(u0, "u0").data_ptr()
         keep = None
         if replay is not None:
+            # the library reads max_outer counts from this array
+            if len(replay) < int(max_outer):
+                raise ValueError(f"replay needs max_outer = {int(max_outer)} counts, got {len(replay)}")
             keep = (ctypes.c_int * len(replay))(*[int(x) for x in replay])
             p.replay_host = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int))
         if iterates is not None:
-            if iterates.dtype != self.dtype or iterates.numel() < (max_outer + 1) * self.ny * self.nx:
-                raise ValueError("iterates buffer too small")
+            if iterates.dtype != self.dtype or not iterates.is_contiguous() or iterates.device != self.device \
+                    or iterates.numel() < (max_outer + 1) * self.ny * self.nx:
+                raise ValueError(f"iterates must be a contiguous {self.dtype} tensor on {self.device} "
+                                 f"holding max_outer + 1 images")
             p.iterates_dev = iterates.data_ptr()
         return p, keep
 
@@ -229,7 +234,7 @@ class TVDeblur:
               u0=None, replay=None, iterates=None, out=None):
         import torch
         self._img(v, "v")
-        u = out if out is not None else torch.empty_like(v)
+        u = self._img(out, "out") if out is not None else torch.empty_like(v)
         p, keep = self._params(alpha, beta, max_outer, inner_tol, max_inner, PRECOND[precond], fp_tol, u0,
                                replay, iterates)
         st = Stats()
@@ -249,7 +254,7 @@ class TVDeblur:
         self._img(v, "v")
         if precond not in REBLUR_PRECOND:
             raise ValueError(f"precond must be one of {sorted(REBLUR_PRECOND)}")
-        u = out if out is not None else torch.empty_like(v)
+        u = self._img(out, "out") if out is not None else torch.empty_like(v)
         p, keep = self._params(alpha, beta, max_outer, inner_tol, max_inner, REBLUR_PRECOND[precond], fp_tol, u0,
                                replay, iterates)
         st = Stats()
@@ -304,10 +309,10 @@ class TVDeblur:
 
     def time_kernel(self, kind, reps=50):
         """Average duration in microseconds of one launch of a PCG-loop kernel
-        class ('band_normal', 'column', 'transform_gemm' or 'x_pass'), from a
+        class ('band_normal', 'column', 'update', 'transform_gemm' or 'x_pass'), from a
         back-to-back burst of reps launches with the parameters of the last
         solve (see tvdeblur_time_kernel)."""
-        kinds = {"band_normal": 0, "column": 2, "transform_gemm": 8, "x_pass": 9}
+        kinds = {"band_normal": 0, "column": 2, "update": 7, "transform_gemm": 8, "x_pass": 9}
         if kind not in kinds:
             raise ValueError(f"kind must be one of {sorted(kinds)}")
         import torch
@@ -422,6 +427,14 @@ class TVDeblurBatch:
             if v.dtype != self.dtype or tuple(v.shape) != self.shapes[k] or not v.is_contiguous() \
                     or v.device != self.device:
                 raise ValueError(f"v[{k}] must be a contiguous {self.dtype} {self.shapes[k]} tensor on {self.device}")
+        if outs is not None:
+            if len(outs) != self.count:
+                raise ValueError("one output per image")
+            for k, u in enumerate(outs):
+                if u.dtype != self.dtype or tuple(u.shape) != self.shapes[k] or not u.is_contiguous() \
+                        or u.device != self.device:
+                    raise ValueError(f"outs[{k}] must be a contiguous {self.dtype} {self.shapes[k]} tensor "
+                                     f"on {self.device}")
         us = outs if outs is not None else [torch.empty_like(v) for v in vs]
         vp = (ctypes.c_void_p * self.count)(*[v.data_ptr() for v in vs])
         up = (ctypes.c_void_p * self.count)(*[u.data_ptr() for u in us])
@@ -438,6 +451,10 @@ class TVDeblurBatch:
         p.transform = TRANSFORM[transform]
         rkeep = None
         if replay is not None:
+            # count x max_outer counts, image-major, read in full by the library;
+            # a shorter list (an image that stops early on fp_tol) is padded with zeros
+            if len(replay) != self.count or any(len(r) > int(max_outer) for r in replay):
+                raise ValueError(f"replay needs {self.count} lists of at most max_outer = {int(max_outer)} counts")
             flat = [int(c) for r in replay for c in (list(r) + [0] * max_outer)[:max_outer]]
             rkeep = (ctypes.c_int * len(flat))(*flat)
             p.replay_host = ctypes.cast(rkeep, ctypes.POINTER(ctypes.c_int))

@@ -77,3 +77,39 @@ def test_x_d_preconditioner_is_scaled_system_preconditioner():
     S = np.diag(st["s"].ravel())
     Pi = O.dense_matrix(lambda r: O.precond_apply(r, st, AR), shape)
     np.testing.assert_allclose(Pi, S @ Xd_inv @ S, atol=1e-13)
+
+
+@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("variant", ["none", "diag", "x", "d_x", "x_d"])
+def test_preconditioner_solve_inverts_its_matrix(bc, variant):
+    """precond_apply is the inverse of the preconditioner matrix the paper
+    defines, formed densely and independently of the fast formulas:
+      I;  D = I + alpha diag(L)                       (eq. (D));
+      X   = Q2^T diag(mu) Q2                          (eqs. (R), (M); Section 3.2);
+      D_X = D^{1/2} Q2^T diag(mu) Q2 D^{1/2}          (eq. (DR2));
+      X_D = Q2^T diag(mu) Q2 for the scaled system (eq. (scalesys)), which
+            acts on eq. (fp) as D^{1/2} X_D D^{1/2},
+    with mu taken from precond_setup_dense (dense diag(Q2 A Q2^T) of dense H
+    and L, pinned to the fast setup above) and Q2 the Kronecker product of
+    the dense 1D bases.  A wrong power of lambda_H, a missing scaling or a
+    transposed transform in precond_apply fails here."""
+    rng = np.random.default_rng(24)
+    ny, nx = 6, 5
+    kap = O.kappa(rng.random((ny, nx)), 0.12)
+    h = quad_sym_psf(1, 2, rng)
+    alpha = 0.04
+    dense = O.precond_setup_dense(kap, alpha, h, bc, variant)
+    Ld = O.dense_matrix(lambda x: O.tv_apply(kap, x), (ny, nx))
+    D = np.eye(ny * nx) + alpha * np.diag(np.diag(Ld))
+    if variant == "none":
+        P = np.eye(ny * nx)
+    elif variant == "diag":
+        P = D
+    else:
+        Q2 = np.kron(O.basis_matrix(ny, bc), O.basis_matrix(nx, bc))
+        X = Q2.T @ np.diag(dense["mu"].ravel()) @ Q2
+        Dh = np.sqrt(D)
+        P = X if variant == "x" else Dh @ X @ Dh
+    fast = O.precond_setup(kap, alpha, O.psf_symbol_eigenvalues(h, ny, nx, bc), bc, variant)
+    Pi = O.dense_matrix(lambda r: O.precond_apply(r, fast, bc), (ny, nx))
+    np.testing.assert_allclose(Pi @ P, np.eye(ny * nx), atol=1e-11)
