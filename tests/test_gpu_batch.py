@@ -207,9 +207,15 @@ def test_batch_errors():
     with pytest.raises(TvdError) as e:
         b.solve(vs, [1e-3, float("nan")])
     assert e.value.name == "TVD_EINVAL"
+    # an output aliasing an input: rejected by the library
     with pytest.raises(TvdError) as e:
-        b.solve(vs, [1e-3, 1e-3], outs=[vs[1], torch.empty_like(vs[1])])
+        b.solve(vs, [1e-3, 1e-3], outs=[vs[0], torch.empty_like(vs[1])])
     assert e.value.name == "TVD_EINVAL"
+    # an output of the wrong shape or type: rejected by the binding before any call
+    with pytest.raises(ValueError):
+        b.solve(vs, [1e-3, 1e-3], outs=[vs[1], torch.empty_like(vs[1])])
+    with pytest.raises(ValueError):
+        b.solve(vs, [1e-3, 1e-3], outs=[torch.empty_like(vs[0], dtype=torch.float64), torch.empty_like(vs[1])])
     with pytest.raises(TvdError) as e:
         b.solve(vs, [1e-3, 1e-3], max_outer=0)
     assert e.value.name == "TVD_EINVAL"

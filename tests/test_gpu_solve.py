@@ -292,3 +292,33 @@ def test_time_kernel_burst(transform):
         h.time_kernel(other, 5)
     u2, _ = h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
     assert torch.equal(u1, u2)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+def test_fp_tol_stops_where_the_oracle_stops(prec):
+    """fp_tol > 0 on a single image: the fixed-point loop ends after the first
+    step whose relative change ||u^{k+1} - u^k|| / ||u^{k+1}|| falls below
+    fp_tol (Section 5's outer stopping rule), at the oracle's step, with the
+    oracle's image to the bar."""
+    p = synth.small_problem(n=40, ny=36, psf_size=7, sigma=1.3, n_outer=40, alpha=2e-3, beta=0.1)
+    fp_tol = 2.4e-3
+    vq = host(dev(p.v, prec))
+    uo, so = O.fp_solve(vq, p.psf, p.bc, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d", fp_tol=fp_tol)
+    k = so["outer_steps"]
+    ch = so["fp_change"]
+    print(f"oracle stops after {k} of {p.n_outer} steps, changes {['%.2e' % c for c in ch]}", flush=True)
+    assert 1 < k < p.n_outer
+    # the stop is not borderline: the last change is clearly below fp_tol and
+    # the one before clearly above it
+    assert ch[-1] < 0.9 * fp_tol and ch[-2] > 1.1 * fp_tol
+    ug, sg = gpu_solve(p, prec, fp_tol=fp_tol)
+    print(f"gpu stops after {sg['outer_steps']} steps, iters {sg['inner_iters'][:sg['outer_steps']]} "
+          f"oracle {so['inner_iters']}", flush=True)
+    assert sg["outer_steps"] == k
+    np.testing.assert_allclose(sg["fp_change"][:k], ch, rtol=1e-3 if prec == "f32_mixed" else 1e-8)
+    err = rel2(ug, uo)
+    if sg["inner_iters"][:k] != so["inner_iters"]:
+        ug, sr = gpu_solve(p, prec, replay=so["inner_iters"], n_outer=k)
+        err = rel2(ug, uo)
+    print(f"rel err {err:.3e}", flush=True)
+    assert err <= BAR[prec]
