@@ -25,11 +25,17 @@ def basis_matrix(n, bc):
 
     Anti-reflective, Section 3.1, eq. (hats): Q = S^ = diag(1, S_{n-2}, 1)
     with S_m = sqrt(2/(m+1)) (sin(ij pi/(m+1)))_{i,j=1..m}, eq. (lambda).
+
+    n = 1 (the one-pixel axis of a 1D signal held as a 1 x n image, Section
+    5.1): the axis has only the constant mode, Q = [1] for both BCs (the
+    DCT-II formula gives it; for AR the first and last entries coincide).
     """
     _check_bc(bc)
+    if n == 1:
+        return np.ones((1, 1))
     if bc == BC_REFLECTIVE:
         if n < 2:
-            raise ValueError("n >= 2 required")
+            raise ValueError("n >= 1 required")
         i = np.arange(1, n + 1)[:, None]     # position (paper's i)
         j = np.arange(1, n + 1)[None, :]     # frequency (paper's j)
         Cn = np.sqrt((2.0 - (j == 1)) / n) * np.cos((2 * i - 1) * (j - 1) * np.pi / (2 * n))
@@ -48,6 +54,8 @@ def basis_matrix(n, bc):
 
 
 def _fwd_1d(X, bc, axis):
+    if np.shape(X)[axis] == 1:       # one-pixel axis: Q = [1]
+        return np.array(X, dtype=np.float64, copy=True)
     if bc == BC_REFLECTIVE:
         return scipy.fft.dct(X, type=2, norm="ortho", axis=axis)
     Y = np.array(X, dtype=np.float64, copy=True)
@@ -58,6 +66,8 @@ def _fwd_1d(X, bc, axis):
 
 
 def _inv_1d(Y, bc, axis):
+    if np.shape(Y)[axis] == 1:
+        return np.array(Y, dtype=np.float64, copy=True)
     if bc == BC_REFLECTIVE:
         return scipy.fft.idct(Y, type=2, norm="ortho", axis=axis)
     return _fwd_1d(Y, bc, axis)      # S^ is a symmetric involution

@@ -91,6 +91,7 @@ class Problem:
     max_inner: int
     noise: float
     seed: int
+    fp_tol: float = 0.0
 
 
 def make_problem(name, n, shapes, psf, bc, alpha, beta, n_outer, noise, seed,
@@ -158,6 +159,53 @@ def batch_problems(count, base_seed=4000, sides=(128, 192, 256, 384, 512),
                                 "antireflective", alpha, 0.05, n_outer, 0.01,
                                 base_seed + 10_000 + i))
     return out
+
+
+def out_of_focus_1d(m):
+    """Out-of-focus PSF of Section 5.1, eq. (of): h_i = c for |i| < m, else 0,
+    with c normalising the sum to 1; returned as a 1 x (2m-1) PSF."""
+    if m < 1:
+        raise ValueError("m >= 1")
+    return np.full((1, 2 * m - 1), 1.0 / (2 * m - 1))
+
+
+def signal_half_width(n):
+    """m(n) of eq. (of): the PSF reaches m-1 samples past each end of the
+    field of view, which covers [0.1, 0.9] of the scene (Section 5.1), so the
+    margin of 0.1 of the scene on each side is about n/8 samples."""
+    return max(2, int(round(n / 8.0)))
+
+
+def signal_problem(n=203, bc="antireflective", alpha=1e-3, beta=0.1, n_outer=100, fp_tol=1e-3,
+                   noise=0.01, seed=203, inner_tol=1e-6, max_inner=1000, pieces=8):
+    """1D signal deblurring of Section 5.1 as a 1 x n image: a seeded scene of
+    n + 2(m-1) samples on [0, 1] made of `pieces` segments (constant or
+    linear with probability 1/2 each, levels U[0, 1], breakpoints uniform),
+    blurred by the out-of-focus PSF of half-width m = m(n), the field of view
+    the central n samples, plus white Gaussian noise at the given level
+    relative to ||h * u|| (1% as in Section 5.1).  The paper's own signal is
+    shown only as a figure; only the shape of the set-up is reproduced."""
+    rng = np.random.default_rng(seed)
+    m = signal_half_width(n)
+    F = n + 2 * (m - 1)
+    x = np.arange(F, dtype=np.float64)
+    cuts = np.sort(rng.choice(np.arange(1, F), size=pieces - 1, replace=False))
+    edges = np.concatenate([[0], cuts, [F]])
+    scene = np.zeros(F)
+    for a, b in zip(edges[:-1], edges[1:]):
+        lo, hi = rng.random(), rng.random()
+        if rng.random() < 0.5:
+            scene[a:b] = lo
+        else:
+            scene[a:b] = lo + (hi - lo) * (x[a:b] - a) / max(1, b - a)
+    psf = out_of_focus_1d(m)
+    blurred = np.convolve(scene, psf[0], mode="valid")
+    sigma = noise * np.linalg.norm(blurred) / np.sqrt(blurred.size)
+    v = blurred + sigma * rng.standard_normal(blurred.shape)
+    p = Problem(f"signal_{n}", v[None, :].copy(), scene[m - 1:m - 1 + n][None, :].copy(), psf, bc, alpha,
+                beta, n_outer, inner_tol, max_inner, noise, seed)
+    p.fp_tol = fp_tol
+    return p
 
 
 def small_problem(n=32, psf_size=7, sigma=1.2, bc="antireflective", alpha=1e-3,
