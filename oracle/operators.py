@@ -16,7 +16,12 @@ import scipy.sparse
 
 BC_REFLECTIVE = "reflective"
 BC_ANTIREFLECTIVE = "antireflective"
-_BCS = (BC_REFLECTIVE, BC_ANTIREFLECTIVE)
+# the two classical BCs the paper compares with (Section 1 and Section 2):
+# zero (Dirichlet) ghosts, giving a Toeplitz blur, and periodic ghosts,
+# giving a circulant one
+BC_DIRICHLET = "dirichlet"
+BC_PERIODIC = "periodic"
+_BCS = (BC_REFLECTIVE, BC_ANTIREFLECTIVE, BC_DIRICHLET, BC_PERIODIC)
 
 
 def _check_bc(bc):
@@ -34,21 +39,28 @@ def extension_matrix(n, m, bc):
       anti-reflective: u~[-j] = 2u[0] - u[j],     u~[n-1+j] = 2u[n-1] - u[n-1-j]
     The anti-reflective rule needs u[j] for j <= m, so m <= n-1; the
     reflective rule needs m <= n.
+    Zero (Dirichlet) BCs: every ghost is 0 (Toeplitz blur).  Periodic BCs:
+    u~[-j] = u[n-j], u~[n-1+j] = u[j-1] (circulant blur), m <= n.
     """
     _check_bc(bc)
     if m < 0:
         raise ValueError("m must be >= 0")
     if bc == BC_ANTIREFLECTIVE and m > n - 1:
         raise ValueError("anti-reflective extension needs m <= n-1")
-    if bc == BC_REFLECTIVE and m > n:
-        raise ValueError("reflective extension needs m <= n")
+    if bc in (BC_REFLECTIVE, BC_PERIODIC) and m > n:
+        raise ValueError("reflective / periodic extension needs m <= n")
     E = np.zeros((n + 2 * m, n))
     for t in range(n):
         E[t + m, t] = 1.0
     for j in range(1, m + 1):
         lo = m - j            # row of u~[-j]
         hi = m + n - 1 + j    # row of u~[n-1+j]
-        if bc == BC_REFLECTIVE:
+        if bc == BC_DIRICHLET:
+            continue
+        if bc == BC_PERIODIC:
+            E[lo, n - j] += 1.0
+            E[hi, j - 1] += 1.0
+        elif bc == BC_REFLECTIVE:
             E[lo, j - 1] += 1.0
             E[hi, n - j] += 1.0
         else:

@@ -11,7 +11,7 @@ coefficients of a vector x are Q x and the algebra is {Q^T diag(lam) Q}.
 import numpy as np
 import scipy.fft
 
-from .operators import BC_ANTIREFLECTIVE, BC_REFLECTIVE, _check_bc
+from .operators import BC_ANTIREFLECTIVE, BC_DIRICHLET, BC_PERIODIC, BC_REFLECTIVE, _check_bc
 
 
 def basis_matrix(n, bc):
@@ -29,11 +29,21 @@ def basis_matrix(n, bc):
     n = 1 (the one-pixel axis of a 1D signal held as a 1 x n image, Section
     5.1): the axis has only the constant mode, Q = [1] for both BCs (the
     DCT-II formula gives it; for AR the first and last entries coincide).
+
+    Zero-Dirichlet BCs (the Toeplitz blur, not in any fast algebra): the
+    same DCT-II, i.e. the cosine-transform preconditioners the paper cites
+    for this case (Section 1).  Periodic BCs: the real orthonormal Fourier
+    basis 1/sqrt(n); sqrt(2/n) cos(2 pi k i/n), sqrt(2/n) sin(2 pi k i/n) for
+    k = 1..ceil(n/2)-1 (in that order, cosine then sine per k); (-1)^i/sqrt(n)
+    when n is even.  It diagonalises every symmetric circulant matrix, so the
+    periodic blur of a symmetric PSF.
     """
     _check_bc(bc)
     if n == 1:
         return np.ones((1, 1))
-    if bc == BC_REFLECTIVE:
+    if bc == BC_PERIODIC:
+        return _real_fourier(n)
+    if bc in (BC_REFLECTIVE, BC_DIRICHLET):
         if n < 2:
             raise ValueError("n >= 1 required")
         i = np.arange(1, n + 1)[:, None]     # position (paper's i)
@@ -53,10 +63,25 @@ def basis_matrix(n, bc):
     return Q
 
 
+def _real_fourier(n):
+    """Rows: the real orthonormal Fourier basis (see basis_matrix)."""
+    i = np.arange(n, dtype=np.float64)
+    rows = [np.full(n, 1.0 / np.sqrt(n))]
+    for k in range(1, (n + 1) // 2):
+        rows.append(np.sqrt(2.0 / n) * np.cos(2.0 * np.pi * k * i / n))
+        rows.append(np.sqrt(2.0 / n) * np.sin(2.0 * np.pi * k * i / n))
+    if n % 2 == 0:
+        rows.append(np.cos(np.pi * i) / np.sqrt(n))
+    return np.array(rows)
+
+
 def _fwd_1d(X, bc, axis):
     if np.shape(X)[axis] == 1:       # one-pixel axis: Q = [1]
         return np.array(X, dtype=np.float64, copy=True)
-    if bc == BC_REFLECTIVE:
+    if bc == BC_PERIODIC:            # dense product with the real Fourier basis
+        return np.moveaxis(np.tensordot(basis_matrix(np.shape(X)[axis], bc), np.asarray(X, dtype=np.float64),
+                                        axes=([1], [axis])), 0, axis)
+    if bc in (BC_REFLECTIVE, BC_DIRICHLET):
         return scipy.fft.dct(X, type=2, norm="ortho", axis=axis)
     Y = np.array(X, dtype=np.float64, copy=True)
     sl = [slice(None)] * Y.ndim
@@ -68,7 +93,10 @@ def _fwd_1d(X, bc, axis):
 def _inv_1d(Y, bc, axis):
     if np.shape(Y)[axis] == 1:
         return np.array(Y, dtype=np.float64, copy=True)
-    if bc == BC_REFLECTIVE:
+    if bc == BC_PERIODIC:
+        return np.moveaxis(np.tensordot(basis_matrix(np.shape(Y)[axis], bc).T, np.asarray(Y, dtype=np.float64),
+                                        axes=([1], [axis])), 0, axis)
+    if bc in (BC_REFLECTIVE, BC_DIRICHLET):
         return scipy.fft.idct(Y, type=2, norm="ortho", axis=axis)
     return _fwd_1d(Y, bc, axis)      # S^ is a symmetric involution
 
@@ -95,11 +123,19 @@ def symbol_grid(n, bc):
     Anti-reflective, eq. (gridy): y_j = (j-1) pi / (n-1) for j = 1..n-1 and
     y_n = 0; 0-based theta_0 = 0, theta_k = k pi/(n-1) (k = 1..n-2),
     theta_{n-1} = 0.
+    Periodic: 2 pi k / n for the cosine and the sine row of frequency k, in
+    the order of basis_matrix.  Zero-Dirichlet has no grid (its blur is not
+    in the cosine algebra; see psf_symbol_eigenvalues).
     """
     _check_bc(bc)
     k = np.arange(n, dtype=np.float64)
     if n == 1:
         return np.zeros(1)              # a single pixel: only the constant mode
+    if bc == BC_DIRICHLET:
+        raise ValueError("the zero-Dirichlet blur has no symbol grid")
+    if bc == BC_PERIODIC:
+        freq = [0] + [kk for kk in range(1, (n + 1) // 2) for _ in (0, 1)] + ([n // 2] if n % 2 == 0 else [])
+        return 2.0 * np.pi * np.asarray(freq, dtype=np.float64) / n
     if bc == BC_REFLECTIVE:
         return np.pi * k / n
     th = np.pi * k / (n - 1)
@@ -113,9 +149,33 @@ def psf_symbol_eigenvalues(h, ny, nx, bc):
     quadrantally symmetric PSF it is real."""
     h = np.asarray(h, dtype=np.float64)
     my, mx = (h.shape[0] - 1) // 2, (h.shape[1] - 1) // 2
+    if bc == BC_DIRICHLET:
+        return _toeplitz_cosine_projection(h, ny, nx)
     a = np.arange(-my, my + 1, dtype=np.float64)
     b = np.arange(-mx, mx + 1, dtype=np.float64)
     Ey = np.exp(1j * np.outer(symbol_grid(ny, bc), a))
     Ex = np.exp(1j * np.outer(symbol_grid(nx, bc), b))
     lam = Ey @ h @ Ex.T
     return lam.real.copy()
+
+
+def _toeplitz_cosine_projection(h, ny, nx):
+    """Zero-Dirichlet BCs: the eigenvalues of the optimal cosine-algebra
+    approximation of the Toeplitz blur (level-2 projection, as Section 3.2
+    projects L), diag(Q2 H Q2^T) with Q the DCT-II.  H = sum_{ab} h_ab
+    Z_a (x) Z_b with Z_a the shift by a with zero fill, so
+    lambda[k, l] = sum_{ab} h_ab c_a[k] c_b[l],  c_a[k] = sum_i phi_k(i) phi_k(i+a)
+    over 0 <= i, i+a < n."""
+    my, mx = (h.shape[0] - 1) // 2, (h.shape[1] - 1) // 2
+
+    def shifts(n, m):
+        Q = basis_matrix(n, BC_DIRICHLET)
+        c = np.zeros((2 * m + 1, n))
+        for a in range(-m, m + 1):
+            lo, hi = max(0, -a), min(n, n - a)
+            if lo < hi:
+                c[a + m] = np.sum(Q[:, lo:hi] * Q[:, lo + a:hi + a], axis=1)
+        return c
+
+    cy, cx = shifts(ny, my), shifts(nx, mx)
+    return cy.T @ h @ cx

@@ -6,6 +6,7 @@ import pytest
 import oracle as O
 
 AR, R = "antireflective", "reflective"
+DIR, PER = "dirichlet", "periodic"  # the two classical baseline BCs
 
 
 def quad_sym_psf(my, mx, rng):
@@ -17,7 +18,7 @@ def quad_sym_psf(my, mx, rng):
     return h / h.sum()
 
 
-@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("bc", [AR, R, DIR, PER])
 @pytest.mark.parametrize("variant", ["diag", "x", "d_x", "x_d"])
 def test_fast_setup_equals_dense_projection(bc, variant):
     """The GEMM-form eigenvalues (lam_L, lam_D, lam_Lt) equal diag(Q2 A Q2^T)
@@ -36,7 +37,7 @@ def test_fast_setup_equals_dense_projection(bc, variant):
             np.testing.assert_allclose(fast[key], dense[key], rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("bc", [AR, R, DIR, PER])
 @pytest.mark.parametrize("variant", ["diag", "x", "d_x", "x_d"])
 def test_preconditioner_spd_and_preconditioned_spectrum(bc, variant):
     """PCG needs an SPD preconditioner (Section 1): P^{-1} is symmetric
@@ -79,7 +80,7 @@ def test_x_d_preconditioner_is_scaled_system_preconditioner():
     np.testing.assert_allclose(Pi, S @ Xd_inv @ S, atol=1e-13)
 
 
-@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("bc", [AR, R, DIR, PER])
 @pytest.mark.parametrize("variant", ["none", "diag", "x", "d_x", "x_d"])
 def test_preconditioner_solve_inverts_its_matrix(bc, variant):
     """precond_apply is the inverse of the preconditioner matrix the paper

@@ -8,6 +8,7 @@ import oracle as O
 from paper_1011_5964_amd import synth
 
 AR, R = "antireflective", "reflective"
+DIR, PER = "dirichlet", "periodic"  # the two classical baseline BCs
 
 
 def test_pcg_matches_dense_solve():
@@ -45,7 +46,7 @@ def test_pcg_zero_residual_start_and_replay():
     assert info["iters"] == 2
 
 
-@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("bc", [AR, R, DIR, PER])
 @pytest.mark.parametrize("variant", ["none", "x", "x_d"])
 def test_fixed_point_objective_decreases_monotonically(bc, variant):
     """The lagged-diffusivity step minimises a quadratic majoriser of T at
@@ -66,7 +67,7 @@ def test_identity_psf_alpha_zero_recovers_v_exactly():
     assert st["inner_iters"] == [0]
 
 
-@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("bc", [AR, R, PER])   # zero ghosts do not reproduce constants
 def test_constant_image_is_a_fixed_point(bc):
     p = synth.small_problem(n=12)
     v = np.full((12, 12), 0.4)
@@ -74,7 +75,7 @@ def test_constant_image_is_a_fixed_point(bc):
     np.testing.assert_allclose(u, v, atol=1e-14)
 
 
-@pytest.mark.parametrize("bc", [AR, R])
+@pytest.mark.parametrize("bc", [AR, R, DIR, PER])
 def test_fixed_point_limit_solves_euler_lagrange(bc):
     """Converged FP iterates satisfy g(u) = 0 (eq. (el)) to the solver
     tolerance."""
