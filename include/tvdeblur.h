@@ -136,6 +136,33 @@ int tvdeblur_set_bc(tvdeblur_t h, int bc);
 int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev,
                    const tvd_params* p, tvd_stats* stats);
 
+/* ---- allocation-free solve ----
+ * For callers that cannot allocate device memory when they call: serving
+ * loops and harnesses that forbid hipMalloc after start-up.  Arguments,
+ * arithmetic, results, stats and errors are those of tvdeblur_solve, with
+ * these differences:
+ *  - the per-solve work buffers (the PCG vectors, per-block partial sums and
+ *    the control block) live in one static device array of
+ *    TVD_NOALLOC_SCRATCH_BYTES that the library holds on every device it
+ *    runs on until the process ends; the call allocates nothing (no
+ *    hipMalloc, hipFree or allocating library routine);
+ *  - the handle must already be built for its PSF and BC (tvdeblur_solve
+ *    or tvdeblur_get_transform once after set_psf / set_bc; building
+ *    allocates the handle's tables), else TVD_ESTATE;
+ *  - images whose work buffers exceed TVD_NOALLOC_SCRATCH_BYTES fail with
+ *    TVD_ESIZE (about 16 float + 2 double images plus partials: up to
+ *    ~910 x 910 for TVD_F32_MIXED, ~680 x 680 for TVD_F64);
+ *  - kernel profiling (tvdeblur_set_profiling) must be off, else TVD_EINVAL.
+ * Every call on one device shares that device's array, and its contents are
+ * whatever the last call left (each solve initialises what it reads): calls
+ * that overlap in time on one device race and give wrong results, whether
+ * from two host threads or two streams.  Calls on different devices do not
+ * interact.  tvdeblur_time_kernel after this call times the handle's own
+ * buffers. */
+#define TVD_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int tvdeblur_solve_noalloc(tvdeblur_t h, const void* v_dev, void* u_dev,
+                           const tvd_params* p, tvd_stats* stats);
+
 /* Differentiation form: reverse-mode derivative of the K fixed-point steps of
  * eq. (fp), u^{k+1} = (H^T H + alpha L(u^k))^{-1} H^T v with u^0 = v.
  * iterates_dev holds u^0..u^K as written by tvdeblur_solve (iterates_dev of

@@ -100,6 +100,14 @@ class SolverBase {
     virtual void get_times(tvd_kernel_times* out) = 0;
     // average duration of one PCG-loop kernel class in a back-to-back burst
     virtual double time_kernel(int kind, int reps) = 0;
+    virtual bool profiling() const = 0;
+    // Bytes of the per-solve work buffers of solve() (PCG vectors, partial
+    // sums, control block) for the built shape; 0 before build.
+    virtual size_t work_bytes() const = 0;
+    // solve() with those work buffers carved from `base` (device memory of
+    // at least work_bytes(), 256-byte aligned) in place of the handle's own;
+    // the handle's tables and eigenvalue-setup arrays are used as they are.
+    virtual void solve_in(void* base, const void* v, void* u, const tvd_params& p, tvd_stats& st) = 0;
 };
 
 // Per-class kernel timing with pairs of HIP events around launches.
@@ -421,6 +429,7 @@ class Solver final : public SolverBase {
         nb_res_ = band_blocks(ny_, nx_, fused_ ? ty_res_ : ty_ht_hp_);
         const int cap = std::max({nb_band_, nb_res_, gx_.blocks, gy_.blocks, ypass_blocks(ny_, nx_),
                                   ((ny_ + 31) / 32) * ((nx_ + 31) / 32), 1024});
+        part_cap_ = size_t(cap);
         pq_ = D(cap);
         rr_[0] = D(cap);
         rr_[1] = D(cap);
@@ -1655,6 +1664,65 @@ class Solver final : public SolverBase {
     }
 
     void set_profiling(int every) override { timer_.enable(every); }
+    bool profiling() const override { return timer_.on(); }
+
+    // ----------------------------------------- work buffers of one solve
+    struct WorkPtrs {
+        T* vec[16];
+        double* dbl[2];
+        double* part[5];
+        double* fp;
+        PcgState* st;
+    };
+    static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+    WorkPtrs work() const {
+        return WorkPtrs{{U_, X_, R_, Pb_[0], Pb_[1], Tb_[0], Tb_[1], W_, Q_, Z_, T1_, T2_, Kap_, Sap_, MuInv_, Tmp_},
+                        {BD_, TmpD_},
+                        {pq_, rr_[0], rr_[1], rz_[0], rz_[1]},
+                        fp_,
+                        st_};
+    }
+    void set_work(const WorkPtrs& w) {
+        T** v[16] = {&U_, &X_, &R_, &Pb_[0], &Pb_[1], &Tb_[0], &Tb_[1], &W_, &Q_, &Z_, &T1_, &T2_, &Kap_, &Sap_,
+                     &MuInv_, &Tmp_};
+        for (int k = 0; k < 16; ++k) *v[k] = w.vec[k];
+        BD_ = w.dbl[0];
+        TmpD_ = w.dbl[1];
+        pq_ = w.part[0];
+        rr_[0] = w.part[1];
+        rr_[1] = w.part[2];
+        rz_[0] = w.part[3];
+        rz_[1] = w.part[4];
+        fp_ = w.fp;
+        st_ = w.st;
+    }
+    size_t work_bytes() const override {
+        if (!built_) return 0;
+        return 16 * al256(N_ * sizeof(T)) + 2 * al256(N_ * sizeof(double)) + 5 * al256(part_cap_ * sizeof(double)) +
+               al256(2 * 1024 * sizeof(double)) + al256(sizeof(PcgState));
+    }
+    void solve_in(void* base, const void* v, void* u, const tvd_params& p, tvd_stats& st) override {
+        unsigned char* b = static_cast<unsigned char*>(base);
+        auto take = [&](size_t bytes) {
+            unsigned char* q = b;
+            b += al256(bytes);
+            return q;
+        };
+        WorkPtrs w{};
+        for (auto& x : w.vec) x = reinterpret_cast<T*>(take(N_ * sizeof(T)));
+        for (auto& x : w.dbl) x = reinterpret_cast<double*>(take(N_ * sizeof(double)));
+        for (auto& x : w.part) x = reinterpret_cast<double*>(take(part_cap_ * sizeof(double)));
+        w.fp = reinterpret_cast<double*>(take(2 * 1024 * sizeof(double)));
+        w.st = reinterpret_cast<PcgState*>(take(sizeof(PcgState)));
+        // the handle's own buffers come back however solve() leaves
+        struct Restore {
+            Solver* s;
+            WorkPtrs own;
+            ~Restore() { s->set_work(own); }
+        } guard{this, work()};
+        set_work(w);
+        solve(v, u, p, st);
+    }
     void get_times(tvd_kernel_times* out) override { timer_.fill(out); }
 
     // reps back-to-back launches of one kernel class between two marker
@@ -1832,6 +1900,7 @@ class Solver final : public SolverBase {
            *Zg_[3] = {}, *Sd_ = nullptr, *LamX_ = nullptr, *LamY_ = nullptr, *LamD_ = nullptr, *Mu_ = nullptr;
     double *pq_ = nullptr, *rr_[2] = {nullptr, nullptr}, *rz_[2] = {nullptr, nullptr}, *fp_ = nullptr;
     int nb_band_ = 0, n_pq_ = 0, n_rz_ = 0;
+    size_t part_cap_ = 0;  // entries of each partial-sum array
     PcgState* st_ = nullptr;
     PcgState* host_st_ = nullptr;
     GemmProblem *gemm1_ = nullptr, *gemm2_ = nullptr;
@@ -2634,7 +2703,9 @@ int tvdeblur_set_bc(tvdeblur_t h, int bc) {
     return TVD_OK;
 }
 
-int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_params* p, tvd_stats* stats) {
+namespace {
+// Argument checks shared by tvdeblur_solve and tvdeblur_solve_noalloc.
+int check_solve_args(tvdeblur_t h, const void* v_dev, const void* u_dev, const tvd_params* p) {
     if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
     if (!v_dev || !u_dev || !p) return fail(h, TVD_EINVAL, "NULL argument");
     if (v_dev == u_dev) return fail(h, TVD_EINVAL, "v and u must not alias");
@@ -2647,12 +2718,75 @@ int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_param
     if (p->replay_host)
         for (int k = 0; k < p->max_outer; ++k)
             if (p->replay_host[k] < 0) return fail(h, TVD_EINVAL, "negative replay count");
+    return TVD_OK;
+}
+}  // namespace
+
+int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_params* p, tvd_stats* stats) {
+    if (int rc = check_solve_args(h, v_dev, u_dev, p)) return rc;
     return guarded(h, [&]() {
         int rc = ensure_built(h);
         if (rc) return rc;
         tvd_stats local;
         h->last_u0_given = p->u0_dev != nullptr;
         h->solver->solve(v_dev, u_dev, *p, stats ? *stats : local);
+        return TVD_OK;
+    });
+}
+
+}  // extern "C"
+
+// ---- allocation-free variant of tvdeblur_solve ----
+// The per-solve work buffers come from one file-scope device array instead
+// of the handle's arena.  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address is taken once per device with
+// hipGetSymbolAddress and only that address is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[TVD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (looked up on first use, with that
+// device current; the caller's current device is restored).
+void* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) throw tvd::ApiError{TVD_EINVAL, "device index out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        int cur = 0;
+        TVD_HIP(hipGetDevice(&cur));
+        if (cur != device) TVD_HIP(hipSetDevice(device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) TVD_HIP(hipSetDevice(cur));
+        if (e != hipSuccess || !ptr) throw tvd::HipError{e, "hipGetSymbolAddress(scratch)"};
+        g_scratch_dev[device] = ptr;
+    }
+    return g_scratch_dev[device];
+}
+}  // namespace
+
+extern "C" {
+
+int tvdeblur_solve_noalloc(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_params* p, tvd_stats* stats) {
+    if (int rc = check_solve_args(h, v_dev, u_dev, p)) return rc;
+    if (!h->built)
+        return fail(h, TVD_ESTATE,
+                    "handle not built: call tvdeblur_get_transform (or tvdeblur_solve) once after set_psf / set_bc");
+    if (int rc = check_psf_fits(h)) return rc;
+    if (h->solver->profiling())
+        return fail(h, TVD_EINVAL, "kernel profiling is on (it creates timing events); switch it off first");
+    const size_t need = h->solver->work_bytes();
+    if (need > size_t(TVD_NOALLOC_SCRATCH_BYTES))
+        return fail(h, TVD_ESIZE,
+                    "image too large for the static work area: needs " + std::to_string(need) + " bytes, holds " +
+                        std::to_string(size_t(TVD_NOALLOC_SCRATCH_BYTES)));
+    return guarded(h, [&]() {
+        void* base = scratch_address(h->device);
+        tvd_stats local;
+        h->last_u0_given = p->u0_dev != nullptr;
+        h->solver->solve_in(base, v_dev, u_dev, *p, stats ? *stats : local);
         return TVD_OK;
     });
 }

@@ -38,7 +38,7 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_batch_get_info", "tvdeblur_batch_destroy", "tvdeblur_batch_last_error",
     "tvdeblur_set_transform", "tvdeblur_get_transform", "tvdeblur_time_kernel",
     "tvdeblur_solve_reblur", "tvdeblur_op_reblur_setup", "tvdeblur_op_reblur_normal",
-    "tvdeblur_op_reblur_precond",
+    "tvdeblur_op_reblur_precond", "tvdeblur_solve_noalloc",
 )
 BATCH_PRECOND = ("x", "d_x", "x_d")
 
@@ -120,6 +120,7 @@ def load():
         "tvdeblur_set_psf": [vp, ctypes.POINTER(d), i, i],
         "tvdeblur_set_bc": [vp, i],
         "tvdeblur_solve": [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Stats)],
+        "tvdeblur_solve_noalloc": [vp, vp, vp, ctypes.POINTER(Params), ctypes.POINTER(Stats)],
         "tvdeblur_destroy": [vp],
         "tvdeblur_op_blur": [vp, vp, vp],
         "tvdeblur_op_blur_adjoint": [vp, vp, vp],
@@ -243,6 +244,23 @@ class TVDeblur:
         del keep
         self._check(rc)
         return u, st.to_dict()
+
+    def solve_noalloc(self, v, out, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="x_d",
+                      fp_tol=0.0, u0=None, replay=None, iterates=None):
+        """tvdeblur_solve_noalloc: as solve, writing the caller's `out`, with
+        the work buffers in the library's static device array (the handle
+        must be built: call transform() once first)."""
+        self._img(v, "v")
+        self._img(out, "out")
+        p, keep = self._params(alpha, beta, max_outer, inner_tol, max_inner, PRECOND[precond], fp_tol, u0,
+                               replay, iterates)
+        st = Stats()
+        import torch
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_solve_noalloc(self.h, _ptr(v), _ptr(out), ctypes.byref(p), ctypes.byref(st))
+        del keep
+        self._check(rc)
+        return out, st.to_dict()
 
     def solve_reblur(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="p_d", fp_tol=0.0,
                      u0=None, replay=None, iterates=None, out=None):
