@@ -74,9 +74,12 @@ def ar_transform_inverse_matrix(n):
 
 def _ar_inv_1d(X, axis):
     """T^{-1} along one axis: keep the two end values, DST-I (library,
-    orthonormal) of the interior minus the linear interpolant of the ends."""
+    orthonormal) of the interior minus the linear interpolant of the ends.
+    A one-pixel axis (a 1D signal held as a 1 x n image) is left as it is."""
     X = np.moveaxis(np.asarray(X, dtype=np.float64), axis, 0)
     n = X.shape[0]
+    if n == 1:
+        return np.moveaxis(X.copy(), 0, axis)
     p = _ramp(n).reshape((-1,) + (1,) * (X.ndim - 1))
     Y = X.copy()
     Y[1:n - 1] = scipy.fft.dst(X[1:n - 1] - p * X[0] - p[::-1] * X[n - 1], type=1, norm="ortho", axis=0)
@@ -87,6 +90,8 @@ def _ar_fwd_1d(Y, axis):
     """T along one axis: interior = DST-I of the interior + ends times p, Jp."""
     Y = np.moveaxis(np.asarray(Y, dtype=np.float64), axis, 0)
     n = Y.shape[0]
+    if n == 1:
+        return np.moveaxis(Y.copy(), 0, axis)
     p = _ramp(n).reshape((-1,) + (1,) * (Y.ndim - 1))
     X = Y.copy()
     X[1:n - 1] = scipy.fft.dst(Y[1:n - 1], type=1, norm="ortho", axis=0) + p * Y[0] + p[::-1] * Y[n - 1]
@@ -188,8 +193,12 @@ def ar_end_weights(n):
 def ar_extend_eigs(lam_in, ny, nx):
     """Eigenvalues of AR_2(A) on the full ny x nx grid from the interior
     ones: E_y lam_in E_x^T with E = [w^T; I; w^T].  The grid is that of
-    eq. (gridy): index 0 and n-1 are the two y = 0 columns of T_n."""
+    eq. (gridy): index 0 and n-1 are the two y = 0 columns of T_n.  A
+    one-pixel axis (1D signals, ny = 1) has no ends: E = [1] and lam_in keeps
+    that axis whole."""
     def ext(n):
+        if n == 1:
+            return np.ones((1, 1))
         E = np.zeros((n, n - 2))
         E[1:n - 1] = np.eye(n - 2)
         w = ar_end_weights(n)
@@ -276,8 +285,11 @@ def reblur_precond_setup(kap, alpha, lam_h, variant="p_d"):
     if variant == "diag":                     # D = I + alpha diag(L), eq. (D)
         return {"variant": variant, "d": D}
 
+    def inner(n):
+        return slice(0, 1) if n == 1 else slice(1, n - 1)
+
     def ar2(lam_hat):
-        return ar_extend_eigs(lam_hat[1:ny - 1, 1:nx - 1], ny, nx)
+        return ar_extend_eigs(lam_hat[inner(ny), inner(nx)], ny, nx)
 
     if variant in ("p", "d_p"):
         s = ones if variant == "p" else 1.0 / np.sqrt(D)

@@ -105,3 +105,51 @@ def test_out_of_focus_psf_and_signal_recipe():
     # the observation is the valid convolution of the scene, so its field of
     # view needs m-1 scene samples on each side
     assert p.fp_tol == 1e-3 and p.inner_tol == 1e-6
+
+
+@pytest.mark.parametrize("variant", ["p", "d_p", "p_d"])
+def test_signal_reblur_preconditioner_is_the_literal_ar_projection(variant):
+    """1D reblurring preconditioners (Section 3): the fast eigenvalues (the
+    S^ projection of the interior plus the end rule through the weights w)
+    equal diag(T^{-1} M T) of the literal matrices built with AR(.) written
+    out as in Section 3, and those matrices lie in the algebra."""
+    from oracle import reblur as RB
+    n, alpha = 23, 5e-2
+    p = synth.signal_problem(n, AR, alpha=alpha)
+    kap = O.kappa(p.v, p.beta)
+    lam_h = O.psf_symbol_eigenvalues(p.psf, 1, n, AR)
+    st = RB.reblur_precond_setup(kap, alpha, lam_h, variant)
+    Hd = O.dense_matrix(lambda x: O.blur(x, p.psf, AR), (1, n))
+    Ld = O.dense_matrix(lambda x: O.tv_apply(kap, x), (1, n))
+    T, Ti = RB.ar_transform_matrix(n), RB.ar_transform_inverse_matrix(n)
+    D = 1.0 + alpha * np.diag(Ld)
+    if variant == "p_d":
+        S = np.diag(1.0 / np.sqrt(D))
+        AS = RB.ar_projection(S)
+        M = Hd @ Hd @ AS @ AS + alpha * RB.ar_projection(S @ Ld @ S)
+    else:
+        M = Hd @ Hd + alpha * RB.ar_projection(Ld)
+    E = Ti @ M @ T
+    np.testing.assert_allclose(E - np.diag(np.diag(E)), 0.0, atol=1e-11 * np.abs(E).max())
+    np.testing.assert_allclose(st["mu"][0], np.diag(E), rtol=1e-10, atol=1e-13)
+    # the solve inverts s^{-1} T diag(mu) T^{-1} s^{-1}
+    Mfull = np.diag(1.0 / st["s"][0]) @ T @ np.diag(st["mu"][0]) @ Ti @ np.diag(1.0 / st["s"][0])
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal((1, n))
+    z = RB.reblur_precond_apply(r, st)
+    np.testing.assert_allclose(Mfull @ z[0], r[0], rtol=0, atol=1e-10 * np.abs(r).max())
+
+
+@pytest.mark.parametrize("variant", ["none", "diag", "p", "d_p", "p_d"])
+def test_signal_reblur_step_is_the_dense_solve_and_rows_equal_columns(variant):
+    from oracle import reblur as RB
+    p = synth.signal_problem(40, AR, alpha=1e-2)
+    u1, _ = RB.fp_solve_reblur(p.v, p.psf, p.alpha, p.beta, 1, 1e-15, 500, variant)
+    kap = O.kappa(p.v, p.beta)
+    A = O.dense_matrix(lambda x: RB.reblur_apply(x, p.psf, kap, p.alpha), p.v.shape)
+    ref = np.linalg.solve(A, RB.reblur(p.v, p.psf).ravel())
+    np.testing.assert_allclose(u1.ravel(), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+    u, st = RB.fp_solve_reblur(p.v, p.psf, p.alpha, p.beta, 5, 1e-6, 500, variant)
+    ut, stt = RB.fp_solve_reblur(p.v.T.copy(), p.psf.T.copy(), p.alpha, p.beta, 5, 1e-6, 500, variant)
+    assert st["inner_iters"] == stt["inner_iters"]
+    np.testing.assert_allclose(u, ut.T, rtol=0, atol=1e-13)
