@@ -220,7 +220,7 @@ def fixture(name):
 CONFIG_RUNS = [("c1", "f64", None), ("c1", "f32_mixed", None),
                ("c2_ar", "f64", "c2_ar_f64"), ("c2_ar", "f32_mixed", "c2_ar_f32"),
                ("c2_r", "f64", "c2_r_f64"), ("c2_r", "f32_mixed", "c2_r_f32"),
-               ("c3_gauss", "f32_mixed", "c3_gauss"), ("c3_disk", "f32_mixed", "c3_disk")]
+               ("c3_gauss", "f32_mixed", "c3_gauss_f32"), ("c3_disk", "f32_mixed", "c3_disk_f32")]
 
 
 def configs_form(args):
@@ -247,7 +247,7 @@ def configs_form(args):
         fx = fixture(fx_name) if fx_name else None
         if fx is not None:
             keep["rel_err_vs_oracle"] = rel2(u, fx["u"].astype(np.float64))
-            keep["oracle_iters_per_step"] = [int(c) for c in fx["counts"]]
+            keep["oracle_iters_per_step"] = [int(c) for c in fx["inner_iters"]]
         elif name == "c1":
             import oracle as O
             vq = p.v.astype(np.float32).astype(np.float64) if prec == "f32_mixed" else p.v
@@ -516,6 +516,63 @@ def diff_form(args, f64_restore_s):
             "speedup_fwd_bwd_vs_plain_f64_forward": f64_restore_s / statistics.median(tb)}
 
 
+SIGNAL_ALPHAS = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
+SIGNAL_BETAS = [1e-3, 1e-2, 1.0]
+SIGNAL_NS = [101, 203, 407, 815, 1631]
+SIGNAL_VARIANTS = ["none", "diag", "x", "d_x", "x_d"]
+
+
+def signals_form(args):
+    """The paper's 1D experiments (Section 5.1, Tables 1-2 and the n sweep) on
+    synthetic signals, each table one batched launch: n = 203, the out-of-focus
+    PSF of eq. (of) with m(n) = round(n/8), 1% noise, FP stop at a relative
+    change below 1e-3, PCG tol 1e-6; both BCs x I, D, X, D_X, X_D; the alpha
+    sweep at beta 0.1, the beta sweep at alpha 1e-3, and the n sweep at
+    alpha 1e-3, beta 0.1.  Reports N and the average PCG iterations per step
+    (the trends compare with the paper's; its own signal is not available)
+    and the time of each launch; FP64."""
+    import numpy as np
+    from paper_1011_5964_amd import synth
+    from paper_1011_5964_amd.lib import TVDeblurSignals
+    res = {"workload": "synthetic piecewise constant / linear signals, out-of-focus PSF m(n) = round(n/8), 1% noise, "
+                       "FP stop 1e-3, PCG tol 1e-6, max 1000 (n sweep 4000) iterations, FP64, one launch per table"}
+
+    def run_table(rows, max_inner, system="normal"):
+        names = SIGNAL_VARIANTS if system == "normal" else ["none", "diag", "p", "d_p", "p_d"]
+        probs = [pr for pr, _ in rows for _ in names]
+        variants = [v for _ in rows for v in names]
+        sb = TVDeblurSignals([q.v.shape[1] for q in probs], [q.psf for q in probs], [q.bc for q in probs],
+                             reblur=[system == "reblur"] * len(probs))
+        v = sb.pack([q.v[0] for q in probs])
+        alphas = [q.alpha for q in probs]
+        betas = [q.beta for q in probs]
+
+        def go():
+            return sb.solve(v, alphas, betas=betas, precond=variants, max_outer=100, fp_tol=1e-3, inner_tol=1e-6,
+                            max_inner=max_inner, system=system)
+
+        times, (u, st) = time_calls(go, 3, 1)
+        table = []
+        for r, (_, label) in enumerate(rows):
+            cell = st[5 * r:5 * r + 5]
+            table.append({"row": label, "N": cell[0]["outer_steps"],
+                          **{vn: round(float(np.mean(c["inner_iters"])), 1) for vn, c in zip(names, cell)},
+                          "converged": all(c["all_converged"] for c in cell)})
+        sb.close()
+        return {"signals": len(probs), "launch_s": statistics.median(times),
+                "krylov_iters": int(sum(c["total_inner_iters"] for c in st)), "rows": table}
+
+    for bc, system in (("reflective", "normal"), ("antireflective", "normal"), ("antireflective", "reblur")):
+        tag = f"{bc}_pcg" if system == "normal" else "antireflective_reblur_pbicgstab"
+        res[f"table1_alpha_{tag}"] = run_table(
+            [(synth.signal_problem(203, bc, alpha=a, beta=0.1), f"alpha {a:g}") for a in SIGNAL_ALPHAS], 1000, system)
+        res[f"table2_beta_{tag}"] = run_table(
+            [(synth.signal_problem(203, bc, alpha=1e-3, beta=b), f"beta {b:g}") for b in SIGNAL_BETAS], 1000, system)
+        res[f"n_sweep_{tag}"] = run_table(
+            [(synth.signal_problem(n, bc, alpha=1e-3, beta=0.1), f"n {n}") for n in SIGNAL_NS], 4000, system)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -523,12 +580,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="all",
                     help="comma list of forms measured beside the headline: f64, batch, diff, sweep, reblur, "
-                         "configs ('all' = these six), tables (iteration tables, only when named); or 'none'")
+                         "configs, signals ('all' = these seven), tables (2D iteration tables, only when named); "
+                         "or 'none'")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="fixed-point steps of the oracle CPU sample (0 = skip the oracle)")
     ap.add_argument("--transform", choices=("auto", "fft", "gemm"), default="auto",
                     help="preconditioner transforms of the headline and plain FP64 solves: timed choice (default), "
                          "line transforms, or products on the matrix cores")
+    ap.add_argument("--workload", default="m512",
+                    help="headline workload (profiling runs): m512 (the metric's), c1, c2_ar, c2_r, c3_gauss, "
+                         "c3_disk, c5; any other than m512 makes the line a profiling record, not the metric")
+    ap.add_argument("--precision", choices=("f32_mixed", "f64"), default="f32_mixed",
+                    help="precision of the headline solves (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy (y = -x, float32) of this many MiB three times: "
                          "the reference kernel that scales hardware traffic counters")
@@ -547,19 +610,22 @@ def main():
         print("no HIP device visible", file=sys.stderr)
         sys.exit(1)
 
-    p = synth.config("m512")
+    p = synth.config(args.workload)
     n = p.v.shape[0]
-    print(f"[bench] headline f32_mixed {n}x{n}: {args.warmup} warm-up + {args.steps} timed solves",
-          file=sys.stderr, flush=True)
-    r32, u32 = headline(args, p, "f32_mixed")
+    print(f"[bench] headline {args.precision} {args.workload} {n}x{n}: {args.warmup} warm-up + {args.steps} "
+          f"timed solves", file=sys.stderr, flush=True)
+    r32, u32 = measure(args, p, args.precision, args.steps, args.warmup, args.transform)
     out = {"metric": "512² AR-BC TV restore time (s) & PCG iters/s at ≤1e-5 rel err vs FP64 oracle",
            "value": round(r32["restore_time_s"], 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 3),
            "restore_time_s": round(r32["restore_time_s"], 6),
            "pcg_iters_per_s": round(r32["pcg_iters_per_s"], 1), "higher_is_better": False, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "precision": "f32_mixed (FP64 dots, scalars, stopping test)",
+           "vs_baseline": None, "dtype": "f32" if args.precision == "f32_mixed" else "f64",
+           "precision": ("f32_mixed (FP64 dots, scalars, stopping test)" if args.precision == "f32_mixed"
+                         else "f64"),
            "data": "synthetic",
-           "config": {"workload": WORKLOAD, "n": n, "psf": "gaussian 21x21 sigma 3", "bc": "antireflective",
+           "config": {"workload": WORKLOAD if args.workload == "m512" else f"profiling record: {args.workload}",
+                      "n": n, "psf": f"{p.psf.shape[0]}x{p.psf.shape[1]}", "bc": p.bc,
                       "precond": "x_d", "fixed_point_steps": p.n_outer,
                       "pcg_iters_per_solve": r32["pcg_iters_per_solve"]},
            "roofline": r32["roofline"], "iteration_roofline": r32["iteration_roofline"],
@@ -567,7 +633,7 @@ def main():
            "pcg_iters_per_s_inner_loop": round(r32["pcg_iters_per_s_inner_loop"], 1),
            "setup_share": round(r32["setup_share"], 4), "kernel_classes": r32["kernel_classes"]}
 
-    sel = {"all": {"f64", "batch", "diff", "sweep", "reblur", "configs"}, "none": set()}.get(
+    sel = {"all": {"f64", "batch", "diff", "sweep", "reblur", "configs", "signals"}, "none": set()}.get(
         args.forms, set(args.forms.split(",")))
     forms = {}
     u64 = None
@@ -597,6 +663,9 @@ def main():
     if "tables" in sel:
         print("[bench] iteration tables (normal equations and reblurring system)", file=sys.stderr, flush=True)
         forms["tables"] = tables_form(args)
+    if "signals" in sel:
+        print("[bench] 1D signal tables (one launch per table)", file=sys.stderr, flush=True)
+        forms["signals"] = signals_form(args)
     if "configs" in sel:
         forms["configs"] = configs_form(args)
     reblur_slot = None
@@ -622,11 +691,12 @@ def main():
             d0 = time.perf_counter()
             _, s1 = O.fp_solve(p.v, p.psf, p.bc, p.alpha, p.beta, k1, p.inner_tol, p.max_inner, "x_d")
             d1 = time.perf_counter()
-        out["cpu_baseline"] = {"value": round(o_iters / (c1 - c0), 2), "unit": "PCG iters/s", "cores": cores,
+        out["cpu_baseline"] = {"value": round((c1 - c0) * p.n_outer / k, 3), "unit": "s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"first {k} of {p.n_outer} fixed-point steps of the same 512x512 workload "
                                          f"({o_iters} PCG iterations in {c1 - c0:.1f} s, BLAS and scipy.fft on "
-                                         f"{cores} threads)",
+                                         f"{cores} threads), restore time scaled to {p.n_outer} steps",
+                               "pcg_iters_per_s": round(o_iters / (c1 - c0), 2),
                                "one_core": {"value": round(sum(s1["inner_iters"]) / (d1 - d0), 2),
                                             "sample": f"first {k1} fixed-point steps on 1 thread "
                                                       f"({sum(s1['inner_iters'])} PCG iterations, "
@@ -655,9 +725,10 @@ def main():
                 "oracle_iters": sr["inner_iters"]}
     if probs is not None:
         # per-image error of the batch against the oracle's stored solve of each image
-        fx = fixture("c4")
+        fx = fixture("c4_f32")
         if fx is not None:
-            errs = [rel2(u.double().cpu().numpy(), fx[f"u{i}"].astype(np.float64)) for i, u in enumerate(last["u"])]
+            errs = [rel2(u.double().cpu().numpy(), fx[f"u_{i:02d}"].astype(np.float64))
+                    for i, u in enumerate(last["u"])]
             forms["batch"]["rel_err_vs_oracle"] = {"max": max(errs), "median": statistics.median(errs),
                                                    "images": len(errs)}
     if forms:

@@ -71,6 +71,12 @@ typedef struct tvdeblur_handle* tvdeblur_t;
 /* boundary condition of the blur H (Section 2) */
 #define TVD_BC_REFLECTIVE      1
 #define TVD_BC_ANTIREFLECTIVE  2
+/* the two classical BCs the paper compares with (Sections 1-2): zero ghosts
+ * (Toeplitz blur; preconditioned in the DCT-II algebra with the optimal
+ * projection diag(Q2 H Q2^T) of the blur) and periodic ghosts (circulant
+ * blur; the real Fourier basis diagonalises it, symbol at 2 pi k / n) */
+#define TVD_BC_DIRICHLET       3
+#define TVD_BC_PERIODIC        4
 
 /* preconditioner (columns I, D, X, D_X, X_D of Tables 1-3) */
 #define TVD_PREC_NONE  0
@@ -124,7 +130,13 @@ int tvdeblur_create(tvdeblur_t* out, int ny, int nx, int precision, void* hip_st
 int tvdeblur_set_psf(tvdeblur_t h, const double* psf_host, int py, int px);
 
 /* Boundary condition of H: TVD_BC_REFLECTIVE or TVD_BC_ANTIREFLECTIVE
- * (Section 2).  L(u) is always zero-Neumann.  Errors: TVD_EINVAL, TVD_ESIZE. */
+ * (Section 2), or one of the two classical BCs the paper compares with:
+ * TVD_BC_DIRICHLET (zero ghosts; the DCT-II preconditioners) and
+ * TVD_BC_PERIODIC (wrap-around ghosts; the real Fourier basis, whose
+ * transforms always run as matrix-core products; needs 4m + 1 <= n per axis).
+ * L(u) is always zero-Neumann.  The reblurring system takes anti-reflective
+ * BCs only; the batching form all but periodic.  Errors: TVD_EINVAL,
+ * TVD_ESIZE. */
 int tvdeblur_set_bc(tvdeblur_t h, int bc);
 
 /* Run the fixed-point / PCG method (eq. (fp)) on v_dev, writing u_dev.
@@ -221,6 +233,20 @@ const char* tvdeblur_last_error(tvdeblur_t h);
  * <rhat, v> or omega became 0; u_dev then holds the last iterate). */
 int tvdeblur_solve_reblur(tvdeblur_t h, const void* v_dev, void* u_dev,
                           const tvd_params* p, tvd_stats* stats);
+
+/* Boundary condition of L(u^k) in the reblurring system (Section 3 defines
+ * the preconditioners with zero-Neumann L; its experiments also impose
+ * anti-reflective BCs on L): TVD_L_NEUMANN (default) or
+ * TVD_BC_ANTIREFLECTIVE.  The anti-reflective L takes the diffusivity on
+ * every face of the image, the ghost faces included, from the
+ * anti-reflectively extended u^k, and applies the flux divergence with the
+ * argument extended the same way (one ghost line per side): it differs from
+ * the Neumann L only in the edge rows and columns and is not symmetric.  The
+ * preconditioners keep the Neumann eigenvalues and D (the inner block of L is
+ * the same).  Applies to later tvdeblur_solve_reblur and op_reblur_* calls.
+ * Errors: TVD_EINVAL. */
+#define TVD_L_NEUMANN 0
+int tvdeblur_set_reblur_l_bc(tvdeblur_t h, int l_bc);
 
 /* Setup of the reblurring preconditioner (any of the five above) from uk_dev;
  * tvdeblur_op_export then returns its kappa, s, mu, lambda_H and D. */
@@ -414,6 +440,79 @@ int tvdeblur_batch_destroy(tvdeblur_batch_t b);
 
 /* Message of the last failure on b, or of the last failed batch create when b is NULL. */
 const char* tvdeblur_batch_last_error(tvdeblur_batch_t b);
+
+/* ---- 1D signals (Section 5.1): many independent signals, one launch ----
+ *
+ * Each signal is its own instance of eq. (fp) in one dimension,
+ * (H^T H + alpha L(u^k)) u^{k+1} = H^T v with u^0 = v, where H is the 1D blur
+ * of a symmetric normalised PSF (e.g. the out-of-focus PSF of eq. (of))
+ * under the signal's boundary condition and L(u^k) the zero-Neumann TV
+ * operator with cell diffusivity 1/sqrt((u_{i+1} - u_i)^2 + beta^2).  Each
+ * step runs PCG warm-started at u^k with the signal's preconditioner (I, D of
+ * eq. (D), X = R or M of Section 3, D_X, X_D) and the stopping test of
+ * Section 5 (or, for the reblurring system of eq. (fpp), PBiCGstab with P,
+ * D_P, P_D as tvdeblur_solve_reblur); the fixed-point loop stops after
+ * max_outer steps or at the first relative change below fp_tol.  One workgroup runs one signal from start to
+ * finish, so a solve of the whole batch is a single kernel launch.  All
+ * arithmetic is IEEE double (the paper's precision; there is no FP32 form).
+ * Signals are packed back to back in one device buffer: signal i starts at
+ * the sum of the n of the signals before it. */
+
+typedef struct tvdeblur_signals* tvdeblur_signals_t;
+
+typedef struct {
+    int n;                    /* samples, 3..4096 */
+    const double* psf_host;   /* plen taps (odd), centre at plen/2, symmetric,
+                                 sum 1 (checked as in tvdeblur_set_psf); copied */
+    int plen;                 /* half-width plen/2 <= n-1 (AR) or <= n (reflective) */
+    int bc;                   /* TVD_BC_* (periodic: 4 plen/2 + 1 <= n) */
+    int reblur;               /* nonzero: also build the tables of the reblurring
+                                 system (anti-reflective only; two more n x n arrays) */
+} tvd_signal_desc;
+
+typedef struct {
+    const double* alpha_host;  /* count alphas (>= 0, finite) */
+    const double* beta_host;   /* count betas (> 0), or NULL: beta for all */
+    double beta;
+    const int* precond_host;   /* count TVD_PREC_* codes, or NULL: precond for all */
+    int    precond;
+    int    max_outer;          /* 1..TVD_MAX_OUTER */
+    double fp_tol;             /* 0 = run exactly max_outer steps */
+    double inner_tol;          /* ||r|| < inner_tol ||r_0|| (strict) */
+    int    max_inner;          /* >= 1 */
+    const int* replay_host;    /* NULL, or count x max_outer iteration counts
+                                  (signal-major) to run exactly, stopping test skipped */
+    const int* system_host;    /* count of 0 / 1, or NULL: system for all */
+    int    system;             /* 0: eq. (fp) by PCG with I, D, X, D_X, X_D;
+                                  1: the reblurring system eq. (fpp),
+                                  (H'H + alpha L(u^k)) u^{k+1} = H'v, by PBiCGstab with
+                                  I, D, P, D_P, P_D (precond codes NONE, DIAG, X, D_X,
+                                  X_D) as tvdeblur_solve_reblur; one iteration = two
+                                  operator products */
+} tvd_signal_params;
+
+/* Build the tables of `count` (1..65536) signals on the current device: the
+ * bands of H^T H and H^T with the BC folded in, the transform basis, the
+ * symbol eigenvalues on the BC grid.  Work is queued on hip_stream (a
+ * hipStream_t, NULL = null stream).  Errors: TVD_EINVAL, TVD_ENOTSYM,
+ * TVD_ENORM, TVD_ESIZE, TVD_ENOMEM, TVD_EDEVICE (message from
+ * tvdeblur_signals_last_error(NULL)). */
+int tvdeblur_signals_create(tvdeblur_signals_t* out, int count, const tvd_signal_desc* descs, void* hip_stream);
+
+/* Solve every signal: v_dev, u_dev are device buffers of sum(n) doubles
+ * (packed as above, caller-owned, must not alias).  stats_host (may be NULL)
+ * receives count tvd_stats; their time fields are the launch's.  Returns
+ * after the results are complete.  A breakdown stops that signal only and
+ * the call returns TVD_EBREAKDOWN after the others have finished.
+ * Errors: TVD_EINVAL, TVD_EDEVICE, TVD_EBREAKDOWN. */
+int tvdeblur_signals_solve(tvdeblur_signals_t s, const double* v_dev, double* u_dev,
+                           const tvd_signal_params* p, tvd_stats* stats_host);
+
+/* Release the signals' tables and work area.  NULL is accepted. */
+int tvdeblur_signals_destroy(tvdeblur_signals_t s);
+
+/* Message of the last failure on s, or of the last failed create when s is NULL. */
+const char* tvdeblur_signals_last_error(tvdeblur_signals_t s);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtvdeblur.so")
 ARCH = os.environ.get("TVD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["tvd_kernels.hip", "tvd_plan.cpp", "tvd_capi.cpp"]
+SOURCES = ["tvd_kernels.hip", "tvd_plan.cpp", "tvd_capi.cpp", "tvd_signal.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

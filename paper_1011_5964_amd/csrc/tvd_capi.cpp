@@ -92,6 +92,8 @@ class SolverBase {
     virtual void op_reblur_setup(const void* uk, double alpha, double beta, int variant) = 0;
     virtual void op_reblur_normal(const void* x, void* y) = 0;
     virtual void op_reblur_precond(const void* r, void* z) = 0;
+    // BC of L(u^k) in the reblurring system: 0 zero-Neumann, TVD_BC_ANTIREFLECTIVE
+    virtual void set_reblur_l_bc(int l_bc) = 0;
     virtual void set_profiling(int every) = 0;
     // Transform implementation of the preconditioner: 0 = pick by timing at
     // build, 1 = FFT line passes, 2 = products on the matrix cores.
@@ -225,6 +227,8 @@ class Solver final : public SolverBase {
         }
     }
     ~Solver() override {
+        clear_pcg_graphs();
+        if (cap_s_) (void)hipStreamDestroy(cap_s_);
         (void)hipEventDestroy(ev_poll_);
         for (auto& e : ev_step_)
             for (hipEvent_t x : e) (void)hipEventDestroy(x);
@@ -236,9 +240,13 @@ class Solver final : public SolverBase {
 
     // ---------------------------------------------------------------- build
     void build(const std::vector<double>& psf, int py, int px, int bc) override {
+        clear_pcg_graphs();
         geo_.release();
+        CstD_ = nullptr;
+        Cst_ = nullptr;
         solved_ = false;
         bc_ = bc;
+        wrap_ = bc == TVD_BC_PERIODIC ? 1 : 0;
         const PsfFactors f = factor_psf(psf.data(), py, px);
         my_ = f.my;
         mx_ = f.mx;
@@ -247,17 +255,21 @@ class Solver final : public SolverBase {
         reblur_ready_ = false;
         reblur_mode_ = false;
         // 1D blur matrices of each factor with the BC folded in, and bands
+        // (periodic BCs: circulant matrices, whose bands wrap around)
+        auto band = [&](const std::vector<double>& A, int n, int w) {
+            return wrap_ ? band_wrapped(A, n, w) : band_of(A, n, w);
+        };
         std::vector<double> hy, hx, hty, htx, ky, kx;
         for (int r = 0; r < rank_; ++r) {
             const std::vector<double> Hy = blur_matrix_1d(f.gy[r], ny_, bc);
             const std::vector<double> Hx = blur_matrix_1d(f.gx[r], nx_, bc);
-            append(hy, band_of(Hy, ny_, my_));
-            append(hx, band_of(Hx, nx_, mx_));
-            append(hty, band_of(transpose(Hy, ny_), ny_, my_));
-            append(htx, band_of(transpose(Hx, nx_), nx_, mx_));
+            append(hy, band(Hy, ny_, my_));
+            append(hx, band(Hx, nx_, mx_));
+            append(hty, band(transpose(Hy, ny_), ny_, my_));
+            append(htx, band(transpose(Hx, nx_), nx_, mx_));
             if (rank_ == 1) {
-                ky = band_of(matmul_tn(Hy, Hy, ny_), ny_, 2 * my_);
-                kx = band_of(matmul_tn(Hx, Hx, nx_), nx_, 2 * mx_);
+                ky = band(matmul_tn(Hy, Hy, ny_), ny_, 2 * my_);
+                kx = band(matmul_tn(Hx, Hx, nx_), nx_, 2 * mx_);
             }
         }
         Hy_ = geo_.upload<T>(hy, s_);
@@ -281,6 +293,7 @@ class Solver final : public SolverBase {
             probe.kap = reinterpret_cast<const T*>(1);
             ty_fused_ = pick_ty(probe);
             BandArgsT<T, T, double, T> probe_hp{};
+            probe_hp.wrap = wrap_;
             probe_hp.wy = 2 * my_;
             probe_hp.wx = 2 * mx_;
             probe_hp.nterms = 1;
@@ -298,6 +311,7 @@ class Solver final : public SolverBase {
             probe.S = reinterpret_cast<const T*>(1);
             ty_ht_ = pick_ty(probe);
             BandArgsT<double, T, double, T> probe_hp{};
+            probe_hp.wrap = wrap_;
             probe_hp.wy = my_;
             probe_hp.wx = mx_;
             probe_hp.nterms = rank_;
@@ -365,6 +379,12 @@ class Solver final : public SolverBase {
         // when both band half-widths fit the tile halo.
         yfull_ = xsplit_ && 2 * my_ <= 32 && kw_ <= 32 &&
                  ypass_full_lds_bytes(2 * my_, kw_, sizeof(T)) + kStaticLds <= max_lds_;
+        // periodic BCs: only the whole-operator y-pass and the band kernels
+        // wrap their halos; without the former the operator runs as bands
+        if (wrap_ && !yfull_) {
+            xsplit_ = false;
+            xpass_ = false;
+        }
         // basis matrices for the eigenvalue setup
         make_basis(ny_, Wy_, Puy_, Puly_, Ply_);
         if (ny_ == nx_) {
@@ -468,6 +488,11 @@ class Solver final : public SolverBase {
     // process by shape, PSF widths, BC and element type).
     void choose_transform() {
         tmode_ = 0;
+        if (bc_ == TVD_BC_PERIODIC) {  // the real Fourier basis runs as products only
+            if (!gemm_ok_) throw ApiError{TVD_EINVAL, "periodic BCs need the matrix-core product form"};
+            tmode_ = 1;
+            return;
+        }
         if (!gemm_ok_ || treq_ == 1) return;
         if (treq_ == 2) {
             tmode_ = 1;
@@ -722,6 +747,7 @@ class Solver final : public SolverBase {
     // b = H^T v with FP64 coefficients and accumulation (stored in FP64).
     void rhs_hp(const T* v) {
         BandArgsT<T, T, double, double> a{};
+        a.wrap = wrap_;
         a.ny = ny_;
         a.nx = nx_;
         a.wy = my_;
@@ -744,6 +770,7 @@ class Solver final : public SolverBase {
     }
     BandArgsT<T, T, double, T> residual_fused_args(const T* x, T* r, double* rr_out) const {
         BandArgsT<T, T, double, T> a{};
+        a.wrap = wrap_;
         a.ny = ny_;
         a.nx = nx_;
         a.wy = 2 * my_;
@@ -764,6 +791,7 @@ class Solver final : public SolverBase {
     void residual_hp_launch(const T* x, T* r, double* rr_out) {
         if (fused_) {
             BandArgsT<T, T, double, T> a{};
+            a.wrap = wrap_;
             a.ny = ny_;
             a.nx = nx_;
             a.wy = 2 * my_;
@@ -782,6 +810,7 @@ class Solver final : public SolverBase {
             TVD_HIP(launch_band(a, ty_res_, s_, nullptr));
         } else {
             BandArgsT<T, T, double, double> h{};
+            h.wrap = wrap_;
             h.ny = ny_;
             h.nx = nx_;
             h.wy = my_;
@@ -793,6 +822,7 @@ class Solver final : public SolverBase {
             h.Y = TmpD_;
             TVD_HIP(launch_band(h, pick_ty(h), s_, nullptr));
             BandArgsT<double, T, double, T> a{};
+            a.wrap = wrap_;
             a.ny = ny_;
             a.nx = nx_;
             a.wy = my_;
@@ -829,6 +859,7 @@ class Solver final : public SolverBase {
     bool full_y() const { return tmode_ == 1 && yfull_; }
     YPassArgs<T> ypass_args(int it) const {
         YPassArgs<T> a{};
+        a.wrap = wrap_;
         a.ny = ny_;
         a.nx = nx_;
         a.w = 2 * my_;
@@ -983,7 +1014,9 @@ class Solver final : public SolverBase {
             TVD_HIP(hipEventRecord(e[2], s_));
             TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
             TVD_HIP(hipEventRecord(ev_poll_, s_));
-            std::swap(U_, X_);
+            // u^{k+1} = x: a copy rather than a pointer swap, so that every
+            // buffer keeps its address and captured PCG iterations stay valid
+            TVD_HIP(hipMemcpyAsync(U_, X_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
             if (pipelined && k + 1 < p.max_outer) {
                 enqueue_setup(k + 1);
                 setup_done = true;
@@ -1158,6 +1191,7 @@ class Solver final : public SolverBase {
     // b = H'v = H v in FP64 (into BD_).
     void rhs_reblur(const T* v) {
         BandArgsT<T, T, double, double> a{};
+        a.wrap = wrap_;
         a.ny = ny_;
         a.nx = nx_;
         a.wy = my_;
@@ -1172,6 +1206,7 @@ class Solver final : public SolverBase {
     // r = b - A'x with FP64 coefficients and ||r||^2 partials (one per step).
     void residual_reblur(const T* x, T* r, double* rr_out) {
         BandArgsT<T, T, double, T> a{};
+        a.wrap = wrap_;
         a.ny = ny_;
         a.nx = nx_;
         a.wy = 2 * my_;
@@ -1181,6 +1216,7 @@ class Solver final : public SolverBase {
         a.Bx = KxRD_;
         a.X = x;
         a.kap = Kapd_;
+        a.cst = l_bc_ == TVD_BC_ANTIREFLECTIVE ? CstD_ : nullptr;
         a.alpha = alpha_;
         a.Bvec = BD_;
         a.Y = r;
@@ -1193,6 +1229,7 @@ class Solver final : public SolverBase {
     // (and <q, q> when qq is set).
     void ypass_reblur(const T* z, T* q, const T* dotw, double* pq, double* qq) {
         YPassArgs<T> a{};
+        a.wrap = wrap_;
         a.ny = ny_;
         a.nx = nx_;
         a.w = 2 * my_;
@@ -1209,6 +1246,7 @@ class Solver final : public SolverBase {
         a.khi = khiR_;
         a.dotw = dotw;
         a.qq_part = qq;
+        a.cst = l_bc_ == TVD_BC_ANTIREFLECTIVE ? Cst_ : nullptr;
         int nb = 0;
         timer_.begin(KernelTimer::kBand, s_);
         TVD_HIP(launch_ypass_full_bcg<T>(a, s_, &nb));
@@ -1340,7 +1378,21 @@ class Solver final : public SolverBase {
     void reblur_setup(const T* uk, double alpha, double beta, int variant) {
         reblur_mode_ = true;
         setup(uk, alpha, beta, variant);
+        if (l_bc_ == TVD_BC_ANTIREFLECTIVE) {
+            // L(u^k) under anti-reflective BCs: per-pixel stencil coefficients
+            // (FP64 for the residual, working precision for the operator);
+            // the preconditioner keeps the Neumann eigenvalues and D (the
+            // inner block of L is the same)
+            if (!CstD_) {
+                CstD_ = static_cast<double*>(geo_.alloc(4 * N_ * sizeof(double)));
+                Cst_ = static_cast<T*>(geo_.alloc(4 * N_ * sizeof(T)));
+            }
+            double* const cd[4] = {CstD_, CstD_ + N_, CstD_ + 2 * N_, CstD_ + 3 * N_};
+            T* const cw[4] = {Cst_, Cst_ + N_, Cst_ + 2 * N_, Cst_ + 3 * N_};
+            TVD_HIP(launch_kappa_ar<T>(ny_, nx_, uk, beta, cd, cw, s_));
+        }
     }
+    void set_reblur_l_bc(int l_bc) override { l_bc_ = l_bc; }
     void solve_reblur(const void* vv, void* uu, const tvd_params& p, tvd_stats& st) override {
         ensure_reblur();
         const auto t0 = std::chrono::steady_clock::now();
@@ -1363,9 +1415,11 @@ class Solver final : public SolverBase {
             bicgstab(maxit, tol, prev_iters);
             TVD_HIP(hipEventRecord(ev_c_, s_));
             TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+            // u^{k+1} = x by a copy (every work buffer keeps its address:
+            // the normal-equations solve replays captured iterations)
+            TVD_HIP(hipMemcpyAsync(U_, X_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
             TVD_HIP(hipStreamSynchronize(s_));
             timer_.harvest();
-            std::swap(U_, X_);
             float a = 0, b = 0;
             TVD_HIP(hipEventElapsedTime(&a, ev_a_, ev_b_));
             TVD_HIP(hipEventElapsedTime(&b, ev_b_, ev_c_));
@@ -1465,6 +1519,40 @@ class Solver final : public SolverBase {
         // idle while the host reads it; if the PCG had already stopped, that
         // iteration's kernels find the done flag and exit.
         int next_poll = std::max(2, predicted - 1);
+        if (transform && use_graphs_ && !timer_.on()) {
+            // The same iterations replayed from HIP graphs of two iterations
+            // each (captured once per starting iteration: the buffers and the
+            // stopping-test arguments depend on it), one chunk enqueued ahead
+            // of every poll.
+            check_pcg_graphs(xp, gm);
+            auto chunk = [&](int i) -> int {
+                if (i + 1 < maxit) {
+                    TVD_HIP(hipGraphLaunch(pcg_graph(i, maxit, xp, gm), s_));
+                    return i + 1;
+                }
+                enqueue_iteration(i, maxit, xp, gm);
+                return i;
+            };
+            int it = 1;
+            while (it <= maxit) {
+                const int last = chunk(it);
+                it = last + 1;
+                if (last >= next_poll && last < maxit) {
+                    TVD_HIP(hipMemcpyAsync(host_st_, st_, sizeof(PcgState), hipMemcpyDeviceToHost, s_));
+                    TVD_HIP(hipEventRecord(ev_poll_, s_));
+                    if (it <= maxit) it = chunk(it) + 1;
+                    TVD_HIP(hipEventSynchronize(ev_poll_));
+                    if (host_st_->done) break;
+                    next_poll = it;
+                }
+            }
+            last_rr = rr_[0];
+            last_rr_n = gm ? nb_upd_ : gx_.blocks;
+            int nfp = 0;
+            TVD_HIP(launch_fpchange<T>(int(N_), X_, U_, fp_, &nfp, s_));
+            TVD_HIP(launch_finalize<T>(st_, last_rr, last_rr_n, fp_, nfp, maxit, s_));
+            return;
+        }
         bool ahead = false;  // iteration it was enqueued during the last poll
         for (int it = 1; it <= maxit; ++it) {
             if (ahead) {
@@ -1514,6 +1602,62 @@ class Solver final : public SolverBase {
         int nfp = 0;
         TVD_HIP(launch_fpchange<T>(int(N_), X_, U_, fp_, &nfp, s_));
         TVD_HIP(launch_finalize<T>(st_, last_rr, last_rr_n, fp_, nfp, maxit, s_));
+    }
+
+    // Graphs of two PCG iterations from iteration it (transform
+    // preconditioners).  What the captured launches bake in -- buffers,
+    // alpha, the variant, the transform form, the block counts -- is
+    // recorded, and the graphs are dropped when any of it changes.
+    struct GraphSig {
+        const void *st, *x, *u, *r;
+        double alpha;
+        int variant, tmode, xp, gm, n_pq, n_rz, nb_upd;
+        bool operator==(const GraphSig& o) const {
+            return st == o.st && x == o.x && u == o.u && r == o.r && alpha == o.alpha && variant == o.variant &&
+                   tmode == o.tmode && xp == o.xp && gm == o.gm && n_pq == o.n_pq && n_rz == o.n_rz &&
+                   nb_upd == o.nb_upd;
+        }
+    };
+    void check_pcg_graphs(bool xp, bool gm) {
+        const GraphSig g{st_, X_, U_, R_, alpha_, variant_, tmode_, int(xp), int(gm), n_pq_, n_rz_, nb_upd_};
+        if (!(g == graph_sig_)) {
+            clear_pcg_graphs();
+            graph_sig_ = g;
+        }
+    }
+    void clear_pcg_graphs() {
+        for (auto& kv : pgraphs_) (void)hipGraphExecDestroy(kv.second);
+        pgraphs_.clear();
+        graph_sig_ = GraphSig{};
+    }
+    hipGraphExec_t pcg_graph(int it, int maxit, bool xp, bool gm) {
+        auto f = pgraphs_.find(it);
+        if (f != pgraphs_.end()) return f->second;
+        // captured on a private non-blocking stream (the caller's stream may
+        // be the null stream, which cannot capture); replayed on the caller's
+        if (!cap_s_) TVD_HIP(hipStreamCreateWithFlags(&cap_s_, hipStreamNonBlocking));
+        const hipStream_t home = s_;
+        hipGraph_t g = nullptr;
+        TVD_HIP(hipStreamBeginCapture(cap_s_, hipStreamCaptureModeRelaxed));
+        s_ = cap_s_;
+        try {
+            enqueue_iteration(it, maxit, xp, gm);
+            enqueue_iteration(it + 1, maxit, xp, gm);
+        } catch (...) {
+            s_ = home;
+            hipGraph_t dummy = nullptr;
+            (void)hipStreamEndCapture(cap_s_, &dummy);
+            if (dummy) (void)hipGraphDestroy(dummy);
+            throw;
+        }
+        s_ = home;
+        TVD_HIP(hipStreamEndCapture(cap_s_, &g));
+        hipGraphExec_t e = nullptr;
+        const hipError_t rc = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        TVD_HIP(rc);
+        pgraphs_[it] = e;
+        return e;
     }
 
     // The launches of transform-preconditioned PCG iteration it (as in pcg's
@@ -1718,9 +1862,14 @@ class Solver final : public SolverBase {
         struct Restore {
             Solver* s;
             WorkPtrs own;
-            ~Restore() { s->set_work(own); }
-        } guard{this, work()};
+            ~Restore() {
+                s->set_work(own);
+                s->use_graphs_ = graphs;
+            }
+            bool graphs;
+        } guard{this, work(), use_graphs_};
         set_work(w);
+        use_graphs_ = false;  // instantiating a graph allocates
         solve(v, u, p, st);
     }
     void get_times(tvd_kernel_times* out) override { timer_.fill(out); }
@@ -1803,6 +1952,7 @@ class Solver final : public SolverBase {
     }
     BandArgs<T> band_base() const {
         BandArgs<T> a{};
+        a.wrap = wrap_;
         a.ny = ny_;
         a.nx = nx_;
         return a;
@@ -1869,6 +2019,11 @@ class Solver final : public SolverBase {
     size_t max_lds_;
     DeviceArena geo_;
     int bc_ = 0, my_ = 0, mx_ = 0, rank_ = 0;
+    int wrap_ = 0;  // periodic BCs: every band and tile halo wraps around
+    bool use_graphs_ = true;  // replay PCG iterations from HIP graphs (off in the allocation-free solve)
+    hipStream_t cap_s_ = nullptr;  // capture stream of those graphs
+    std::map<int, hipGraphExec_t> pgraphs_;
+    GraphSig graph_sig_{};
     bool fused_ = false;
     int ty_fused_ = 0, ty_h_ = 0, ty_ht_ = 0;
     const T *Hy_ = nullptr, *Hx_ = nullptr, *HTy_ = nullptr, *HTx_ = nullptr, *Ky_ = nullptr, *Kx_ = nullptr;
@@ -1923,6 +2078,9 @@ class Solver final : public SolverBase {
     double *bcg_rr_ = nullptr, *bcg_rho_ = nullptr, *y_sig_ = nullptr, *y_ts_ = nullptr, *y_tt_ = nullptr;
     int nb_bcg_ = 0, nb_yb_ = 0;
     BcgScalars* bcg_sc_ = nullptr;
+    int l_bc_ = 0;                  // BC of L in the reblurring system (0: zero-Neumann)
+    double* CstD_ = nullptr;        // anti-reflective L: 4 N stencil coefficients, FP64
+    T* Cst_ = nullptr;              // and in the working precision
 };
 
 
@@ -2631,8 +2789,10 @@ int check_psf_fits(tvdeblur_t h) {
     const int my = h->py / 2, mx = h->px / 2;
     if (h->bc == TVD_BC_ANTIREFLECTIVE && (my > h->ny - 1 || mx > h->nx - 1))
         return fail(h, TVD_ESIZE, "anti-reflective BCs need PSF half-width <= n-1");
-    if (h->bc == TVD_BC_REFLECTIVE && (my > h->ny || mx > h->nx))
-        return fail(h, TVD_ESIZE, "reflective BCs need PSF half-width <= n");
+    if ((h->bc == TVD_BC_REFLECTIVE || h->bc == TVD_BC_DIRICHLET) && (my > h->ny || mx > h->nx))
+        return fail(h, TVD_ESIZE, "reflective / zero-Dirichlet BCs need PSF half-width <= n");
+    if (h->bc == TVD_BC_PERIODIC && (4 * my + 1 > h->ny || 4 * mx + 1 > h->nx))
+        return fail(h, TVD_ESIZE, "periodic BCs need 4 m + 1 <= n (the wrapped band of H^T H)");
     return TVD_OK;
 }
 
@@ -2696,7 +2856,7 @@ int tvdeblur_set_psf(tvdeblur_t h, const double* psf_host, int py, int px) {
 
 int tvdeblur_set_bc(tvdeblur_t h, int bc) {
     if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
-    if (bc != TVD_BC_REFLECTIVE && bc != TVD_BC_ANTIREFLECTIVE) return fail(h, TVD_EINVAL, "bad boundary condition");
+    if (bc < TVD_BC_REFLECTIVE || bc > TVD_BC_PERIODIC) return fail(h, TVD_EINVAL, "bad boundary condition");
     h->bc = bc;
     h->built = false;
     if (!h->psf.empty()) return check_psf_fits(h);
@@ -2869,7 +3029,9 @@ int tvdeblur_batch_create(tvdeblur_batch_t* out, int count, const tvd_image_desc
     if (count < 1 || count > 4096) return bfail(nullptr, TVD_EINVAL, "count must be in 1..4096");
     if (!descs) return bfail(nullptr, TVD_EINVAL, "descs is NULL");
     if (precision != TVD_F64 && precision != TVD_F32_MIXED) return bfail(nullptr, TVD_EINVAL, "bad precision");
-    if (bc != TVD_BC_REFLECTIVE && bc != TVD_BC_ANTIREFLECTIVE) return bfail(nullptr, TVD_EINVAL, "bad boundary condition");
+    if (bc < TVD_BC_REFLECTIVE || bc > TVD_BC_DIRICHLET)
+        return bfail(nullptr, TVD_EINVAL, "bad boundary condition (the batching form takes reflective, "
+                                          "anti-reflective or zero-Dirichlet BCs)");
     for (int i = 0; i < count; ++i) {
         const tvd_image_desc& d = descs[i];
         const std::string who = "image " + std::to_string(i) + ": ";
@@ -3029,6 +3191,16 @@ int tvdeblur_solve_reblur(tvdeblur_t h, const void* v_dev, void* u_dev, const tv
         if (rc) return rc;
         tvd_stats local;
         h->solver->solve_reblur(v_dev, u_dev, *p, stats ? *stats : local);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_set_reblur_l_bc(tvdeblur_t h, int l_bc) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (l_bc != TVD_L_NEUMANN && l_bc != TVD_BC_ANTIREFLECTIVE)
+        return fail(h, TVD_EINVAL, "L takes zero-Neumann or anti-reflective BCs");
+    return guarded(h, [&]() {
+        h->solver->set_reblur_l_bc(l_bc);
         return TVD_OK;
     });
 }

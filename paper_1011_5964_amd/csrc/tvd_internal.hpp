@@ -89,6 +89,9 @@ struct BandArgsT {
     const PcgState* st;    // exit when st->done (nullable)
     int tile_y;            // tile height (8 or 16), chosen by the launcher
     int bgx, bgy;          // this image's grid (set by the launcher; batched launches)
+    int wrap;              // periodic BCs: the input wraps around (circulant bands)
+    const TA* cst;         // nullptr, or 4 N per-pixel stencil coefficients (up, down,
+                           // left, right; the anti-reflective L) used instead of kap
 };
 template <typename T>
 using BandArgs = BandArgsT<T, T, T, T>;
@@ -151,6 +154,9 @@ struct YPassArgs {
     // are <dotw, q> into pq_part and, when qq_part is set, <q, q> into it
     const T* dotw;
     double* qq_part;
+    int wrap;               // periodic BCs: tile halos wrap around (circulant bands)
+    const T* cst;           // BiCGstab form: nullptr, or 4 N per-pixel stencil
+                            // coefficients (the anti-reflective L) instead of kap
 };
 
 // Scalars of preconditioned BiCGstab carried between its launches: rho by
@@ -437,6 +443,9 @@ hipError_t launch_diag_update(int n, T* x, T* r, const T* p, const T* q, const T
                               int check, const double* rr_in, int n_rr_in, int* nblocks, hipStream_t s);
 
 template <typename T>
+hipError_t launch_kappa_ar(int ny, int nx, const T* u, double beta, double* const cdbl[4], T* const cw[4],
+                           hipStream_t s);
+template <typename T>
 hipError_t launch_kappa(int ny, int nx, const T* u, double alpha, double beta, int variant,
                         T* kap, double* kapd, T* s_apply, double* s_mu, double* Dd, hipStream_t s);
 hipError_t launch_gemm_operands(int ny, int nx, const double* kapd, const double* s_mu, double* A1,
@@ -476,10 +485,14 @@ int validate_psf(const double* h, int py, int px, std::string& err);
 PsfFactors factor_psf(const double* h, int py, int px);
 
 // Dense 1D blur matrix (n x n, row-major) of the 1D filter g (length 2m+1,
-// centre at m) under the boundary condition bc (1 reflective, 2 AR).
+// centre at m) under the boundary condition bc (1 reflective, 2 AR, 3 zero
+// Dirichlet, 4 periodic).
 std::vector<double> blur_matrix_1d(const std::vector<double>& g, int n, int bc);
 // Band of a dense n x n matrix: out[i*(2w+1) + d + w] = A[i][i+d] (0 outside).
 std::vector<double> band_of(const std::vector<double>& A, int n, int w);
+// Band of a circulant n x n matrix: out[i*(2w+1) + d + w] = A[i][(i+d) mod n]
+// (2w + 1 <= n, so no entry is counted twice).
+std::vector<double> band_wrapped(const std::vector<double>& A, int n, int w);
 std::vector<double> transpose(const std::vector<double>& A, int n);
 // Band rows [lo, hi) all equal one Toeplitz row; data = [that row | rows < lo
 // | rows >= hi], each 2w+1 wide (lo = hi = n when no row repeats).
@@ -490,9 +503,12 @@ struct ToeplitzBand {
 ToeplitzBand compress_band(const std::vector<double>& band, int n, int w);
 std::vector<double> matmul_tn(const std::vector<double>& A, const std::vector<double>& B, int n);
 
-// Basis matrix Phi[i*n + k] = phi_k(i) of the transform of the BC.
+// Basis matrix Phi[i*n + k] = phi_k(i) of the transform of the BC (DCT-II
+// for reflective and zero-Dirichlet, S^ for AR, the real Fourier basis for
+// periodic).
 std::vector<double> basis_matrix(int n, int bc);
-// lambda_H[k*nx + l] = h^(theta_k, theta_l) on the BC grid.
+// lambda_H[k*nx + l] = h^(theta_k, theta_l) on the BC grid; for zero
+// Dirichlet the optimal cosine-algebra projection diag(Q2 H Q2^T).
 std::vector<double> symbol_eigenvalues(const double* h, int py, int px, int ny, int nx, int bc);
 // T_n and T_n^{-1} of the anti-reflective algebra, row-major (n >= 3).
 void ar_transform_matrices(int n, std::vector<double>& T, std::vector<double>& Ti);

@@ -229,8 +229,13 @@ __device__ __forceinline__ void band_body(const BandArgsT<TX, TS, T, TOut>& a, i
         stage_lds<T>(PH * PW, tid, kBandThreads,
             [&](int k) -> T {
                 const int r = k / PW, c = k - r * PW;
-                const int gi = i0 - hy + r, gj = j0 - hx + c;
-                if (gi < 0 || gi >= ny || gj < 0 || gj >= nx) return T(0);
+                int gi = i0 - hy + r, gj = j0 - hx + c;
+                if (a.wrap) {  // periodic: the circulant bands read wrapped neighbours
+                    gi = ((gi % ny) + ny) % ny;
+                    gj = ((gj % nx) + nx) % nx;
+                } else if (gi < 0 || gi >= ny || gj < 0 || gj >= nx) {
+                    return T(0);
+                }
                 const size_t g = size_t(gi) * nx + gj;
                 if (!upd) return T(Xp[g]);
                 TX w = Zp[g];
@@ -367,12 +372,21 @@ __device__ __forceinline__ void band_body(const BandArgsT<TX, TS, T, TOut>& a, i
                 lf = pc[-1];
                 rt = pc[1];
             }
-            const T kc = a.kap[g];
             T lp = T(0);
-            if (gi > 0) lp += a.kap[g - nx] * (cen - up);
-            if (gi < ny - 1) lp += kc * (cen - dn);
-            if (gj > 0) lp += a.kap[g - 1] * (cen - lf);
-            if (gj < nx - 1) lp += kc * (cen - rt);
+            if (a.cst) {  // per-pixel stencil coefficients (anti-reflective L)
+                const T* c4 = a.cst;
+                const size_t N = size_t(ny) * nx;
+                if (gi > 0) lp += c4[g] * (cen - up);
+                if (gi < ny - 1) lp += c4[N + g] * (cen - dn);
+                if (gj > 0) lp += c4[2 * N + g] * (cen - lf);
+                if (gj < nx - 1) lp += c4[3 * N + g] * (cen - rt);
+            } else {
+                const T kc = a.kap[g];
+                if (gi > 0) lp += a.kap[g - nx] * (cen - up);
+                if (gi < ny - 1) lp += kc * (cen - dn);
+                if (gj > 0) lp += a.kap[g - 1] * (cen - lf);
+                if (gj < nx - 1) lp += kc * (cen - rt);
+            }
             res += T(a.alpha) * lp;
         } else if (a.dotmode == 1) {
             cen = P[(hy + ti) * PW + hx + tx];
@@ -1158,7 +1172,13 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
     for (int k = 0; k < kYFRegs; ++k) {
         const int e = tid + k * kYThreads;
         const int r = e / TW, c = e - r * TW;
-        const int gi = i0 - hy + r, gj = min(max(j0 - hx + c, 0), nx - 1);
+        int gi = i0 - hy + r, gj = j0 - hx + c;
+        if (a.wrap) {  // periodic: rows and columns of the halo wrap around
+            gi = ((gi % ny) + ny) % ny;
+            gj = ((gj % nx) + nx) % nx;
+        } else {
+            gj = min(max(gj, 0), nx - 1);
+        }
         const bool in = e < nreg && gi >= 0 && gi < ny;
         const size_t g = in ? size_t(gi) * nx + gj : 0;
         zv[k] = in ? a.z[g] : T(0);
@@ -1167,9 +1187,22 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
     const int gi = i0 + ty, gj = j0 + tx;
     const bool own = gi < ny && gj < nx;
     const size_t g = own ? size_t(gi) * nx + gj : 0;
-    const T kc = own ? a.kap[g] : T(0);
-    const T ku = (own && gi > 0) ? a.kap[g - nx] : T(0);
-    const T kl = (own && gj > 0) ? a.kap[g - 1] : T(0);
+    // stencil coefficients up / down / left / right: the cell diffusivity
+    // (zero-Neumann L) or the per-pixel ones of the anti-reflective L
+    T c_up, c_dn, c_lf, c_rt;
+    if (kBcg && a.cst) {
+        const size_t N = size_t(ny) * nx;
+        c_up = own ? a.cst[g] : T(0);
+        c_dn = own ? a.cst[N + g] : T(0);
+        c_lf = own ? a.cst[2 * N + g] : T(0);
+        c_rt = own ? a.cst[3 * N + g] : T(0);
+    } else {
+        const T kc = own ? a.kap[g] : T(0);
+        c_up = (own && gi > 0) ? a.kap[g - nx] : T(0);
+        c_lf = (own && gj > 0) ? a.kap[g - 1] : T(0);
+        c_dn = kc;
+        c_rt = kc;
+    }
     T dw = T(0);
     if constexpr (kBcg) dw = own ? a.dotw[g] : T(0);
     if (done) return;
@@ -1261,10 +1294,10 @@ __device__ __forceinline__ void ypass_full_body(const YPassArgs<T>& a, int bx, i
             kxp = band_dot(a.xband + size_t(rr) * bw, arow, bw);
         }
         T lp = T(0);
-        if (gi > 0) lp += ku * (pc - prow[-TW]);
-        if (gi < ny - 1) lp += kc * (pc - prow[TW]);
-        if (gj > 0) lp += kl * (pc - prow[-1]);
-        if (gj < nx - 1) lp += kc * (pc - prow[1]);
+        if (gi > 0) lp += c_up * (pc - prow[-TW]);
+        if (gi < ny - 1) lp += c_dn * (pc - prow[TW]);
+        if (gj > 0) lp += c_lf * (pc - prow[-1]);
+        if (gj < nx - 1) lp += c_rt * (pc - prow[1]);
         const T qv = kxp + T(a.alpha) * lp;
         a.q[g] = qv;
         if constexpr (kBcg) {
@@ -1895,6 +1928,76 @@ __global__ void k_kappa_b(const KappaArgs<T>* __restrict__ as) {
     const int i = blockIdx.y;
     if (i >= a.ny || j >= a.nx) return;
     kappa_at(i, j, a.ny, a.nx, a.u, a.alpha, a.beta, a.variant, a.kap, a.kapd, a.s_apply, a.s_mu, a.Dd);
+}
+
+// L(u^k) under anti-reflective BCs (the reblurring system's AR L): the
+// diffusivity on every face of the image, the ghost faces included, from the
+// anti-reflectively extended u^k (one ghost line per side, rows first, then
+// columns; on a row face the y-difference of the cell above it, on a column
+// face the x-difference of the cell left of it), folded into the four
+// coefficients of a 5-point stencil per pixel:
+//   (L y)_ij = cu (y_ij - y_i-1,j) + cd (y_ij - y_i+1,j) + cl (y_ij - y_i,j-1) + cr (y_ij - y_i,j+1)
+// interior rows: cu = kx(face above), cd = kx(face below); row 0: cu = 0,
+// cd = kx(face 1) - kx(ghost face 0) (the ghost flux reflects the first
+// difference); the last row: cu = kx(its upper face) - kx(ghost face),
+// cd = 0; columns alike.  Needs ny, nx >= 3.
+template <typename T>
+__global__ void k_kappa_ar(int ny, int nx, const T* __restrict__ u, double beta, double* cu, double* cd,
+                           double* cl, double* cr, T* cut, T* cdt, T* clt, T* crt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= nx) return;
+    const double b2 = beta * beta;
+    auto R = [&](int r, int c) -> double {  // rows extended, c in [0, nx)
+        if (r < 0) return 2.0 * double(u[c]) - double(u[size_t(nx) + c]);
+        if (r >= ny) return 2.0 * double(u[size_t(ny - 1) * nx + c]) - double(u[size_t(ny - 2) * nx + c]);
+        return double(u[size_t(r) * nx + c]);
+    };
+    auto E = [&](int r, int c) -> double {  // then columns
+        if (c < 0) return 2.0 * R(r, 0) - R(r, 1);
+        if (c >= nx) return 2.0 * R(r, nx - 1) - R(r, nx - 2);
+        return R(r, c);
+    };
+    // face f between rows f-1 and f (f = 0..ny), column j
+    auto KX = [&](int f) {
+        const double gx = E(f, j) - E(f - 1, j), gy = E(f - 1, j + 1) - E(f - 1, j);
+        return 1.0 / sqrt(gx * gx + gy * gy + b2);
+    };
+    // face f between columns f-1 and f (f = 0..nx), row i
+    auto KY = [&](int f) {
+        const double gy = E(i, f) - E(i, f - 1), gx = E(i + 1, f - 1) - E(i, f - 1);
+        return 1.0 / sqrt(gx * gx + gy * gy + b2);
+    };
+    double vu, vd, vl, vr;
+    if (i == 0) {
+        vu = 0.0;
+        vd = KX(1) - KX(0);
+    } else if (i == ny - 1) {
+        vu = KX(ny - 1) - KX(ny);
+        vd = 0.0;
+    } else {
+        vu = KX(i);
+        vd = KX(i + 1);
+    }
+    if (j == 0) {
+        vl = 0.0;
+        vr = KY(1) - KY(0);
+    } else if (j == nx - 1) {
+        vl = KY(nx - 1) - KY(nx);
+        vr = 0.0;
+    } else {
+        vl = KY(j);
+        vr = KY(j + 1);
+    }
+    const size_t g = size_t(i) * nx + j;
+    cu[g] = vu;
+    cd[g] = vd;
+    cl[g] = vl;
+    cr[g] = vr;
+    cut[g] = T(vu);
+    cdt[g] = T(vd);
+    clt[g] = T(vl);
+    crt[g] = T(vr);
 }
 
 __device__ __forceinline__ void operands_at(int i, int j, int ny, int nx, const double* __restrict__ kap,
@@ -2537,6 +2640,15 @@ hipError_t launch_kappa(int ny, int nx, const T* u, double alpha, double beta, i
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_kappa_ar(int ny, int nx, const T* u, double beta, double* const cdbl[4], T* const cw[4],
+                           hipStream_t s) {
+    dim3 grid((nx + 255) / 256, ny);
+    tvd_launch(k_kappa_ar<T>, grid, dim3(256), 0, s, ny, nx, u, beta, cdbl[0], cdbl[1], cdbl[2], cdbl[3], cw[0],
+               cw[1], cw[2], cw[3]);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm_operands(int ny, int nx, const double* kapd, const double* s_mu, double* A1,
                                 double* A2, double* A3, double* B1, double* B2, double* B3, hipStream_t s) {
     dim3 grid((nx + 255) / 256, ny);
@@ -2746,6 +2858,8 @@ hipError_t launch_ypass_full_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s
                                               int, const double*, int, int*, hipStream_t);                    \
     template hipError_t launch_kappa<T>(int, int, const T*, double, double, int, T*, double*, T*, double*,    \
                                         double*, hipStream_t);                                                \
+    template hipError_t launch_kappa_ar<T>(int, int, const T*, double, double* const[4], T* const[4],         \
+                                           hipStream_t);                                                      \
     template hipError_t launch_mu<T>(int, const double*, const double*, const double*, const double*, int,    \
                                      double, double*, T*, hipStream_t);                                       \
     template hipError_t launch_fpchange<T>(int, const T*, const T*, double*, int*, hipStream_t);              \

@@ -198,6 +198,10 @@ std::vector<double> blur_matrix_1d(const std::vector<double>& g, int n, int bc) 
             double* row = &H[size_t(i) * n];
             if (e >= 0 && e < n) {
                 row[e] += w;
+            } else if (bc == 3) {  // zero ghosts: Toeplitz
+                continue;
+            } else if (bc == 4) {  // periodic ghosts: circulant (m <= n)
+                row[(e % n + n) % n] += w;
             } else if (e < 0) {
                 const int j = -e;
                 if (bc == 2) {  // u~_{-j} = 2u_0 - u_j
@@ -217,6 +221,14 @@ std::vector<double> blur_matrix_1d(const std::vector<double>& g, int n, int bc) 
             }
         }
     return H;
+}
+
+std::vector<double> band_wrapped(const std::vector<double>& A, int n, int w) {
+    const int bw = 2 * w + 1;
+    std::vector<double> out(size_t(n) * bw, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int d = -w; d <= w; ++d) out[size_t(i) * bw + d + w] = A[size_t(i) * n + ((i + d) % n + n) % n];
+    return out;
 }
 
 std::vector<double> band_of(const std::vector<double>& A, int n, int w) {
@@ -333,7 +345,21 @@ std::vector<double> ar_end_weights(int n) {
 
 std::vector<double> basis_matrix(int n, int bc) {
     std::vector<double> P(size_t(n) * n, 0.0);
-    if (bc == 1) {  // DCT-II: phi_k(i) = sqrt((2 - [k=0])/n) cos(pi k (2i+1) / (2n))
+    if (bc == 4) {  // real Fourier: 1, cos/sin pairs of frequency f, (-1)^i for even n
+        for (int i = 0; i < n; ++i) {
+            P[size_t(i) * n] = 1.0 / std::sqrt(double(n));
+            for (int k = 1; k < n; ++k) {
+                const int f = (k + 1) / 2;
+                double v;
+                if (n % 2 == 0 && k == n - 1) v = ((i & 1) ? -1.0 : 1.0) / std::sqrt(double(n));
+                else if (k & 1) v = std::sqrt(2.0 / n) * cos_pi_frac(2LL * f * i, n);
+                else v = std::sqrt(2.0 / n) * sin_pi_frac(2LL * f * i, n);
+                P[size_t(i) * n + k] = v;
+            }
+        }
+        return P;
+    }
+    if (bc == 1 || bc == 3) {  // DCT-II: phi_k(i) = sqrt((2 - [k=0])/n) cos(pi k (2i+1) / (2n))
         for (int i = 0; i < n; ++i)
             for (int k = 0; k < n; ++k)
                 P[size_t(i) * n + k] =
@@ -356,21 +382,42 @@ std::vector<double> symbol_eigenvalues(const double* h, int py, int px, int ny, 
         if (bc == 1) {
             den = n;
             for (int k = 0; k < n; ++k) num[k] = k;
+        } else if (bc == 4) {  // 2 pi f / n for the cosine and sine rows of frequency f
+            den = n;
+            for (int k = 1; k < n; ++k) num[k] = 2LL * ((k + 1) / 2);
         } else {
             den = n - 1;
             for (int k = 1; k < n - 1; ++k) num[k] = k;
         }
     };
-    std::vector<long long> ny_num, nx_num;
-    long long dy, dx;
-    grid(ny, ny_num, dy);
-    grid(nx, nx_num, dx);
-    // lam = Cy h Cx^T, Cy[k][a] = cos(a theta_k)
-    std::vector<double> Cy(size_t(ny) * py), Cx(size_t(nx) * px);
-    for (int k = 0; k < ny; ++k)
-        for (int a = -my; a <= my; ++a) Cy[size_t(k) * py + a + my] = cos_pi_frac(a * ny_num[k], dy);
-    for (int l = 0; l < nx; ++l)
-        for (int b = -mx; b <= mx; ++b) Cx[size_t(l) * px + b + mx] = cos_pi_frac(b * nx_num[l], dx);
+    // lam = Cy h Cx^T with C[k][a] = cos(a theta_k) on the BC grid, or for
+    // zero-Dirichlet BCs (Toeplitz blur) C[k][a] = sum_i phi_k(i) phi_k(i+a)
+    // over the DCT-II basis: the optimal cosine-algebra projection
+    // diag(Q2 H Q2^T), the blur being sum_ab h_ab Z_a (x) Z_b with zero-fill
+    // shifts Z_a.
+    auto table = [&](int n, int m, std::vector<double>& C) {
+        const int w = 2 * m + 1;
+        C.assign(size_t(n) * w, 0.0);
+        if (bc == 3) {
+            const std::vector<double> P = basis_matrix(n, 3);  // P[i*n + k] = phi_k(i)
+            for (int k = 0; k < n; ++k)
+                for (int a = -m; a <= m; ++a) {
+                    double s = 0.0;
+                    const int lo = std::max(0, -a), hi = std::min(n, n - a);
+                    for (int i = lo; i < hi; ++i) s += P[size_t(i) * n + k] * P[size_t(i + a) * n + k];
+                    C[size_t(k) * w + a + m] = s;
+                }
+            return;
+        }
+        std::vector<long long> num;
+        long long den;
+        grid(n, num, den);
+        for (int k = 0; k < n; ++k)
+            for (int a = -m; a <= m; ++a) C[size_t(k) * w + a + m] = cos_pi_frac(a * num[k], den);
+    };
+    std::vector<double> Cy, Cx;
+    table(ny, my, Cy);
+    table(nx, mx, Cx);
     std::vector<double> tmp(size_t(ny) * px, 0.0);  // Cy h
     for (int k = 0; k < ny; ++k)
         for (int a = 0; a < py; ++a) {
@@ -390,7 +437,7 @@ std::vector<double> symbol_eigenvalues(const double* h, int py, int px, int ny, 
 AxisTables make_axis_tables(int n, int bc) {
     AxisTables t;
     t.n = n;
-    t.kind = (bc == 2) ? 1 : 2;
+    t.kind = (bc == 2) ? 1 : 2;  // zero-Dirichlet uses the reflective DCT-II
     t.L = (t.kind == 1) ? 2 * (n - 1) : 2 * n;
     if (is_pow2(t.L)) {
         t.M = t.L;

@@ -19,7 +19,7 @@ TVD_OK = 0
 ERRORS = {-1: "TVD_EINVAL", -2: "TVD_ENOTSYM", -3: "TVD_ENORM", -4: "TVD_ESIZE", -5: "TVD_ESTATE",
           -6: "TVD_EDEVICE", -7: "TVD_EBREAKDOWN", -8: "TVD_ENOMEM"}
 PRECISION = {"f64": 0, "f32_mixed": 1}
-BC = {"reflective": 1, "antireflective": 2}
+BC = {"reflective": 1, "antireflective": 2, "dirichlet": 3, "periodic": 4}
 PRECOND = {"none": 0, "diag": 1, "x": 2, "d_x": 3, "x_d": 4}
 # preconditioners of the reblurring system: I, D and P, D_P, P_D (Section 3)
 # on the same enum slots
@@ -38,7 +38,8 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_batch_get_info", "tvdeblur_batch_destroy", "tvdeblur_batch_last_error",
     "tvdeblur_set_transform", "tvdeblur_get_transform", "tvdeblur_time_kernel",
     "tvdeblur_solve_reblur", "tvdeblur_op_reblur_setup", "tvdeblur_op_reblur_normal",
-    "tvdeblur_op_reblur_precond", "tvdeblur_solve_noalloc",
+    "tvdeblur_op_reblur_precond", "tvdeblur_solve_noalloc", "tvdeblur_signals_create", "tvdeblur_signals_solve",
+    "tvdeblur_signals_destroy", "tvdeblur_signals_last_error", "tvdeblur_set_reblur_l_bc",
 )
 BATCH_PRECOND = ("x", "d_x", "x_d")
 
@@ -103,6 +104,19 @@ class BatchInfo(ctypes.Structure):
                 ("time_inner_s", ctypes.c_double)]
 
 
+class SignalDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("psf_host", ctypes.POINTER(ctypes.c_double)), ("plen", ctypes.c_int),
+                ("bc", ctypes.c_int), ("reblur", ctypes.c_int)]
+
+
+class SignalParams(ctypes.Structure):
+    _fields_ = [("alpha_host", ctypes.POINTER(ctypes.c_double)), ("beta_host", ctypes.POINTER(ctypes.c_double)),
+                ("beta", ctypes.c_double), ("precond_host", ctypes.POINTER(ctypes.c_int)), ("precond", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("fp_tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("max_inner", ctypes.c_int), ("replay_host", ctypes.POINTER(ctypes.c_int)),
+                ("system_host", ctypes.POINTER(ctypes.c_int)), ("system", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -144,12 +158,16 @@ def load():
         "tvdeblur_batch_destroy": [vp],
         "tvdeblur_set_transform": [vp, i],
         "tvdeblur_get_transform": [vp, ctypes.POINTER(i)],
+        "tvdeblur_signals_create": [ctypes.POINTER(vp), i, ctypes.POINTER(SignalDesc), vp],
+        "tvdeblur_signals_solve": [vp, vp, vp, ctypes.POINTER(SignalParams), ctypes.POINTER(Stats)],
+        "tvdeblur_signals_destroy": [vp],
+        "tvdeblur_set_reblur_l_bc": [vp, i],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = i
-    for name in ("tvdeblur_last_error", "tvdeblur_batch_last_error"):
+    for name in ("tvdeblur_last_error", "tvdeblur_batch_last_error", "tvdeblur_signals_last_error"):
         getattr(lib, name).argtypes = [vp]
         getattr(lib, name).restype = ctypes.c_char_p
     _lib = lib
@@ -261,6 +279,11 @@ class TVDeblur:
         del keep
         self._check(rc)
         return out, st.to_dict()
+
+    def set_reblur_l_bc(self, l_bc):
+        """BC of L(u^k) in the reblurring system: 'neumann' (default) or
+        'antireflective'."""
+        self._check(self.lib.tvdeblur_set_reblur_l_bc(self.h, {"neumann": 0, "antireflective": 2}[l_bc]))
 
     def solve_reblur(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="p_d", fp_tol=0.0,
                      u0=None, replay=None, iterates=None, out=None):
@@ -523,3 +546,124 @@ class AlphaSweep:
 
     def close(self):
         self.batch.close()
+
+
+class TVDeblurSignals:
+    """Many independent 1D signals (tvdeblur_signals_*): each its own length,
+    PSF and BC; every solve is one kernel launch.  Signals travel packed back
+    to back in one float64 device tensor (offsets() gives where each starts)."""
+
+    def __init__(self, ns, psfs, bcs, stream=None, reblur=None):
+        """reblur: None, or per signal whether to build the reblurring
+        system's tables (anti-reflective signals only)."""
+        import torch
+        self.lib = load()
+        self.ns = [int(n) for n in ns]
+        self.count = len(self.ns)
+        if len(psfs) != self.count or len(bcs) != self.count:
+            raise ValueError("one PSF and one BC per signal")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.device = stream.device
+        self._psfs = [np.ascontiguousarray(np.ravel(h), dtype=np.float64) for h in psfs]
+        descs = (SignalDesc * self.count)()
+        rb = [False] * self.count if reblur is None else list(reblur)
+        if len(rb) != self.count:
+            raise ValueError("one reblur flag per signal")
+        for i, (n, h, bc) in enumerate(zip(self.ns, self._psfs, bcs)):
+            descs[i].n, descs[i].plen, descs[i].bc, descs[i].reblur = n, h.size, BC[bc], 1 if rb[i] else 0
+            descs[i].psf_host = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_signals_create(ctypes.byref(s), self.count, descs,
+                                                  ctypes.c_void_p(stream.cuda_stream))
+        if rc != TVD_OK:
+            raise TvdError(rc, self.lib.tvdeblur_signals_last_error(None).decode())
+        self.s = s
+        self.total = sum(self.ns)
+
+    def offsets(self):
+        return [int(x) for x in np.concatenate([[0], np.cumsum(self.ns)[:-1]])]
+
+    def pack(self, signals):
+        """Device tensor holding the given 1D arrays back to back."""
+        import torch
+        flat = np.concatenate([np.ravel(np.asarray(x, dtype=np.float64)) for x in signals])
+        if flat.size != self.total:
+            raise ValueError(f"signals hold {flat.size} samples, the batch {self.total}")
+        return torch.tensor(flat, dtype=torch.float64, device=self.device)
+
+    def unpack(self, t):
+        a = t.detach().cpu().numpy()
+        return [a[o:o + n].copy() for o, n in zip(self.offsets(), self.ns)]
+
+    def close(self):
+        if getattr(self, "s", None):
+            self.lib.tvdeblur_signals_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, v, alphas, beta=0.1, betas=None, precond="x_d", max_outer=100, fp_tol=1e-3, inner_tol=1e-6,
+              max_inner=1000, replay=None, out=None, system="normal"):
+        """v: packed float64 device tensor.  precond: one name for all or a
+        list per signal (for the reblurring system 'none', 'diag', 'p',
+        'd_p', 'p_d').  system: 'normal' (eq. (fp), PCG) or 'reblur' (eq.
+        (fpp), PBiCGstab), one for all or a list.  replay: None or per signal
+        max_outer counts.  Returns (packed restored tensor, list of
+        per-signal stats dicts)."""
+        import torch
+        for name, t in (("v", v), ("out", out)):
+            if t is not None and (t.dtype != torch.float64 or t.numel() != self.total or not t.is_contiguous()
+                                  or t.device != self.device):
+                raise ValueError(f"{name} must be a contiguous float64 tensor of {self.total} samples on {self.device}")
+        if len(alphas) != self.count:
+            raise ValueError("one alpha per signal")
+        u = out if out is not None else torch.empty_like(v)
+        p = SignalParams()
+        keep = []
+        a = (ctypes.c_double * self.count)(*[float(x) for x in alphas])
+        keep.append(a)
+        p.alpha_host = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+        p.beta = float(beta)
+        if betas is not None:
+            if len(betas) != self.count:
+                raise ValueError("one beta per signal")
+            b = (ctypes.c_double * self.count)(*[float(x) for x in betas])
+            keep.append(b)
+            p.beta_host = ctypes.cast(b, ctypes.POINTER(ctypes.c_double))
+        systems = [system] * self.count if isinstance(system, str) else list(system)
+        precs = [precond] * self.count if isinstance(precond, str) else list(precond)
+        if len(systems) != self.count or len(precs) != self.count:
+            raise ValueError("one system and one preconditioner per signal")
+        codes = [(REBLUR_PRECOND if sy == "reblur" else PRECOND)[pr] for sy, pr in zip(systems, precs)]
+        pc = (ctypes.c_int * self.count)(*codes)
+        sy = (ctypes.c_int * self.count)(*[{"normal": 0, "reblur": 1}[x] for x in systems])
+        keep += [pc, sy]
+        p.precond_host = ctypes.cast(pc, ctypes.POINTER(ctypes.c_int))
+        p.system_host = ctypes.cast(sy, ctypes.POINTER(ctypes.c_int))
+        p.max_outer, p.fp_tol, p.inner_tol, p.max_inner = int(max_outer), float(fp_tol), float(inner_tol), int(max_inner)
+        if replay is not None:
+            if len(replay) != self.count:
+                raise ValueError("one replay row per signal")
+            rows = []
+            for r in replay:
+                if len(r) > int(max_outer):
+                    raise ValueError("replay row longer than max_outer")
+                rows.append(list(r) + [0] * (int(max_outer) - len(r)))
+            rp = (ctypes.c_int * (self.count * int(max_outer)))(*[int(x) for row in rows for x in row])
+            keep.append(rp)
+            p.replay_host = ctypes.cast(rp, ctypes.POINTER(ctypes.c_int))
+        stats = (Stats * self.count)()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tvdeblur_signals_solve(self.s, ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                                 ctypes.byref(p), stats)
+        del keep
+        if rc != TVD_OK:
+            raise TvdError(rc, self.lib.tvdeblur_signals_last_error(self.s).decode())
+        return u, [s.to_dict() for s in stats]

@@ -131,6 +131,35 @@ int main() {
         std::snprintf(what, sizeof what, "H H band and its compressed rows, n = %d", n);
         check(e < 64 * eps && ec == 0.0, what, std::fmax(e, ec));
     }
+    // periodic (bc 4): the real Fourier basis is orthonormal and diagonalises
+    // the circulant blur with the symbol at 2 pi f / n; zero-Dirichlet (bc 3):
+    // the eigenvalues equal diag(P^T H P) over the DCT-II basis
+    for (int n : {5, 8, 13, 16}) {
+        for (int m : {1, 2}) {
+            const std::vector<double> g = filter(m, unsigned(11 * n + m));
+            std::vector<double> h2(g.size());  // 1 x (2m+1) PSF
+            for (size_t i = 0; i < g.size(); ++i) h2[i] = g[i];
+            for (int bc : {3, 4}) {
+                const std::vector<double> H = tvd::blur_matrix_1d(g, n, bc);
+                const std::vector<double> P = tvd::basis_matrix(n, bc);  // P[i*n+k] = phi_k(i)
+                const std::vector<double> D = matmul(matmul(tvd::transpose(P, n), H, n), P, n);
+                const std::vector<double> O = matmul(tvd::transpose(P, n), P, n);
+                const std::vector<double> lam = tvd::symbol_eigenvalues(h2.data(), 1, 2 * m + 1, 3, n, bc);
+                double off = 0.0, diag = 0.0, orth = 0.0;
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        orth = std::fmax(orth, std::fabs(O[size_t(i) * n + j] - (i == j ? 1.0 : 0.0)));
+                        if (i == j) diag = std::fmax(diag, std::fabs(D[size_t(i) * n + i] - lam[i]));
+                        else off = std::fmax(off, std::fabs(D[size_t(i) * n + j]));
+                    }
+                char what[96];
+                std::snprintf(what, sizeof what, "%s basis and eigenvalues, n = %d, m = %d",
+                              bc == 4 ? "periodic" : "zero-Dirichlet", n, m);
+                const bool ok = orth < 64 * n * eps && diag < 1e3 * n * eps && (bc == 3 || off < 1e3 * n * eps);
+                check(ok, what, std::fmax(orth, std::fmax(diag, bc == 4 ? off : 0.0)));
+            }
+        }
+    }
     std::printf("%s\n", failures ? "FAILED" : "all ok");
     return failures ? 1 : 0;
 }

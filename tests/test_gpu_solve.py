@@ -322,3 +322,32 @@ def test_fp_tol_stops_where_the_oracle_stops(prec):
         err = rel2(ug, uo)
     print(f"rel err {err:.3e}", flush=True)
     assert err <= BAR[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
+def test_graph_replay_equals_stream_launches(prec, transform):
+    """Single-image PCG iterations replayed from HIP graphs give the same
+    bits as the same launches issued one by one on the stream (the path taken
+    while kernel profiling is on), on every fixed-point step, and again when
+    the cached graphs are replayed by later solves and after the parameters
+    change."""
+    from paper_1011_5964_amd.lib import TVDeblur
+    p = synth.config("c1")
+    h = TVDeblur(64, 64, prec)
+    h.set_psf(p.psf)
+    h.set_bc(p.bc)
+    h.set_transform(transform)
+    v = dev(p.v, prec)
+    runs = []
+    for alpha in (p.alpha, 3 * p.alpha, p.alpha):
+        h.set_profiling(1)
+        us, ss = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        h.set_profiling(0)
+        ug, sg = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        ug2, sg2 = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        print(f"alpha {alpha:.1e}: iters {sg['inner_iters']}", flush=True)
+        assert ss["inner_iters"] == sg["inner_iters"] == sg2["inner_iters"]
+        assert torch.equal(us, ug) and torch.equal(ug, ug2)
+        runs.append(ug)
+    assert torch.equal(runs[0], runs[2])

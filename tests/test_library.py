@@ -6,6 +6,7 @@ import re
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_1011_5964_amd import lib as L
@@ -31,7 +32,8 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 
 STRUCTS = {"tvd_params": L.Params, "tvd_stats": L.Stats, "tvd_kernel_times": L.KernelTimes,
-           "tvd_image_desc": L.ImageDesc, "tvd_batch_params": L.BatchParams, "tvd_batch_info": L.BatchInfo}
+           "tvd_image_desc": L.ImageDesc, "tvd_batch_params": L.BatchParams, "tvd_batch_info": L.BatchInfo,
+           "tvd_signal_desc": L.SignalDesc, "tvd_signal_params": L.SignalParams}
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="no C compiler")
@@ -121,3 +123,33 @@ def test_reblur_entry_points_reject_null_without_gpu():
     assert lib.tvdeblur_op_reblur_normal(None, None, None) == -1
     assert lib.tvdeblur_op_reblur_precond(None, None, None) == -1
     assert b"NULL" in lib.tvdeblur_last_error(None)
+
+
+@pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="library not built")
+def test_signals_and_noalloc_argument_errors_without_gpu():
+    """Argument checks of the 1D signal and allocation-free entry points run
+    before any device call."""
+    lib = L.load()
+    out = ctypes.c_void_p()
+    h = np.full(5, 0.2)
+    hp = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def descs(*rows):
+        arr = (L.SignalDesc * len(rows))()
+        for k, (n, plen, bc, ptr) in enumerate(rows):
+            arr[k].n, arr[k].plen, arr[k].bc, arr[k].psf_host = n, plen, bc, ptr
+        return arr
+
+    assert lib.tvdeblur_signals_create(ctypes.byref(out), 0, descs((10, 5, 2, hp)), None) == -1
+    assert lib.tvdeblur_signals_create(ctypes.byref(out), 1, descs((2, 5, 2, hp)), None) == -4
+    assert lib.tvdeblur_signals_create(ctypes.byref(out), 1, descs((10, 5, 7, hp)), None) == -1
+    assert lib.tvdeblur_signals_create(ctypes.byref(out), 1, descs((8, 5, 4, hp)), None) == -4  # 4m+1 > n
+    bad = np.array([0.1, 0.2, 0.4, 0.2, 0.1]) * 1.5
+    bp = bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.tvdeblur_signals_create(ctypes.byref(out), 1, descs((10, 5, 1, bp)), None) == -3
+    skew = np.array([0.1, 0.2, 0.4, 0.25, 0.05])
+    sp = skew.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.tvdeblur_signals_create(ctypes.byref(out), 1, descs((10, 5, 1, sp)), None) == -2
+    assert b"signal 0" in lib.tvdeblur_signals_last_error(None)
+    assert lib.tvdeblur_signals_solve(None, None, None, None, None) == -1
+    assert lib.tvdeblur_solve_noalloc(None, None, None, None, None) == -1
