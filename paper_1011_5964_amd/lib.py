@@ -610,13 +610,14 @@ class TVDeblurSignals:
             pass
 
     def solve(self, v, alphas, beta=0.1, betas=None, precond="x_d", max_outer=100, fp_tol=1e-3, inner_tol=1e-6,
-              max_inner=1000, replay=None, out=None, system="normal"):
+              max_inner=1000, replay=None, out=None, system="normal", allow_breakdown=False):
         """v: packed float64 device tensor.  precond: one name for all or a
         list per signal (for the reblurring system 'none', 'diag', 'p',
         'd_p', 'p_d').  system: 'normal' (eq. (fp), PCG) or 'reblur' (eq.
         (fpp), PBiCGstab), one for all or a list.  replay: None or per signal
-        max_outer counts.  Returns (packed restored tensor, list of
-        per-signal stats dicts)."""
+        max_outer counts.  allow_breakdown: return normally when a signal
+        broke down (its stats say so) instead of raising.  Returns (packed
+        restored tensor, list of per-signal stats dicts)."""
         import torch
         for name, t in (("v", v), ("out", out)):
             if t is not None and (t.dtype != torch.float64 or t.numel() != self.total or not t.is_contiguous()
@@ -664,6 +665,6 @@ class TVDeblurSignals:
             rc = self.lib.tvdeblur_signals_solve(self.s, ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                                  ctypes.byref(p), stats)
         del keep
-        if rc != TVD_OK:
+        if rc != TVD_OK and not (allow_breakdown and ERRORS.get(rc) == "TVD_EBREAKDOWN"):
             raise TvdError(rc, self.lib.tvdeblur_signals_last_error(self.s).decode())
         return u, [s.to_dict() for s in stats]
