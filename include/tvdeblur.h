@@ -101,6 +101,9 @@ typedef struct {
                                   reference that took the same number of steps */
     void*  iterates_dev;       /* NULL, or room for (max_outer+1) images: u^0..u^K are
                                   stored there (checkpoints for the adjoint) */
+    int    record_objective;   /* nonzero: tvdeblur_solve / _noalloc fill
+                                  tvd_stats.tv_objective (one extra blur and
+                                  reduction per step, FP64) */
 } tvd_params;
 
 typedef struct {
@@ -114,6 +117,11 @@ typedef struct {
     double time_total_s;                   /* wall time of the call */
     double time_setup_s;                   /* per-step setup (diffusivity, eigenvalues) */
     double time_inner_s;                   /* PCG loops */
+    double tv_objective[TVD_MAX_OUTER + 1]; /* with record_objective: T(u^0)..T(u^K) of
+                                              eq. (mp), 1/2 ||H u - v||^2 + alpha sum
+                                              sqrt(|grad u|^2 + beta^2) in FP64 (the
+                                              lagged-diffusivity steps decrease it);
+                                              else 0 */
 } tvd_stats;
 
 /* Create a handle for ny x nx images on the current HIP device, queuing
@@ -174,6 +182,24 @@ int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev,
 #define TVD_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 int tvdeblur_solve_noalloc(tvdeblur_t h, const void* v_dev, void* u_dev,
                            const tvd_params* p, tvd_stats* stats);
+
+/* Caller-owned work area for tvdeblur_solve (Section 5's PCG vectors, in
+ * memory the caller's allocator owns, e.g. a torch tensor).
+ * tvdeblur_workspace_bytes builds the handle for its PSF and BC if needed
+ * (else TVD_ESTATE) and writes the bytes the area must hold: the per-solve
+ * work buffers (about 16 images in the working precision plus 2 FP64
+ * images, per-block partial sums and the control block).  The handle's
+ * tables and per-step eigenvalue arrays stay in its own memory.
+ * tvdeblur_set_workspace(h, ws_dev, bytes) makes every later tvdeblur_solve
+ * on h carve those buffers from ws_dev (device memory, 256-byte aligned,
+ * at least the size above, else TVD_EINVAL / TVD_ESIZE); ws_dev = NULL
+ * returns to the handle's own buffers.  The library never frees ws_dev:
+ * it must stay valid, and untouched by other work, while solves on h run.
+ * A later set_psf / set_bc that enlarges the need makes tvdeblur_solve fail
+ * with TVD_ESIZE until a large enough area is set.  Results are identical
+ * to those of the handle's own buffers. */
+int tvdeblur_workspace_bytes(tvdeblur_t h, size_t* bytes_out);
+int tvdeblur_set_workspace(tvdeblur_t h, void* ws_dev, size_t bytes);
 
 /* Differentiation form: reverse-mode derivative of the K fixed-point steps of
  * eq. (fp), u^{k+1} = (H^T H + alpha L(u^k))^{-1} H^T v with u^0 = v.

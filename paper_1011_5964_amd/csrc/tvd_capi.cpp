@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <map>
 #include <mutex>
@@ -17,6 +18,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "tvd_internal.hpp"
@@ -109,7 +111,10 @@ class SolverBase {
     // solve() with those work buffers carved from `base` (device memory of
     // at least work_bytes(), 256-byte aligned) in place of the handle's own;
     // the handle's tables and eigenvalue-setup arrays are used as they are.
-    virtual void solve_in(void* base, const void* v, void* u, const tvd_params& p, tvd_stats& st) = 0;
+    // graphs = false keeps PCG graph replay off (instantiating a graph
+    // allocates).
+    virtual void solve_in(void* base, const void* v, void* u, const tvd_params& p, tvd_stats& st,
+                          bool graphs) = 0;
 };
 
 // Per-class kernel timing with pairs of HIP events around launches.
@@ -936,6 +941,30 @@ class Solver final : public SolverBase {
         n_pq_ = nb_band_;
     }
 
+    // T(u) of eq. (mp) in FP64: H u with the FP64 bands, then per-block
+    // partials summed on the host in a fixed order (synchronises the stream).
+    double objective(const T* u, const T* v, double alpha, double beta) {
+        BandArgsT<T, T, double, double> a{};
+        a.wrap = wrap_;
+        a.ny = ny_;
+        a.nx = nx_;
+        a.wy = my_;
+        a.wx = mx_;
+        a.nterms = rank_;
+        a.By = HyD_;
+        a.Bx = HxD_;
+        a.X = u;
+        a.Y = TmpD_;
+        TVD_HIP(launch_band(a, pick_ty(a), s_, nullptr));
+        int nb = 0;
+        TVD_HIP(launch_objective<T>(ny_, nx_, TmpD_, v, u, alpha, beta, fp_, &nb, s_));
+        TVD_HIP(hipMemcpyAsync(obj_part_.data(), fp_, nb * sizeof(double), hipMemcpyDeviceToHost, s_));
+        TVD_HIP(hipStreamSynchronize(s_));
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t += obj_part_[b];
+        return t;
+    }
+
     // Per-step setup from u^k: kappa, D, s, mu.
     void setup(const T* uk, double alpha, double beta, int variant) {
         timer_.begin(KernelTimer::kSetup, s_, false);
@@ -1002,6 +1031,7 @@ class Solver final : public SolverBase {
             TVD_HIP(hipEventRecord(e[1], s_));
         };
         bool setup_done = false;
+        if (p.record_objective) st.tv_objective[0] = objective(U_, v, p.alpha, p.beta);
         for (int k = 0; k < p.max_outer; ++k) {
             if (iters_out)
                 TVD_HIP(hipMemcpyAsync(iters_out + size_t(k) * N_, U_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
@@ -1036,6 +1066,9 @@ class Solver final : public SolverBase {
             st.outer_steps = k + 1;
             prev_iters = std::max(1, hs.iters);
             if (hs.done != 1 && hs.iters >= maxit && !p.replay_host) st.all_converged = 0;
+            // T(u^{k+1}): U_ holds it once the copy above has run (the next
+            // step's setup, already queued, does not write U_)
+            if (p.record_objective) st.tv_objective[k + 1] = objective(U_, v, p.alpha, p.beta);
             if (hs.done == 2) {
                 st.breakdown = 1;
                 st.all_converged = 0;
@@ -1845,7 +1878,7 @@ class Solver final : public SolverBase {
         return 16 * al256(N_ * sizeof(T)) + 2 * al256(N_ * sizeof(double)) + 5 * al256(part_cap_ * sizeof(double)) +
                al256(2 * 1024 * sizeof(double)) + al256(sizeof(PcgState));
     }
-    void solve_in(void* base, const void* v, void* u, const tvd_params& p, tvd_stats& st) override {
+    void solve_in(void* base, const void* v, void* u, const tvd_params& p, tvd_stats& st, bool graphs) override {
         unsigned char* b = static_cast<unsigned char*>(base);
         auto take = [&](size_t bytes) {
             unsigned char* q = b;
@@ -1869,7 +1902,10 @@ class Solver final : public SolverBase {
             bool graphs;
         } guard{this, work(), use_graphs_};
         set_work(w);
-        use_graphs_ = false;  // instantiating a graph allocates
+        // captured graphs hold the work pointers; the graph signature holds
+        // the control block's address, which moves with `base`, so graphs
+        // taken in another work area are re-captured, not replayed
+        use_graphs_ = use_graphs_ && graphs;
         solve(v, u, p, st);
     }
     void get_times(tvd_kernel_times* out) override { timer_.fill(out); }
@@ -2041,6 +2077,7 @@ class Solver final : public SolverBase {
     LineGeom gxi_{};
     T *Tb_[2] = {nullptr, nullptr}, *W_ = nullptr;
     double *BD_ = nullptr, *TmpD_ = nullptr;
+    std::array<double, 1024> obj_part_{};  // host copy of the objective's block partials
     double *UbarD_ = nullptr, *VbarD_ = nullptr, *Gd_ = nullptr, *adj_part_ = nullptr;
     std::vector<double> lamh_host_;
     const double *lamh2_ = nullptr, *lamh_ = nullptr;
@@ -2759,6 +2796,8 @@ struct tvdeblur_handle {
     int bc = 0;
     bool built = false;
     bool last_u0_given = false;  // the last tvdeblur_solve started from u0_dev, not from v
+    void* ws = nullptr;          // caller-owned work area of tvdeblur_solve (nullable)
+    size_t ws_bytes = 0;
     std::unique_ptr<tvd::SolverBase> solver;
 };
 
@@ -2888,8 +2927,51 @@ int tvdeblur_solve(tvdeblur_t h, const void* v_dev, void* u_dev, const tvd_param
         int rc = ensure_built(h);
         if (rc) return rc;
         tvd_stats local;
+        if (h->ws) {
+            const size_t need = h->solver->work_bytes();
+            if (h->ws_bytes < need)
+                return fail(h, TVD_ESIZE,
+                            "workspace too small for the current PSF / BC: needs " + std::to_string(need) +
+                                " bytes, holds " + std::to_string(h->ws_bytes));
+            h->last_u0_given = p->u0_dev != nullptr;
+            h->solver->solve_in(h->ws, v_dev, u_dev, *p, stats ? *stats : local, true);
+            return TVD_OK;
+        }
         h->last_u0_given = p->u0_dev != nullptr;
         h->solver->solve(v_dev, u_dev, *p, stats ? *stats : local);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_workspace_bytes(tvdeblur_t h, size_t* bytes_out) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (!bytes_out) return fail(h, TVD_EINVAL, "NULL argument");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        *bytes_out = h->solver->work_bytes();
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_set_workspace(tvdeblur_t h, void* ws_dev, size_t bytes) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (!ws_dev) {
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+        return TVD_OK;
+    }
+    if (reinterpret_cast<uintptr_t>(ws_dev) % 256 != 0) return fail(h, TVD_EINVAL, "workspace not 256-byte aligned");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        const size_t need = h->solver->work_bytes();
+        if (bytes < need)
+            return fail(h, TVD_ESIZE,
+                        "workspace too small: needs " + std::to_string(need) + " bytes, given " +
+                            std::to_string(bytes));
+        h->ws = ws_dev;
+        h->ws_bytes = bytes;
         return TVD_OK;
     });
 }
@@ -2946,7 +3028,7 @@ int tvdeblur_solve_noalloc(tvdeblur_t h, const void* v_dev, void* u_dev, const t
         void* base = scratch_address(h->device);
         tvd_stats local;
         h->last_u0_given = p->u0_dev != nullptr;
-        h->solver->solve_in(base, v_dev, u_dev, *p, stats ? *stats : local);
+        h->solver->solve_in(base, v_dev, u_dev, *p, stats ? *stats : local, false);
         return TVD_OK;
     });
 }

@@ -446,6 +446,9 @@ template <typename T>
 hipError_t launch_kappa_ar(int ny, int nx, const T* u, double beta, double* const cdbl[4], T* const cw[4],
                            hipStream_t s);
 template <typename T>
+hipError_t launch_objective(int ny, int nx, const double* hu, const T* v, const T* u, double alpha, double beta,
+                            double* part, int* nblocks, hipStream_t s);
+template <typename T>
 hipError_t launch_kappa(int ny, int nx, const T* u, double alpha, double beta, int variant,
                         T* kap, double* kapd, T* s_apply, double* s_mu, double* Dd, hipStream_t s);
 hipError_t launch_gemm_operands(int ny, int nx, const double* kapd, const double* s_mu, double* A1,

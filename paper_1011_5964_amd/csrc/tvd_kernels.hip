@@ -2080,6 +2080,25 @@ __global__ void k_copy_b(const CopyArgs<T>* __restrict__ as) {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += gridDim.x * blockDim.x) a.dst[k] = a.src[k];
 }
 
+// Per-block FP64 partials of the TV objective of eq. (mp),
+// T(u) = 1/2 ||H u - v||^2 + alpha sum sqrt(|D u|^2 + beta^2), from H u (FP64).
+template <typename T>
+__global__ void k_objective(int ny, int nx, const double* __restrict__ hu, const T* __restrict__ v,
+                            const T* __restrict__ u, double alpha, double beta, double* part) {
+    __shared__ double red[17];
+    const size_t n = size_t(ny) * nx;
+    double acc = 0.0;
+    for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += size_t(gridDim.x) * blockDim.x) {
+        const int i = int(g / nx), j = int(g - size_t(i) * nx);
+        const double c = u[g], r = hu[g] - double(v[g]);
+        const double dx = i < ny - 1 ? double(u[g + nx]) - c : 0.0;
+        const double dy = j < nx - 1 ? double(u[g + 1]) - c : 0.0;
+        acc += 0.5 * r * r + alpha * sqrt(dx * dx + dy * dy + beta * beta);
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 template <typename T>
 __global__ void k_fpchange(int n, const T* x, const T* u, double* part) {
     __shared__ double red[17];
@@ -2671,6 +2690,15 @@ hipError_t launch_mu(int n, const double* lamh2, const double* lamx, const doubl
 }
 
 template <typename T>
+hipError_t launch_objective(int ny, int nx, const double* hu, const T* v, const T* u, double alpha, double beta,
+                            double* part, int* nblocks, hipStream_t s) {
+    const int nb = std::max(1, std::min(1024, int((size_t(ny) * nx + 255) / 256)));
+    *nblocks = nb;
+    tvd_launch(k_objective<T>, dim3(nb), dim3(256), 0, s, ny, nx, hu, v, u, alpha, beta, part);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_fpchange(int n, const T* x, const T* u, double* part, int* nblocks, hipStream_t s) {
     const int nb = elem_blocks(n, 256, 512);
     *nblocks = nb;
@@ -2860,6 +2888,8 @@ hipError_t launch_ypass_full_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s
                                         double*, hipStream_t);                                                \
     template hipError_t launch_kappa_ar<T>(int, int, const T*, double, double* const[4], T* const[4],         \
                                            hipStream_t);                                                      \
+    template hipError_t launch_objective<T>(int, int, const double*, const T*, const T*, double, double,      \
+                                            double*, int*, hipStream_t);                                      \
     template hipError_t launch_mu<T>(int, const double*, const double*, const double*, const double*, int,    \
                                      double, double*, T*, hipStream_t);                                       \
     template hipError_t launch_fpchange<T>(int, const T*, const T*, double*, int*, hipStream_t);              \

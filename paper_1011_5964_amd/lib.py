@@ -40,6 +40,7 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_solve_reblur", "tvdeblur_op_reblur_setup", "tvdeblur_op_reblur_normal",
     "tvdeblur_op_reblur_precond", "tvdeblur_solve_noalloc", "tvdeblur_signals_create", "tvdeblur_signals_solve",
     "tvdeblur_signals_destroy", "tvdeblur_signals_last_error", "tvdeblur_set_reblur_l_bc",
+    "tvdeblur_workspace_bytes", "tvdeblur_set_workspace",
 )
 BATCH_PRECOND = ("x", "d_x", "x_d")
 
@@ -55,7 +56,7 @@ class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("fp_tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_inner", ctypes.c_int),
                 ("precond", ctypes.c_int), ("u0_dev", ctypes.c_void_p), ("replay_host", ctypes.POINTER(ctypes.c_int)),
-                ("iterates_dev", ctypes.c_void_p)]
+                ("iterates_dev", ctypes.c_void_p), ("record_objective", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -63,11 +64,13 @@ class Stats(ctypes.Structure):
                 ("relres", ctypes.c_double * MAX_OUTER), ("fp_change", ctypes.c_double * MAX_OUTER),
                 ("all_converged", ctypes.c_int), ("breakdown", ctypes.c_int),
                 ("total_inner_iters", ctypes.c_longlong), ("time_total_s", ctypes.c_double),
-                ("time_setup_s", ctypes.c_double), ("time_inner_s", ctypes.c_double)]
+                ("time_setup_s", ctypes.c_double), ("time_inner_s", ctypes.c_double),
+                ("tv_objective", ctypes.c_double * (MAX_OUTER + 1))]
 
     def to_dict(self):
         k = self.outer_steps
         return {"outer_steps": k, "inner_iters": list(self.inner_iters[:k]), "relres": list(self.relres[:k]),
+                "tv_objective": list(self.tv_objective[:k + 1]),
                 "fp_change": list(self.fp_change[:k]), "all_converged": bool(self.all_converged),
                 "breakdown": bool(self.breakdown), "total_inner_iters": int(self.total_inner_iters),
                 "time_total_s": self.time_total_s, "time_setup_s": self.time_setup_s,
@@ -162,6 +165,8 @@ def load():
         "tvdeblur_signals_solve": [vp, vp, vp, ctypes.POINTER(SignalParams), ctypes.POINTER(Stats)],
         "tvdeblur_signals_destroy": [vp],
         "tvdeblur_set_reblur_l_bc": [vp, i],
+        "tvdeblur_workspace_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "tvdeblur_set_workspace": [vp, vp, ctypes.c_size_t],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -228,8 +233,10 @@ class TVDeblur:
     def set_bc(self, bc):
         self._check(self.lib.tvdeblur_set_bc(self.h, BC[bc]))
 
-    def _params(self, alpha, beta, max_outer, inner_tol, max_inner, precond_code, fp_tol, u0, replay, iterates):
+    def _params(self, alpha, beta, max_outer, inner_tol, max_inner, precond_code, fp_tol, u0, replay, iterates,
+                objective=False):
         p = Params()
+        p.record_objective = 1 if objective else 0
         p.alpha, p.beta, p.max_outer = float(alpha), float(beta), int(max_outer)
         p.fp_tol, p.inner_tol, p.max_inner = float(fp_tol), float(inner_tol), int(max_inner)
         p.precond = precond_code
@@ -250,12 +257,13 @@ class TVDeblur:
         return p, keep
 
     def solve(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="x_d", fp_tol=0.0,
-              u0=None, replay=None, iterates=None, out=None):
+              u0=None, replay=None, iterates=None, out=None, objective=False):
+        """objective: also return T(u^0..u^K) of eq. (mp) in stats['tv_objective']."""
         import torch
         self._img(v, "v")
         u = self._img(out, "out") if out is not None else torch.empty_like(v)
         p, keep = self._params(alpha, beta, max_outer, inner_tol, max_inner, PRECOND[precond], fp_tol, u0,
-                               replay, iterates)
+                               replay, iterates, objective)
         st = Stats()
         with torch.cuda.device(self.device):
             rc = self.lib.tvdeblur_solve(self.h, _ptr(v), _ptr(u), ctypes.byref(p), ctypes.byref(st))
@@ -279,6 +287,27 @@ class TVDeblur:
         del keep
         self._check(rc)
         return out, st.to_dict()
+
+    def workspace_bytes(self):
+        """tvdeblur_workspace_bytes: bytes of a caller-owned work area for
+        solve (builds the handle for its PSF and BC)."""
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.tvdeblur_workspace_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def set_workspace(self, ws):
+        """tvdeblur_set_workspace: solve carves its work buffers from `ws`
+        (a contiguous device tensor of at least workspace_bytes() bytes,
+        256-byte aligned); None returns to the handle's own.  The handle
+        keeps a reference to `ws` while it is set."""
+        if ws is None:
+            self._check(self.lib.tvdeblur_set_workspace(self.h, None, 0))
+            self._ws = None
+            return
+        if not ws.is_cuda or not ws.is_contiguous():
+            raise ValueError("workspace must be a contiguous device tensor")
+        self._check(self.lib.tvdeblur_set_workspace(self.h, _ptr(ws), ws.numel() * ws.element_size()))
+        self._ws = ws
 
     def set_reblur_l_bc(self, l_bc):
         """BC of L(u^k) in the reblurring system: 'neumann' (default) or

@@ -153,3 +153,13 @@ def test_signals_and_noalloc_argument_errors_without_gpu():
     assert b"signal 0" in lib.tvdeblur_signals_last_error(None)
     assert lib.tvdeblur_signals_solve(None, None, None, None, None) == -1
     assert lib.tvdeblur_solve_noalloc(None, None, None, None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(L.LIB_PATH), reason="library not built")
+def test_workspace_argument_errors_without_gpu():
+    """The caller-workspace entry points reject a NULL handle before any
+    device call."""
+    lib = L.load()
+    n = ctypes.c_size_t(0)
+    assert lib.tvdeblur_workspace_bytes(None, ctypes.byref(n)) == -1
+    assert lib.tvdeblur_set_workspace(None, None, 0) == -1
