@@ -175,6 +175,8 @@ def measure(args, p, prec, steps, warmup, transform="auto", breakdown=True):
         "frac": round(ITER_WORDS * N * w / per_iter_s / 1e9 / HBM_PEAK_GBS, 4),
         "frac_with_transposes": round(ITER_WORDS_WITH_TRANSPOSES * N * w / per_iter_s / 1e9 / HBM_PEAK_GBS, 4)}
     res["transform"] = h.transform()
+    if res["transform"] == "gemm":
+        res["gemm_tile"] = h.gemm_tile()
     loop = {k: x for k, x in kt.items() if k in ALGO_WORDS and x["launches"] > 0}
     burst = {}
     for k in BURST_CLASSES:
@@ -259,8 +261,8 @@ def configs_form(args):
 
 
 def batch_form(args, p_ref_f64_restore_s):
-    """64-image ragged batch (FP32-mixed, graph replay) against 64
-    single-image solves of the same images (FP32-mixed and FP64)."""
+    """64-image ragged batch (FP32-mixed) against 64 single-image solves of
+    the same images (FP32-mixed and FP64; skipped with --no-sequential)."""
     import torch
     from paper_1011_5964_amd import synth
     from paper_1011_5964_amd.lib import TVDeblur, TVDeblurBatch
@@ -274,8 +276,9 @@ def batch_form(args, p_ref_f64_restore_s):
     last = {}
 
     def run():
+        # launches issued one by one: graph replay measured 0.5% slower here
         us, st = b.solve(vs, alphas, beta=0.05, max_outer=probs[0].n_outer, inner_tol=1e-6, max_inner=100,
-                         precond="x_d", use_graph=True)
+                         precond="x_d", use_graph=False)
         last["u"], last["st"] = us, st
         return us
 
@@ -289,7 +292,8 @@ def batch_form(args, p_ref_f64_restore_s):
            "all_converged": all(s["all_converged"] for s in last["st"]),
            "pcg_iters_total": int(sum(s["total_inner_iters"] for s in last["st"])),
            "tuning": {k: info[k] for k in ("line_threads", "tables_in_lds", "from_cache", "candidates",
-                                           "candidate_us", "gemm_us", "transform")},
+                                           "candidate_us", "gemm_us", "gemm64_us", "gemm_tile",
+                                           "transform")},
            "setup_share": info["time_setup_s"] / t_batch}
     # the batch's PCG loops against the HBM roofline: every image's 13 words
     # per pixel per iteration it ran, over the batch's inner-loop time
@@ -299,7 +303,7 @@ def batch_form(args, p_ref_f64_restore_s):
                                  "unit": "GB/s",
                                  "frac": round(algo / info["time_inner_s"] / 1e9 / HBM_PEAK_GBS, 4)}
     # 64 single-image solves, one after another, both precisions
-    for prec, dt in (("f32_mixed", torch.float32), ("f64", torch.float64)):
+    for prec, dt in () if args.no_sequential else (("f32_mixed", torch.float32), ("f64", torch.float64)):
         hs = []
         for p in probs:
             h = TVDeblur(*p.v.shape, prec)
@@ -315,8 +319,9 @@ def batch_form(args, p_ref_f64_restore_s):
         res[f"sequential_{prec}_s"] = st[0]
         for h, _, _ in hs:
             h.close()
-    res["speedup_vs_64_single_f32_mixed"] = res["sequential_f32_mixed_s"] / t_batch
-    res["speedup_vs_64_single_f64"] = res["sequential_f64_s"] / t_batch
+    if not args.no_sequential:
+        res["speedup_vs_64_single_f32_mixed"] = res["sequential_f32_mixed_s"] / t_batch
+        res["speedup_vs_64_single_f64"] = res["sequential_f64_s"] / t_batch
     b.close()
     return res, probs, last
 
@@ -593,6 +598,8 @@ def main():
                          "c3_disk, c5; any other than m512 makes the line a profiling record, not the metric")
     ap.add_argument("--precision", choices=("f32_mixed", "f64"), default="f32_mixed",
                     help="precision of the headline solves (profiling runs)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch form without its 64 single-image comparison solves (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy (y = -x, float32) of this many MiB three times: "
                          "the reference kernel that scales hardware traffic counters")

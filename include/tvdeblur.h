@@ -104,6 +104,14 @@ typedef struct {
     int    record_objective;   /* nonzero: tvdeblur_solve / _noalloc fill
                                   tvd_stats.tv_objective (one extra blur and
                                   reduction per step, FP64) */
+    int    use_graph;          /* nonzero: tvdeblur_solve replays the PCG iterations of
+                                  transform-preconditioned solves from HIP graphs of two
+                                  iterations each (captured on first use, cached by the
+                                  handle); 0: the launches go one by one, which measured
+                                  faster on MI355X (512^2: 30.6 against 32.9 ms per
+                                  restore).  Same bits either way.  Ignored by
+                                  tvdeblur_solve_noalloc (instantiating a graph
+                                  allocates). */
 } tvd_params;
 
 typedef struct {
@@ -337,6 +345,20 @@ int tvdeblur_set_transform(tvdeblur_t h, int mode);
  * Errors: TVD_EINVAL, TVD_ESTATE, TVD_EDEVICE. */
 int tvdeblur_get_transform(tvdeblur_t h, int* active);
 
+/* Block tile of the matrix-core products (32: four waves split the K of one
+ * 32 x 32 tile; 64: a 64 x 64 tile, one 32 x 32 quadrant per wave) into
+ * *tile (host).  Picked with the transform form by timing at build (both
+ * tiles, interleaved, three times each; cached per process by shape, PSF
+ * widths, BC and precision).  Builds the handle first if needed.
+ * Errors: TVD_EINVAL, TVD_ESTATE, TVD_EDEVICE. */
+int tvdeblur_get_gemm_tile(tvdeblur_t h, int* tile);
+
+/* Request a block tile for the products: 0 (default) times both at build,
+ * 32 or 64 uses that one (takes effect now if the handle is built, else when
+ * it is).  The two differ only in rounding (the order of the K sums).
+ * Errors: TVD_EINVAL (other values). */
+int tvdeblur_set_gemm_tile(tvdeblur_t h, int tile);
+
 /* ---- kernel timing (HIP events on the handle's stream) ---- */
 
 #define TVD_KTIME_KINDS 12
@@ -418,6 +440,8 @@ typedef struct {
                                    stopping test skipped, as tvd_params.replay_host */
     int    transform;           /* TVD_TRANSFORM_AUTO (the implementation picked at
                                    create), TVD_TRANSFORM_FFT or TVD_TRANSFORM_GEMM */
+    int    gemm_tile;           /* block tile of the products: 0 (the one picked at
+                                   create), 32 or 64 */
 } tvd_batch_params;
 
 #define TVD_TUNE_MAX 4
@@ -429,11 +453,14 @@ typedef struct {
     int    n_candidates;                /* candidates timed (0 when from_cache) */
     int    cand_threads[TVD_TUNE_MAX];
     double cand_us[TVD_TUNE_MAX];       /* time of one set of transform passes */
-    double gemm_us;                     /* the same with the products on the matrix cores */
+    double gemm_us;                     /* the same with the products on the matrix cores
+                                           (32 x 32 block tiles) */
     int    transform;                   /* implementation of the last solve (TVD_TRANSFORM_*) */
     long long graph_launches;           /* graph replays since create */
     double time_setup_s;                /* last solve: diffusivity/eigenvalue setup */
     double time_inner_s;                /* last solve: PCG loops */
+    double gemm64_us;                   /* the products with 64 x 64 block tiles */
+    int    gemm_tile;                   /* block tile the products use (32 or 64) */
 } tvd_batch_info;
 
 /* Create a batch of `count` (1..4096) image problems on the current HIP

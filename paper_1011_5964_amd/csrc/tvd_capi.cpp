@@ -101,6 +101,10 @@ class SolverBase {
     // build, 1 = FFT line passes, 2 = products on the matrix cores.
     virtual void set_transform(int mode) = 0;
     virtual int transform() const = 0;
+    // block tile of the products (32 or 64), timed at build with the form
+    virtual int gemm_tile() const = 0;
+    // 0: time both tiles at build; 32 or 64: use that one
+    virtual void set_gemm_tile(int tile) = 0;
     virtual void get_times(tvd_kernel_times* out) = 0;
     // average duration of one PCG-loop kernel class in a back-to-back burst
     virtual double time_kernel(int kind, int reps) = 0;
@@ -137,6 +141,14 @@ class KernelTimer {
         used_ = 0;
     }
     bool on() const { return on_; }
+    // Sampling off for launches that are not the solve's own (the build-time
+    // timing of the transform forms); the counts gathered so far are kept.
+    bool suspend() {
+        const bool was = on_;
+        on_ = false;
+        return was;
+    }
+    void resume(bool was) { on_ = was; }
     // Bracket the launches of one kernel class.  single: exactly one kernel
     // follows, timed by events attached to its dispatch; otherwise marker
     // events are recorded around the launches.
@@ -487,31 +499,33 @@ class Solver final : public SolverBase {
         if (built_) choose_transform();
     }
     int transform() const override { return tmode_ == 1 ? 2 : 1; }
+    int gemm_tile() const override { return gtile_; }
+    void set_gemm_tile(int tile) override {
+        treq_tile_ = tile;
+        if (built_) choose_transform();
+    }
 
     // Transform implementation: forced, or the faster of the two on this
     // handle's shape (one preconditioner pass each, timed; cached per
     // process by shape, PSF widths, BC and element type).
     void choose_transform() {
         tmode_ = 0;
-        if (bc_ == TVD_BC_PERIODIC) {  // the real Fourier basis runs as products only
-            if (!gemm_ok_) throw ApiError{TVD_EINVAL, "periodic BCs need the matrix-core product form"};
-            tmode_ = 1;
-            return;
-        }
+        gtile_ = 32;
+        // periodic BCs: the real Fourier basis runs as products only
+        const bool forced = bc_ == TVD_BC_PERIODIC || (treq_ == 2 && gemm_ok_);
+        if (bc_ == TVD_BC_PERIODIC && !gemm_ok_) throw ApiError{TVD_EINVAL, "periodic BCs need the matrix-core product form"};
         if (!gemm_ok_ || treq_ == 1) return;
-        if (treq_ == 2) {
-            tmode_ = 1;
-            return;
-        }
         const std::string key = std::to_string(sizeof(T)) + ":" + std::to_string(bc_) + ":" + std::to_string(ny_) +
                                 "x" + std::to_string(nx_) + ":" + std::to_string(my_) + "x" + std::to_string(mx_) +
                                 ":" + std::to_string(int(xsplit_)) + std::to_string(int(xpass_)) +
-                                std::to_string(int(yfull_));
+                                std::to_string(int(yfull_)) + ":" + std::to_string(int(forced)) + ":" +
+                                std::to_string(treq_tile_);
         {
             std::lock_guard<std::mutex> lk(g_transform_mu);
             auto f = g_transform_cache.find(key);
             if (f != g_transform_cache.end()) {
-                tmode_ = f->second;
+                tmode_ = f->second & 1;
+                gtile_ = (f->second & 2) ? 64 : 32;
                 return;
             }
         }
@@ -519,12 +533,22 @@ class Solver final : public SolverBase {
         TVD_HIP(hipMemsetAsync(Sap_, 0, N_ * sizeof(T), s_));
         TVD_HIP(hipMemsetAsync(MuInv_, 0, N_ * sizeof(T), s_));
         TVD_HIP(launch_init_state(st_, 0.0, s_));
-        // both forms timed three times, interleaved; the product form must win
-        // by 5% to replace the line transforms (a near tie keeps the default)
-        float best[2] = {1e30f, 1e30f};
+        struct Quiet {  // these launches are not sampled by the kernel timer
+            KernelTimer& t;
+            bool was;
+            ~Quiet() { t.resume(was); }
+        } quiet{timer_, timer_.suspend()};
+        // candidates: 0 line transforms, 1 products with 32 x 32 block tiles,
+        // 2 products with 64 x 64 block tiles; each timed three times,
+        // interleaved.  The faster tile is kept; the product form must then
+        // win by 5% to replace the line transforms (a near tie keeps the
+        // default).
+        float best[3] = {1e30f, 1e30f, 1e30f};
         for (int rep = 0; rep < 3; ++rep) {
-            for (int mode = 0; mode < 2; ++mode) {
-                tmode_ = mode;
+            for (int mode = forced ? 1 : 0; mode < 3; ++mode) {
+                if ((mode == 1 && treq_tile_ == 64) || (mode == 2 && treq_tile_ == 32)) continue;
+                tmode_ = mode == 0 ? 0 : 1;
+                gtile_ = mode == 2 ? 64 : 32;
                 // a preconditioner application and the y-pass of the next operator
                 auto pass = [&]() {
                     precond_pass(R_, Z_, rz_[0], xsplit_);
@@ -540,9 +564,11 @@ class Solver final : public SolverBase {
                 best[mode] = std::min(best[mode], ms);
             }
         }
-        tmode_ = best[1] < 0.95f * best[0] ? 1 : 0;
+        const int g = best[2] < best[1] ? 2 : 1;
+        gtile_ = g == 2 ? 64 : 32;
+        tmode_ = (forced || best[g] < 0.95f * best[0]) ? 1 : 0;
         std::lock_guard<std::mutex> lk(g_transform_mu);
-        g_transform_cache[key] = tmode_;
+        g_transform_cache[key] = tmode_ | (gtile_ == 64 ? 2 : 0);
     }
 
     // One application of the transform preconditioner to r (no stopping
@@ -621,6 +647,7 @@ class Solver final : public SolverBase {
         b.iter = it;
         b.M = ny_;
         b.N = nx_;
+        b.tile = gtile_;
         // T1^T = (t Px)^T
         g[0] = b;
         g[0].K = nx_;
@@ -657,7 +684,7 @@ class Solver final : public SolverBase {
         g[3].E2 = r;
         g[3].part = rz_out;
     }
-    int gemm_blocks() const { return ((ny_ + 31) / 32) * ((nx_ + 31) / 32); }
+    int gemm_blocks() const { return ((ny_ + gtile_ - 1) / gtile_) * ((nx_ + gtile_ - 1) / gtile_); }
 
     // Product form of one preconditioner application (see gemm_args), then
     // w = K_x z if xp.
@@ -1008,6 +1035,7 @@ class Solver final : public SolverBase {
     // -------------------------------------------------------------- solve
     void solve(const void* vv, void* uu, const tvd_params& p, tvd_stats& st) override {
         reblur_mode_ = false;
+        graph_req_ = p.use_graph != 0;
         const auto t0 = std::chrono::steady_clock::now();
         const T* v = static_cast<const T*>(vv);
         T* uout = static_cast<T*>(uu);
@@ -1217,6 +1245,7 @@ class Solver final : public SolverBase {
         y_ts_ = D(nb_yb_);
         y_tt_ = D(nb_yb_);
         bcg_sc_ = static_cast<BcgScalars*>(geo_.alloc(sizeof(BcgScalars)));
+        lines_part_ = D(part_cap_);
         TVD_HIP(hipStreamSynchronize(s_));
         reblur_ready_ = true;
     }
@@ -1293,6 +1322,7 @@ class Solver final : public SolverBase {
         b.iter = it;
         b.M = ny_;
         b.N = nx_;
+        b.tile = gtile_;
         MGemmArgs<T> g[4] = {b, b, b, b};
         g[0].K = nx_;
         g[0].A = T2_;
@@ -1322,6 +1352,34 @@ class Solver final : public SolverBase {
             TVD_HIP(launch_mgemm<T>(g[k], s_, &nb));
             timer_.end(s_);
         }
+    }
+    // The same application as three line-transform passes (the fast form of
+    // the T_n algebra, Section 3: T_n^{-1} = S^ after removing the linear
+    // interpolant of the end values, T_n = S^ followed by adding it back):
+    // rows T^{-1}; columns T^{-1}, 1/mu, T; rows T and the scaling.
+    void lines_reblur(int it, T* out) {
+        RowPassArgs<T> f = rowfwd_args(it, false, T2_, nullptr);
+        f.s = nullptr;  // T2_ already holds sc o vector
+        f.ramp = 1;
+        ColPassArgs<T> c = col_args(it, false, 0, nullptr);
+        c.ramp = 1;
+        RowPassArgs<T> i = rowinv_args(out, T1_, lines_part_, false);
+        i.ramp = 1;
+        timer_.begin(KernelTimer::kRowFwd, s_);
+        TVD_HIP(launch_rowpass<T>(f, s_));
+        timer_.end(s_);
+        timer_.begin(KernelTimer::kCol, s_);
+        TVD_HIP(launch_colpass<T>(c, s_));
+        timer_.end(s_);
+        timer_.begin(KernelTimer::kRowInv, s_);
+        TVD_HIP(launch_rowpass<T>(i, s_));
+        timer_.end(s_);
+    }
+    // P, D_P, P_D application in the form the handle's transform choice
+    // names: products (tmode 1) or line transforms.
+    void precond_reblur(int it, T* out) {
+        if (tmode_ == 1) products_reblur(it, out);
+        else lines_reblur(it, out);
     }
     // I, D (no transform): the stages write M^{-1} p and M^{-1} s straight
     // into p^ and s^; P, D_P, P_D: into the products' input.
@@ -1364,10 +1422,10 @@ class Solver final : public SolverBase {
     void bcg_iteration(int it) {
         const bool tr = reblur_transform();
         bcg_stage(it, 1);
-        if (tr) products_reblur(it, Ph_);
+        if (tr) precond_reblur(it, Ph_);
         ypass_reblur(Ph_, Vv_, Rh_, y_sig_, nullptr);
         bcg_stage(it, 2);
-        if (tr) products_reblur(it, Sh_);
+        if (tr) precond_reblur(it, Sh_);
         ypass_reblur(Sh_, Tv_, Sv_, y_ts_, y_tt_);
         bcg_stage(it, 3);
     }
@@ -1505,7 +1563,7 @@ class Solver final : public SolverBase {
             TVD_HIP(hipMemcpyAsync(z, r, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
         } else {
             upd_launch(0, false, static_cast<const T*>(r));  // T2_ = s o r (s = 1/D for D)
-            if (reblur_transform()) products_reblur(0, static_cast<T*>(z));
+            if (reblur_transform()) precond_reblur(0, static_cast<T*>(z));
             else TVD_HIP(hipMemcpyAsync(z, T2_, N_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
         }
         TVD_HIP(hipStreamSynchronize(s_));
@@ -1552,7 +1610,7 @@ class Solver final : public SolverBase {
         // idle while the host reads it; if the PCG had already stopped, that
         // iteration's kernels find the done flag and exit.
         int next_poll = std::max(2, predicted - 1);
-        if (transform && use_graphs_ && !timer_.on()) {
+        if (transform && use_graphs_ && graph_req_ && !timer_.on()) {
             // The same iterations replayed from HIP graphs of two iterations
             // each (captured once per starting iteration: the buffers and the
             // stopping-test arguments depend on it), one chunk enqueued ahead
@@ -1644,15 +1702,15 @@ class Solver final : public SolverBase {
     struct GraphSig {
         const void *st, *x, *u, *r;
         double alpha;
-        int variant, tmode, xp, gm, n_pq, n_rz, nb_upd;
+        int variant, tmode, xp, gm, n_pq, n_rz, nb_upd, gtile;
         bool operator==(const GraphSig& o) const {
             return st == o.st && x == o.x && u == o.u && r == o.r && alpha == o.alpha && variant == o.variant &&
                    tmode == o.tmode && xp == o.xp && gm == o.gm && n_pq == o.n_pq && n_rz == o.n_rz &&
-                   nb_upd == o.nb_upd;
+                   nb_upd == o.nb_upd && gtile == o.gtile;
         }
     };
     void check_pcg_graphs(bool xp, bool gm) {
-        const GraphSig g{st_, X_, U_, R_, alpha_, variant_, tmode_, int(xp), int(gm), n_pq_, n_rz_, nb_upd_};
+        const GraphSig g{st_, X_, U_, R_, alpha_, variant_, tmode_, int(xp), int(gm), n_pq_, n_rz_, nb_upd_, gtile_};
         if (!(g == graph_sig_)) {
             clear_pcg_graphs();
             graph_sig_ = g;
@@ -2056,7 +2114,8 @@ class Solver final : public SolverBase {
     DeviceArena geo_;
     int bc_ = 0, my_ = 0, mx_ = 0, rank_ = 0;
     int wrap_ = 0;  // periodic BCs: every band and tile halo wraps around
-    bool use_graphs_ = true;  // replay PCG iterations from HIP graphs (off in the allocation-free solve)
+    bool use_graphs_ = true;   // graphs allowed (off in the allocation-free solve)
+    bool graph_req_ = false;   // the current solve asked for graph replay (tvd_params.use_graph)
     hipStream_t cap_s_ = nullptr;  // capture stream of those graphs
     std::map<int, hipGraphExec_t> pgraphs_;
     GraphSig graph_sig_{};
@@ -2099,6 +2158,8 @@ class Solver final : public SolverBase {
     std::vector<GemmProblem> gemm1_host_, gemm2_host_;
     bool gemm_ok_ = false, built_ = false;
     int treq_ = 0, tmode_ = 0, nb_upd_ = 0, nb_g4_ = 0;
+    int gtile_ = 32;      // block tile of the products (32 or 64)
+    int treq_tile_ = 0;   // requested tile (0: timed)
     const T *Px_ = nullptr, *PxT_ = nullptr, *Py_ = nullptr, *PyT_ = nullptr;
     hipEvent_t ev_a_{}, ev_b_{}, ev_c_{};
     double alpha_ = 0, beta_ = 0;
@@ -2107,6 +2168,7 @@ class Solver final : public SolverBase {
     // reblurring system (built on first use)
     PsfFactors factors_{};
     bool reblur_ready_ = false, reblur_mode_ = false;
+    double* lines_part_ = nullptr;  // <r, z> partials of the reblurring line passes (unused)
     const T *KyR_ = nullptr, *xbandR_ = nullptr;
     const double *KyRD_ = nullptr, *KxRD_ = nullptr, *arwy_ = nullptr, *arwx_ = nullptr;
     int kloR_ = 0, khiR_ = 0;
@@ -2140,7 +2202,8 @@ class BatchBase {
 struct TuneChoice {
     int threads;
     bool tab_lds;
-    int mode = 0;  // 1: products on the matrix cores
+    int mode = 0;   // 1: products on the matrix cores
+    int tile = 32;  // their block tile
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune_cache;
@@ -2200,6 +2263,8 @@ class BatchSolver final : public BatchBase {
             bmode_ = mode;
             clear_graphs();
         }
+        const int tile = p.gemm_tile ? p.gemm_tile : tuned_tile_;
+        if (mode == 1 && tile != info_.gemm_tile) set_gemm_tile(tile);
         info_.transform = bmode_ == 1 ? TVD_TRANSFORM_GEMM : TVD_TRANSFORM_FFT;
         for (int i = 0; i < B_; ++i) {
             Solver<T>& S = *img_[i];
@@ -2448,8 +2513,8 @@ class BatchSolver final : public BatchBase {
                 m1.push_back(g[0]);
                 m4o.push_back(g[3]);
                 xa.push_back(S.xpass_args(S.Z_));
-                g_mg_.gx = std::max(g_mg_.gx, (S.nx_ + 31) / 32);
-                g_mg_.gy = std::max(g_mg_.gy, (S.ny_ + 31) / 32);
+                g_mg_.gx = std::max(g_mg_.gx, (S.nx_ + S.gtile_ - 1) / S.gtile_);
+                g_mg_.gy = std::max(g_mg_.gy, (S.ny_ + S.gtile_ - 1) / S.gtile_);
                 g_upd_.gx = std::max(g_upd_.gx, upd_block_count(N));
                 g_xp_.gx = std::max(g_xp_.gx, S.ny_);
                 g_xp_.lds = std::max(g_xp_.lds, size_t(S.nx_ + S.xband_len_) * sizeof(T));
@@ -2612,12 +2677,15 @@ class BatchSolver final : public BatchBase {
     // Pick the thread count of the transform passes by timing them on this
     // batch (forward row pass, column pass, inverse row pass with x-pass).
     void tune() {
+        info_.gemm_tile = 32;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto f = g_tune_cache.find(key_);
             if (f != g_tune_cache.end()) {
                 apply(f->second.threads, f->second.tab_lds);
                 tuned_mode_ = f->second.mode;
+                tuned_tile_ = f->second.tile;
+                set_gemm_tile(f->second.tile);
                 info_.from_cache = 1;
                 return;
             }
@@ -2671,32 +2739,51 @@ class BatchSolver final : public BatchBase {
         }
         if (best.threads == 0) throw ApiError{TVD_ESIZE, "no transform-pass geometry fits the batch"};
         apply(best.threads, best.tab_lds);
-        // the product form, against the best line-transform geometry; it must
+        // the product form with 32 x 32 and 64 x 64 block tiles, against the
+        // best line-transform geometry; the faster tile is kept, and it must
         // win by 5% (a near tie keeps the line transforms)
         best.mode = 0;
         if (gemm_ok_) {
             bmode_ = 1;
-            fill_tables();
-            auto pass = [&]() {
-                TVD_HIP(launch_upd_b<T>(upd0_, 0, g_upd_, s_));
-                gemm_pass(gm1n_, gm4_[0], 0);
-                ypass_b(y1_);
-            };
-            pass();
-            TVD_HIP(hipEventRecord(ev_a_, s_));
-            constexpr int kReps = 5;
-            for (int r = 0; r < kReps; ++r) pass();
-            TVD_HIP(hipEventRecord(ev_b_, s_));
-            TVD_HIP(hipEventSynchronize(ev_b_));
-            float ms = 0.f;
-            TVD_HIP(hipEventElapsedTime(&ms, ev_a_, ev_b_));
-            info_.gemm_us = 1e3 * ms / kReps;
-            if (info_.gemm_us < 0.95 * best_us) best.mode = 1;
+            double gbest = 0.0;
+            for (int tile : {32, 64}) {
+                set_gemm_tile(tile);
+                fill_tables();
+                auto pass = [&]() {
+                    TVD_HIP(launch_upd_b<T>(upd0_, 0, g_upd_, s_));
+                    gemm_pass(gm1n_, gm4_[0], 0);
+                    ypass_b(y1_);
+                };
+                pass();
+                TVD_HIP(hipEventRecord(ev_a_, s_));
+                constexpr int kReps = 5;
+                for (int r = 0; r < kReps; ++r) pass();
+                TVD_HIP(hipEventRecord(ev_b_, s_));
+                TVD_HIP(hipEventSynchronize(ev_b_));
+                float ms = 0.f;
+                TVD_HIP(hipEventElapsedTime(&ms, ev_a_, ev_b_));
+                const double us = 1e3 * ms / kReps;
+                if (tile == 32) info_.gemm_us = us;
+                else info_.gemm64_us = us;
+                if (gbest == 0.0 || us < gbest) {
+                    gbest = us;
+                    best.tile = tile;
+                }
+            }
+            set_gemm_tile(best.tile);
+            if (gbest < 0.95 * best_us) best.mode = 1;
             bmode_ = 0;
         }
         tuned_mode_ = best.mode;
+        tuned_tile_ = best.tile;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key_] = best;
+    }
+
+    void set_gemm_tile(int tile) {
+        for (auto& S : img_) S->gtile_ = tile;
+        info_.gemm_tile = tile;
+        clear_graphs();
     }
 
     bool apply(int threads, bool tab) {
@@ -2771,7 +2858,7 @@ class BatchSolver final : public BatchBase {
     bool gemm_ok_ = false;
     bool yfull_ = false;     // product form: k_ypass_full for every image
     size_t g_yf_lds_ = 0;
-    int bmode_ = 0, tuned_mode_ = 0;
+    int bmode_ = 0, tuned_mode_ = 0, tuned_tile_ = 32;
     GemmProblem* g1_[2] = {};
     GemmProblem* g2_[2] = {};
     int n1_[2] = {}, n2_[2] = {};
@@ -3159,6 +3246,8 @@ int tvdeblur_batch_solve(tvdeblur_batch_t b, const void* const* v_dev_host, void
         return bfail(b, TVD_EINVAL, "batched solves take TVD_PREC_X, TVD_PREC_D_X or TVD_PREC_X_D");
     if (p->transform != TVD_TRANSFORM_AUTO && p->transform != TVD_TRANSFORM_FFT && p->transform != TVD_TRANSFORM_GEMM)
         return bfail(b, TVD_EINVAL, "bad transform");
+    if (p->gemm_tile != 0 && p->gemm_tile != 32 && p->gemm_tile != 64)
+        return bfail(b, TVD_EINVAL, "gemm_tile must be 0, 32 or 64");
     if (p->replay_host)
         for (size_t k = 0; k < size_t(b->count) * p->max_outer; ++k)
             if (p->replay_host[k] < 0 || p->replay_host[k] > 100000)
@@ -3348,6 +3437,26 @@ int tvdeblur_get_transform(tvdeblur_t h, int* active) {
         int rc = ensure_built(h);
         if (rc) return rc;
         *active = h->solver->transform();
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_set_gemm_tile(tvdeblur_t h, int tile) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (tile != 0 && tile != 32 && tile != 64) return fail(h, TVD_EINVAL, "tile must be 0, 32 or 64");
+    return guarded(h, [&]() {
+        h->solver->set_gemm_tile(tile);
+        return TVD_OK;
+    });
+}
+
+int tvdeblur_get_gemm_tile(tvdeblur_t h, int* tile) {
+    if (!h) return fail(nullptr, TVD_EINVAL, "NULL handle");
+    if (!tile) return fail(h, TVD_EINVAL, "tile is NULL");
+    return guarded(h, [&]() {
+        int rc = ensure_built(h);
+        if (rc) return rc;
+        *tile = h->solver->gemm_tile();
         return TVD_OK;
     });
 }

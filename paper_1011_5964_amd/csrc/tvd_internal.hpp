@@ -123,6 +123,11 @@ struct RowPassArgs {
     T* wout;                // nullptr: no x-pass
     const T* xband;
     int kw, klo, khi, xband_len;
+    // 1: the transform is T_n of the anti-reflective algebra instead of S^
+    // (DST-I plans only): mode 0 applies T_n^{-1} (the interior minus the
+    // linear interpolant of the two end values, then S^), mode 1 applies
+    // T_n (S^, then the interior plus that interpolant)
+    int ramp;
 };
 
 // Column half of the fused normal operator for the PCG direction update:
@@ -224,6 +229,8 @@ struct MGemmArgs {
     int n_rr;
     int iter;
     PcgState* st;           // nullptr: plain product
+    int tile;               // block tile: 32 (four waves split K of one 32 x 32
+                            // tile) or 64 (64 x 64, one 32 x 32 quadrant per wave)
 };
 
 // PCG update of the product-form preconditioner path: x += a p, r -= a q
@@ -274,6 +281,7 @@ struct ColPassArgs {
     int n_rr;
     PcgState* st;
     int iter;
+    int ramp;               // 1: T_n^{-1}, then T_n along the columns (see RowPassArgs)
 };
 
 // FP64 GEMM problem C = sum_t coef_t op(A_t) B_t (row-major).

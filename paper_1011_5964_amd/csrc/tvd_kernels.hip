@@ -712,6 +712,21 @@ __device__ __forceinline__ void rowpass_body(const RowPassArgs<T>& a, int bx) {
             xb[c] = (in && vb) ? a.r[gb + t] : T(0);
         }
     }
+    // T_n: the two end values of each line (mode 0: of s o r), whose linear
+    // interpolant the interior loses before S^ (mode 0) or gains after it
+    T e0a = T(0), e1a = T(0), e0b = T(0), e1b = T(0);
+    if (a.ramp) {
+        const bool sm0 = a.mode == 0 && a.s;
+        if (va) {
+            e0a = src[ga] * (sm0 ? a.s[ga] : T(1));
+            e1a = src[ga + nx - 1] * (sm0 ? a.s[ga + nx - 1] : T(1));
+        }
+        if (vb) {
+            e0b = src[gb] * (sm0 ? a.s[gb] : T(1));
+            e1b = src[gb + nx - 1] * (sm0 ? a.s[gb + nx - 1] : T(1));
+        }
+    }
+    const T inv_span = T(1) / T(nx - 1);
     lds_copy_wait();
     if (done) return;
     const AxisPlan<T> P = lds_plan<T, kTabLds>(a.plan, tab);
@@ -755,6 +770,10 @@ __device__ __forceinline__ void rowpass_body(const RowPassArgs<T>& a, int bx) {
             if (passthrough(t, P)) {
                 if (va) a.dst[ga + t] = va_;
                 if (vb) a.dst[gb + t] = vb_;
+            } else if (a.ramp) {
+                const T f = T(t) * inv_span;
+                va_ -= (T(1) - f) * e0a + f * e1a;
+                vb_ -= (T(1) - f) * e0b + f * e1b;
             }
             put_forward(b0, t, cx<T>{va_, vb_}, P);
         }
@@ -803,7 +822,12 @@ __device__ __forceinline__ void rowpass_body(const RowPassArgs<T>& a, int bx) {
             if (t >= nx) continue;
             T za = zpa[c], zb = zpb[c];
             if (!passthrough(t, P)) {
-                const cx<T> o = get_inverse(res, t, P);
+                cx<T> o = get_inverse(res, t, P);
+                if (a.ramp) {
+                    const T f = T(t) * inv_span;
+                    o.x += (T(1) - f) * e0a + f * e1a;
+                    o.y += (T(1) - f) * e0b + f * e1b;
+                }
                 za = sa[c] * o.x;
                 zb = sb[c] * o.y;
                 if (va) {
@@ -957,6 +981,24 @@ __device__ __forceinline__ void colpass_body(const ColPassArgs<T>& a, int bx) {
         ma[c] = (in && va) ? a.muinv[g + ja] : T(0);
         mb[c] = (in && vb) ? a.muinv[g + jb] : T(0);
     }
+    // T_n along the columns: end values and their scaled coefficients
+    T x0a = T(0), x1a = T(0), x0b = T(0), x1b = T(0), c0a = T(0), c1a = T(0), c0b = T(0), c1b = T(0);
+    if (a.ramp) {
+        const size_t gl = size_t(ny - 1) * nx;
+        if (va) {
+            x0a = a.src[ja];
+            x1a = a.src[gl + ja];
+            c0a = x0a * a.muinv[ja];
+            c1a = x1a * a.muinv[gl + ja];
+        }
+        if (vb) {
+            x0b = a.src[jb];
+            x1b = a.src[gl + jb];
+            c0b = x0b * a.muinv[jb];
+            c1b = x1b * a.muinv[gl + jb];
+        }
+    }
+    const T inv_span = T(1) / T(ny - 1);
     lds_copy_wait();
     if (done) return;
     if (a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && tid == 0, red)) return;
@@ -968,6 +1010,10 @@ __device__ __forceinline__ void colpass_body(const ColPassArgs<T>& a, int bx) {
         if (passthrough(t, P)) {
             if (va) a.dst[size_t(t) * nx + ja] = xa[c] * ma[c];
             if (vb) a.dst[size_t(t) * nx + jb] = xb[c] * mb[c];
+        } else if (a.ramp) {
+            const T f = T(t) * inv_span;
+            xa[c] -= (T(1) - f) * x0a + f * x1a;
+            xb[c] -= (T(1) - f) * x0b + f * x1b;
         }
         put_forward(b0, t, cx<T>{xa[c], xb[c]}, P);
     }
@@ -994,7 +1040,12 @@ __device__ __forceinline__ void colpass_body(const ColPassArgs<T>& a, int bx) {
     for (int c = 0; c < kLinePos; ++c) {
         const int t = lt + c * tpu;
         if (t >= ny || passthrough(t, P)) continue;
-        const cx<T> o = get_inverse(res2, t, P);
+        cx<T> o = get_inverse(res2, t, P);
+        if (a.ramp) {
+            const T f = T(t) * inv_span;
+            o.x += (T(1) - f) * c0a + f * c1a;
+            o.y += (T(1) - f) * c0b + f * c1b;
+        }
         if (va) a.dst[size_t(t) * nx + ja] = o.x;
         if (vb) a.dst[size_t(t) * nx + jb] = o.y;
     }
@@ -1401,18 +1452,22 @@ struct NtCfg<double> {
 };
 constexpr int kNtR = 2;  // rounds per stage
 
-// The stage loop runs branch-free when each wave's quarter of K is a whole
-// number of stages.
+// The stage loop runs branch-free when each wave's share of K (a quarter
+// with 32 x 32 tiles, all of it with 64 x 64 tiles) is a whole number of
+// stages.
 template <typename T>
-__host__ __device__ constexpr bool mgemm_fast_k(int K) {
-    return K % (4 * kNtR * 4 * NtCfg<T>::VEC) == 0;
+__host__ __device__ constexpr bool mgemm_fast_k(int K, int tile = 32) {
+    return K % ((tile == 64 ? 1 : 4) * kNtR * 4 * NtCfg<T>::VEC) == 0;
 }
 
 // kFast: each wave's K range is a whole number of stages, so the stage-pair
 // loop has no branches (its last prefetch re-reads the final stage) and the
 // compiler can count the loads in flight exactly; otherwise a general loop
 // with masked tails.
-template <typename T, bool kFast>
+// kSplit = false: the block tile is 64 x 64 and wave w owns its 32 x 32
+// quadrant (w / 2, w % 2) over the whole of K (no LDS reduction; every
+// operand row is read by two waves of the block).
+template <typename T, bool kFast, bool kSplit = true>
 __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
     using Cfg = MfmaCfg<T>;
     using acc_t = typename Cfg::acc_t;
@@ -1434,7 +1489,8 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         if (done) return true;
         return a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red);
     };
-    const int m0 = by * 32, n0 = bx * 32;
+    const int m0 = kSplit ? by * 32 : by * 64 + (wave >> 1) * 32;
+    const int n0 = kSplit ? bx * 32 : bx * 64 + (wave & 1) * 32;
     const int g = lane >> 4, idx = lane & 15;
     // rows outside the matrix feed only rows / columns of C that are not
     // stored: their addresses are clamped to row 0
@@ -1444,7 +1500,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     const gmem_t<T>* pb1 = gmem(a.Bt) + size_t(n0 + 16 + idx < N ? n0 + 16 + idx : 0) * K;
     using gvec_t = const gmem_t<vec_t>;
     const int kq = ((K + 4 * STEP - 1) / (4 * STEP)) * STEP;  // this wave's share of K
-    const int kbeg = wave * kq, kend = min(K, kbeg + kq);
+    const int kbeg = kSplit ? wave * kq : 0, kend = kSplit ? min(K, kbeg + kq) : K;
     const int kg = VEC * g;
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
     vec_t fa0[2][kNtR], fa1[2][kNtR], fb0[2][kNtR], fb1[2][kNtR];
@@ -1454,7 +1510,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     const int ti = wave >> 1, tj = wave & 1;
     const int jc = n0 + 16 * tj + idx;
     T e1v[4], e2v[4];
-    {
+    if constexpr (kSplit) {
         const bool has1 = a.epi >= 1 && a.E1, has2 = a.epi == 2;
         const gmem_t<T>* ones = gmem(nt_ones<T>());
         const gmem_t<T>* zeros = gmem(reinterpret_cast<const T*>(g_nt_zeros));
@@ -1546,6 +1602,34 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
             compute_stage(0);
         }
     }
+    if constexpr (!kSplit) {
+        // each wave stores its own quadrant (four 16 x 16 MFMA tiles)
+        const bool has1 = a.epi >= 1 && a.E1;
+        double part = 0.0;
+        auto put = [&](const acc_t& c, int ri, int cj) {
+            const int j = n0 + 16 * cj + idx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = m0 + 16 * ri + Cfg::orow(lane, q);
+                if (i < M && j < N) {
+                    const size_t gidx = size_t(i) * N + j;
+                    const T v = has1 ? c[q] * gmem(a.E1)[gidx] : c[q];
+                    if (a.transC) gmem(a.C)[size_t(j) * M + i] = v;
+                    else gmem(a.C)[gidx] = v;
+                    if (a.epi == 2) part += double(gmem(a.E2)[gidx]) * double(v);
+                }
+            }
+        };
+        put(c00, 0, 0);
+        put(c01, 0, 1);
+        put(c10, 1, 0);
+        put(c11, 1, 1);
+        if (a.epi == 2) {
+            const double sm = block_sum(part, red);
+            if (tid == 0) gmem(a.part)[by * gx + bx] = sm;
+        }
+        return;
+    }
     // sum the four waves' partial tiles: wave w finishes tile (w / 2, w % 2)
     {
         T* mine = red_tile + wave * 16 * 64;
@@ -1579,11 +1663,11 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     }
 }
 
-template <typename T, bool kFast>
+template <typename T, bool kFast, bool kSplit>
 __global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
     int bx, by;
     tile_of_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, bx, by);
-    mgemm_body<T, kFast>(a, bx, by, gridDim.x);
+    mgemm_body<T, kFast, kSplit>(a, bx, by, gridDim.x);
 }
 
 // Batched product: image blockIdx.z, its own tile grid inside the launch
@@ -1591,13 +1675,19 @@ __global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_mgemm_b(const MGemmArgs<T>* __restrict__ as, int it) {
     MGemmArgs<T> a = as[blockIdx.z];
-    const int gx = (a.N + 31) / 32, gy = (a.M + 31) / 32;
+    const int ts = a.tile == 64 ? 64 : 32;
+    const int gx = (a.N + ts - 1) / ts, gy = (a.M + ts - 1) / ts;
     const int b = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int bx = b % gridDim.x, by = b / gridDim.x;
     if (bx >= gx || by >= gy || (a.st && a.st->done)) return;
     a.iter = it;
-    if (mgemm_fast_k<T>(a.K)) mgemm_body<T, true>(a, bx, by, gx);
-    else mgemm_body<T, false>(a, bx, by, gx);
+    if (ts == 64) {
+        if (mgemm_fast_k<T>(a.K, 64)) mgemm_body<T, true, false>(a, bx, by, gx);
+        else mgemm_body<T, false, false>(a, bx, by, gx);
+    } else {
+        if (mgemm_fast_k<T>(a.K)) mgemm_body<T, true>(a, bx, by, gx);
+        else mgemm_body<T, false>(a, bx, by, gx);
+    }
 }
 
 // FP64 sums of products C = sum_t coef_t op(A_t) B_t on the matrix cores
@@ -2358,10 +2448,17 @@ bool mgemm_supported() {
 
 template <typename T>
 hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
-    dim3 grid((a.N + 31) / 32, (a.M + 31) / 32);
+    const int ts = a.tile == 64 ? 64 : 32;
+    dim3 grid((a.N + ts - 1) / ts, (a.M + ts - 1) / ts);
     if (nblocks) *nblocks = int(grid.x * grid.y);
-    if (mgemm_fast_k<T>(a.K)) tvd_launch(k_mgemm<T, true>, grid, dim3(256), 0, s, a);
-    else tvd_launch(k_mgemm<T, false>, grid, dim3(256), 0, s, a);
+    const bool fast = mgemm_fast_k<T>(a.K, ts);
+    if (ts == 64) {
+        if (fast) tvd_launch(k_mgemm<T, true, false>, grid, dim3(256), 0, s, a);
+        else tvd_launch(k_mgemm<T, false, false>, grid, dim3(256), 0, s, a);
+    } else {
+        if (fast) tvd_launch(k_mgemm<T, true, true>, grid, dim3(256), 0, s, a);
+        else tvd_launch(k_mgemm<T, false, true>, grid, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

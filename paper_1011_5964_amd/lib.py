@@ -40,7 +40,8 @@ EXPORTED_SYMBOLS = (
     "tvdeblur_solve_reblur", "tvdeblur_op_reblur_setup", "tvdeblur_op_reblur_normal",
     "tvdeblur_op_reblur_precond", "tvdeblur_solve_noalloc", "tvdeblur_signals_create", "tvdeblur_signals_solve",
     "tvdeblur_signals_destroy", "tvdeblur_signals_last_error", "tvdeblur_set_reblur_l_bc",
-    "tvdeblur_workspace_bytes", "tvdeblur_set_workspace",
+    "tvdeblur_workspace_bytes", "tvdeblur_set_workspace", "tvdeblur_get_gemm_tile",
+    "tvdeblur_set_gemm_tile",
 )
 BATCH_PRECOND = ("x", "d_x", "x_d")
 
@@ -56,7 +57,7 @@ class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("fp_tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_inner", ctypes.c_int),
                 ("precond", ctypes.c_int), ("u0_dev", ctypes.c_void_p), ("replay_host", ctypes.POINTER(ctypes.c_int)),
-                ("iterates_dev", ctypes.c_void_p), ("record_objective", ctypes.c_int)]
+                ("iterates_dev", ctypes.c_void_p), ("record_objective", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -92,7 +93,7 @@ class BatchParams(ctypes.Structure):
                 ("beta", ctypes.c_double), ("max_outer", ctypes.c_int), ("fp_tol", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("max_inner", ctypes.c_int), ("precond", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("replay_host", ctypes.POINTER(ctypes.c_int)),
-                ("transform", ctypes.c_int)]
+                ("transform", ctypes.c_int), ("gemm_tile", ctypes.c_int)]
 
 
 TUNE_MAX = 4
@@ -104,7 +105,7 @@ class BatchInfo(ctypes.Structure):
                 ("cand_threads", ctypes.c_int * TUNE_MAX), ("cand_us", ctypes.c_double * TUNE_MAX),
                 ("gemm_us", ctypes.c_double), ("transform", ctypes.c_int),
                 ("graph_launches", ctypes.c_longlong), ("time_setup_s", ctypes.c_double),
-                ("time_inner_s", ctypes.c_double)]
+                ("time_inner_s", ctypes.c_double), ("gemm64_us", ctypes.c_double), ("gemm_tile", ctypes.c_int)]
 
 
 class SignalDesc(ctypes.Structure):
@@ -167,6 +168,8 @@ def load():
         "tvdeblur_set_reblur_l_bc": [vp, i],
         "tvdeblur_workspace_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "tvdeblur_set_workspace": [vp, vp, ctypes.c_size_t],
+        "tvdeblur_get_gemm_tile": [vp, ctypes.POINTER(i)],
+        "tvdeblur_set_gemm_tile": [vp, i],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -234,9 +237,10 @@ class TVDeblur:
         self._check(self.lib.tvdeblur_set_bc(self.h, BC[bc]))
 
     def _params(self, alpha, beta, max_outer, inner_tol, max_inner, precond_code, fp_tol, u0, replay, iterates,
-                objective=False):
+                objective=False, use_graph=False):
         p = Params()
         p.record_objective = 1 if objective else 0
+        p.use_graph = 1 if use_graph else 0
         p.alpha, p.beta, p.max_outer = float(alpha), float(beta), int(max_outer)
         p.fp_tol, p.inner_tol, p.max_inner = float(fp_tol), float(inner_tol), int(max_inner)
         p.precond = precond_code
@@ -257,13 +261,14 @@ class TVDeblur:
         return p, keep
 
     def solve(self, v, alpha, beta, max_outer, inner_tol=1e-6, max_inner=100, precond="x_d", fp_tol=0.0,
-              u0=None, replay=None, iterates=None, out=None, objective=False):
-        """objective: also return T(u^0..u^K) of eq. (mp) in stats['tv_objective']."""
+              u0=None, replay=None, iterates=None, out=None, objective=False, use_graph=False):
+        """objective: also return T(u^0..u^K) of eq. (mp) in stats['tv_objective'].
+        use_graph: replay the PCG iterations from HIP graphs (same bits)."""
         import torch
         self._img(v, "v")
         u = self._img(out, "out") if out is not None else torch.empty_like(v)
         p, keep = self._params(alpha, beta, max_outer, inner_tol, max_inner, PRECOND[precond], fp_tol, u0,
-                               replay, iterates, objective)
+                               replay, iterates, objective, use_graph)
         st = Stats()
         with torch.cuda.device(self.device):
             rc = self.lib.tvdeblur_solve(self.h, _ptr(v), _ptr(u), ctypes.byref(p), ctypes.byref(st))
@@ -365,6 +370,16 @@ class TVDeblur:
         v = ctypes.c_int()
         self._check(self.lib.tvdeblur_get_transform(self.h, ctypes.byref(v)))
         return {1: "fft", 2: "gemm"}[v.value]
+
+    def set_gemm_tile(self, tile):
+        """Block tile of the products: 0 (timed at build), 32 or 64."""
+        self._check(self.lib.tvdeblur_set_gemm_tile(self.h, int(tile)))
+
+    def gemm_tile(self):
+        """Block tile of the matrix-core products (32 or 64), timed at build."""
+        v = ctypes.c_int()
+        self._check(self.lib.tvdeblur_get_gemm_tile(self.h, ctypes.byref(v)))
+        return v.value
 
     def set_profiling(self, every):
         """every: time every every-th launch of each kernel class (True = 1);
@@ -486,10 +501,11 @@ class TVDeblurBatch:
             pass
 
     def solve(self, vs, alphas, beta=0.05, betas=None, max_outer=10, inner_tol=1e-6, max_inner=100,
-              precond="x_d", fp_tol=0.0, use_graph=True, outs=None, replay=None, transform="auto"):
+              precond="x_d", fp_tol=0.0, use_graph=True, outs=None, replay=None, transform="auto", gemm_tile=0):
         """Returns (list of restored images, list of per-image stats dicts).
         replay: None, or per image a list of max_outer PCG iteration counts.
-        transform: 'auto' (the implementation picked at create), 'fft' or 'gemm'."""
+        transform: 'auto' (the implementation picked at create), 'fft' or 'gemm'.
+        gemm_tile: block tile of the products, 0 (picked at create), 32 or 64."""
         import torch
         if len(vs) != self.count or len(alphas) != self.count:
             raise ValueError("one v and one alpha per image")
@@ -519,6 +535,7 @@ class TVDeblurBatch:
         p.inner_tol, p.max_inner, p.precond = float(inner_tol), int(max_inner), PRECOND[precond]
         p.use_graph = 1 if use_graph else 0
         p.transform = TRANSFORM[transform]
+        p.gemm_tile = int(gemm_tile)
         rkeep = None
         if replay is not None:
             # count x max_outer counts, image-major, read in full by the library;
@@ -540,7 +557,8 @@ class TVDeblurBatch:
         n = bi.n_candidates
         return {"count": bi.count, "line_threads": bi.line_threads, "tables_in_lds": bool(bi.tables_in_lds),
                 "from_cache": bool(bi.from_cache), "candidates": list(bi.cand_threads[:n]),
-                "candidate_us": list(bi.cand_us[:n]), "gemm_us": bi.gemm_us,
+                "candidate_us": list(bi.cand_us[:n]), "gemm_us": bi.gemm_us, "gemm64_us": bi.gemm64_us,
+                "gemm_tile": bi.gemm_tile,
                 "transform": {1: "fft", 2: "gemm"}.get(bi.transform, "none"),
                 "graph_launches": int(bi.graph_launches),
                 "time_setup_s": bi.time_setup_s, "time_inner_s": bi.time_inner_s}

@@ -57,13 +57,23 @@ def ragged_problems(bc, n_outer=3):
     return out
 
 
+def split_form(transform):
+    """'gemm32' / 'gemm64': the product form with that block tile."""
+    if transform.startswith("gemm") and transform != "gemm":
+        return "gemm", int(transform[4:])
+    return transform, 0
+
+
 def batch_solve(probs, prec, variant="x_d", replay=None, use_graph=True, fp_tol=0.0, batch=None, transform="auto"):
     from paper_1011_5964_amd.lib import TVDeblurBatch
     b = batch or TVDeblurBatch([p.v.shape for p in probs], [p.psf for p in probs], probs[0].bc, prec)
     vs = [dev(p.v, prec) for p in probs]
+    form, tile = split_form(transform)
     us, st = b.solve(vs, [p.alpha for p in probs], betas=[p.beta for p in probs], max_outer=probs[0].n_outer,
                      inner_tol=probs[0].inner_tol, max_inner=probs[0].max_inner, precond=variant,
-                     fp_tol=fp_tol, use_graph=use_graph, replay=replay, transform=transform)
+                     fp_tol=fp_tol, use_graph=use_graph, replay=replay, transform=form, gemm_tile=tile)
+    if tile:
+        assert b.info()["gemm_tile"] == tile
     return [host(u) for u in us], st, b
 
 
@@ -82,7 +92,7 @@ def check_batch(probs, prec, variant="x_d", use_graph=True, transform="auto"):
     ref = oracle_solves(probs, prec, variant)
     ug, sg, b = batch_solve(probs, prec, variant, use_graph=use_graph, transform=transform)
     if transform != "auto":
-        assert b.info()["transform"] == transform
+        assert b.info()["transform"] == split_form(transform)[0]
     errs = [rel2(u, uo) for u, (uo, _) in zip(ug, ref)]
     same = [s["inner_iters"] == so["inner_iters"] for s, (_, so) in zip(sg, ref)]
     for k, (e, s, (_, so)) in enumerate(zip(errs, sg, ref)):
@@ -107,7 +117,7 @@ def check_batch(probs, prec, variant="x_d", use_graph=True, transform="auto"):
     return errs, sg, b
 
 
-@pytest.mark.parametrize("transform", ["fft", "gemm"])
+@pytest.mark.parametrize("transform", ["fft", "gemm32", "gemm64"])
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
 @pytest.mark.parametrize("bc", [AR, R])
 def test_ragged_batch_matches_oracle(bc, prec, transform):
@@ -127,7 +137,7 @@ def test_batch_other_transform_variants(variant, transform):
     check_batch(ragged_problems(AR), "f64", variant, transform=transform)
 
 
-@pytest.mark.parametrize("transform", ["fft", "gemm"])
+@pytest.mark.parametrize("transform", ["fft", "gemm32", "gemm64"])
 def test_graph_replay_equals_stream_launches(transform):
     """The graph-captured PCG loop and plain stream launches run the same
     kernels in the same order: bitwise-identical results and counts."""

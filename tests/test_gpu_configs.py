@@ -170,7 +170,8 @@ def test_c5_central_differences_fp64():
 def test_c4_every_image():
     """The 64-image uneven batch (sides 128..512, own Gaussian PSF of size
     9..21 and sigma U[1,4], alpha log-uniform in [1e-4, 1e-2], beta 0.05, AR,
-    X_D, 10 steps), FP32-mixed with graph replay as the benchmark runs it:
+    X_D, 10 steps), FP32-mixed with the launches issued one by one, as the
+    benchmark runs it:
     every image within 1e-5 of the oracle's solve of that image alone."""
     from paper_1011_5964_amd.lib import TVDeblurBatch
     fx = fixture("c4_f32")
@@ -179,7 +180,8 @@ def test_c4_every_image():
     b = TVDeblurBatch([p.v.shape for p in probs], [p.psf for p in probs], "antireflective", "f32_mixed")
     vs = [dev(p.v, "f32_mixed") for p in probs]
     alphas = [p.alpha for p in probs]
-    us, sts = b.solve(vs, alphas, beta=0.05, max_outer=10, inner_tol=1e-6, max_inner=100, precond="x_d")
+    us, sts = b.solve(vs, alphas, beta=0.05, max_outer=10, inner_tol=1e-6, max_inner=100, precond="x_d",
+                      use_graph=False)
     print(f"c4: {len(probs)} images, transform {b.info()['transform']}", flush=True)
     free = [rel2(host(u), fx[f"u_{i:02d}"].astype(np.float64)) for i, u in enumerate(us)]
     same = [sts[i]["inner_iters"] == counts[i] for i in range(len(probs))]
@@ -192,7 +194,7 @@ def test_c4_every_image():
     assert {384, 512} <= sides
     if not all(same):
         ur, sr = b.solve(vs, alphas, beta=0.05, max_outer=10, inner_tol=1e-6, max_inner=100, precond="x_d",
-                         replay=counts)
+                         replay=counts, use_graph=False)
         rep = [rel2(host(u), fx[f"u_{i:02d}"].astype(np.float64)) for i, u in enumerate(ur)]
         print(f"c4 replayed oracle counts: max rel err {max(rep):.2e}", flush=True)
         assert all(sr[i]["inner_iters"] == counts[i] for i in range(len(probs)))

@@ -60,11 +60,17 @@ def rel2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def make(shape, psf, prec, bc=AR):
+def make(shape, psf, prec, bc=AR, transform="auto"):
+    """transform 'fft': the T_n solves as line transforms (S^ passes with the
+    end-value interpolant removed and restored); 'gemm': as products with
+    T_n^{-1} and T_n; 'auto': the handle's timed choice."""
     from paper_1011_5964_amd.lib import TVDeblur
     h = TVDeblur(shape[0], shape[1], prec)
     h.set_psf(psf)
     h.set_bc(bc)
+    h.set_transform(transform)
+    if transform != "auto":
+        assert h.transform() == transform
     return h
 
 
@@ -72,17 +78,18 @@ CASES = [((64, 64), synth.gaussian_psf(9, 1.5)), ((37, 50), synth.gaussian_psf(5
          ((130, 70), synth.gaussian_psf(7, 1.2))]
 
 
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
 @pytest.mark.parametrize("variant", RB.REBLUR_VARIANTS)
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_reblur_setup_operator_and_precond(case, variant, prec):
+def test_reblur_setup_operator_and_precond(case, variant, prec, transform):
     shape, psf = CASES[case]
-    print(f"case reblur ops {shape} {variant} {prec}", flush=True)
+    print(f"case reblur ops {shape} {variant} {prec} {transform}", flush=True)
     rng = np.random.default_rng(17 + case)
     p = synth.small_problem(n=max(shape), psf_size=5, sigma=1.0)
     uk = p.v[:shape[0], :shape[1]] + 0.01 * rng.standard_normal(shape)
     alpha, beta = 3e-3, 0.07
-    h = make(shape, psf, prec)
+    h = make(shape, psf, prec, transform=transform)
     h.reblur_setup(dev(uk, prec), alpha, beta, variant)
     ukq = host(dev(uk, prec))
     kap = O.kappa(ukq, beta)
@@ -115,16 +122,17 @@ def test_reblur_plain_preconditioners(variant, prec):
     assert relerr(host(h.reblur_normal(dev(r, prec))), RB.reblur_apply(r, psf, kap, 3e-3)) < TOL_OP[prec]
 
 
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
 @pytest.mark.parametrize("variant", RB.REBLUR_ALL_VARIANTS)
-def test_reblur_solve_replayed_counts(variant, prec):
+def test_reblur_solve_replayed_counts(variant, prec, transform):
     """Whole fixed-point solve with the oracle's per-step BiCGstab counts
     replayed: the restored image agrees with the oracle's."""
-    print(f"case reblur solve {variant} {prec}", flush=True)
+    print(f"case reblur solve {variant} {prec} {transform}", flush=True)
     p = synth.small_problem(n=48, psf_size=7, sigma=1.2, n_outer=4, ny=40)
     uo, so = RB.fp_solve_reblur(p.v, p.psf, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant)
     vq = host(dev(p.v, prec))
-    h = make(p.v.shape, p.psf, prec)
+    h = make(p.v.shape, p.psf, prec, transform=transform)
     u, st = h.solve_reblur(dev(p.v, prec), p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant,
                            replay=so["inner_iters"])
     assert st["inner_iters"][:p.n_outer] == so["inner_iters"]
@@ -189,16 +197,17 @@ def test_reblur_rejects_what_it_does_not_cover():
         h3.reblur_normal(v)          # before reblur_setup
 
 
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
-def test_reblur_full_size(prec):
+def test_reblur_full_size(prec, transform):
     """The 512 x 512 workload (21 x 21 Gaussian sigma 3, alpha 5e-4, beta
     0.05): operators and preconditioner element by element, then the first
     fixed-point step with the oracle's count replayed."""
-    print(f"case reblur full size {prec}", flush=True)
+    print(f"case reblur full size {prec} {transform}", flush=True)
     p = synth.config("m512")
     n = p.v.shape[0]
     rng = np.random.default_rng(512)
-    h = make((n, n), p.psf, prec)
+    h = make((n, n), p.psf, prec, transform=transform)
     vq = host(dev(p.v, prec))
     h.reblur_setup(dev(vq, prec), p.alpha, p.beta, "p_d")
     kap = O.kappa(vq, p.beta)
@@ -213,18 +222,19 @@ def test_reblur_full_size(prec):
     assert rel2(host(u), uo) < TOL_SOLVE[prec]
 
 
+@pytest.mark.parametrize("transform", ["fft", "gemm"])
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
 @pytest.mark.parametrize("shape", [(3, 5), (4, 4), (5, 3), (6, 17)])
-def test_reblur_smallest_images(shape, prec):
+def test_reblur_smallest_images(shape, prec, transform):
     """The smallest images a handle takes (n >= 3; one interior frequency when
     n = 3), 3 x 3 PSF: replayed solve against the oracle."""
-    print(f"case reblur small {shape} {prec}", flush=True)
+    print(f"case reblur small {shape} {prec} {transform}", flush=True)
     rng = np.random.default_rng(sum(shape))
     psf = synth.gaussian_psf(3, 0.8)
     v = O.blur(rng.random(shape), psf, AR) + 0.01 * rng.standard_normal(shape)
     vq = host(dev(v, prec))
     uo, so = RB.fp_solve_reblur(vq, psf, 1e-2, 0.1, 3, 1e-6, 50, "p_d")
-    h = make(shape, psf, prec)
+    h = make(shape, psf, prec, transform=transform)
     u, st = h.solve_reblur(dev(vq, prec), 1e-2, 0.1, 3, 1e-6, 50, "p_d", replay=so["inner_iters"])
     assert st["inner_iters"][:3] == so["inner_iters"]
     assert rel2(host(u), uo) < TOL_SOLVE[prec]

@@ -327,11 +327,11 @@ def test_fp_tol_stops_where_the_oracle_stops(prec):
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
 @pytest.mark.parametrize("transform", ["fft", "gemm"])
 def test_graph_replay_equals_stream_launches(prec, transform):
-    """Single-image PCG iterations replayed from HIP graphs give the same
-    bits as the same launches issued one by one on the stream (the path taken
-    while kernel profiling is on), on every fixed-point step, and again when
-    the cached graphs are replayed by later solves and after the parameters
-    change."""
+    """Single-image PCG iterations replayed from HIP graphs (use_graph) give
+    the same bits as the same launches issued one by one on the stream (the
+    default, and the path taken while kernel profiling is on), on every
+    fixed-point step, and again when the cached graphs are replayed by later
+    solves and after the parameters change."""
     from paper_1011_5964_amd.lib import TVDeblur
     p = synth.config("c1")
     h = TVDeblur(64, 64, prec)
@@ -342,13 +342,14 @@ def test_graph_replay_equals_stream_launches(prec, transform):
     runs = []
     for alpha in (p.alpha, 3 * p.alpha, p.alpha):
         h.set_profiling(1)
-        us, ss = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        up, sp = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d", use_graph=True)
         h.set_profiling(0)
-        ug, sg = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
-        ug2, sg2 = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        us, ss = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d")
+        ug, sg = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d", use_graph=True)
+        ug2, sg2 = h.solve(v, alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, "x_d", use_graph=True)
         print(f"alpha {alpha:.1e}: iters {sg['inner_iters']}", flush=True)
-        assert ss["inner_iters"] == sg["inner_iters"] == sg2["inner_iters"]
-        assert torch.equal(us, ug) and torch.equal(ug, ug2)
+        assert sp["inner_iters"] == ss["inner_iters"] == sg["inner_iters"] == sg2["inner_iters"]
+        assert torch.equal(up, us) and torch.equal(us, ug) and torch.equal(ug, ug2)
         runs.append(ug)
     assert torch.equal(runs[0], runs[2])
 
@@ -403,8 +404,8 @@ def test_caller_workspace(prec):
     assert elems <= nbytes <= elems + 64 * 1024 * 1024
     ws = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
     h.set_workspace(ws)
-    for _ in range(2):
-        u, st = h.solve(v, *args)
+    for graph in (False, True, True):
+        u, st = h.solve(v, *args, use_graph=graph)
         assert torch.equal(u, u_own) and st["inner_iters"] == st_own["inner_iters"]
     assert int(ws.count_nonzero()) > 0  # the solve ran in the caller's area
     h.set_workspace(None)

@@ -42,19 +42,30 @@ def rel2(a, b):
 
 
 def handle(shape, psf, bc, prec, transform):
+    """transform: 'fft', 'auto', 'gemm' (timed tile), or 'gemm32' / 'gemm64'
+    (products with that block tile)."""
     from paper_1011_5964_amd.lib import TVDeblur
     h = TVDeblur(shape[0], shape[1], prec)
     h.set_psf(psf)
     h.set_bc(bc)
-    h.set_transform(transform)
+    if transform.startswith("gemm") and transform != "gemm":
+        h.set_gemm_tile(int(transform[4:]))
+        h.set_transform("gemm")
+        assert h.gemm_tile() == int(transform[4:])
+    else:
+        h.set_transform(transform)
     return h
 
 
+def form(transform):
+    return "gemm" if transform.startswith("gemm") else transform
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
-@pytest.mark.parametrize("transform", ["fft", "gemm"])
+@pytest.mark.parametrize("transform", ["fft", "gemm32", "gemm64"])
 @pytest.mark.parametrize("bc", [AR, R])
 @pytest.mark.parametrize("variant", ["x", "d_x", "x_d"])
-@pytest.mark.parametrize("shape", [(64, 64), (37, 50), (130, 70), (33, 300)])
+@pytest.mark.parametrize("shape", [(64, 64), (37, 50), (130, 70), (33, 300), (200, 136)])
 def test_precond_forms_match_oracle(shape, variant, bc, transform, prec):
     """z = P^{-1} r for both transform implementations on square, ragged and
     elongated images (several 32 x 32 product tiles plus tails in every
@@ -67,7 +78,7 @@ def test_precond_forms_match_oracle(shape, variant, bc, transform, prec):
     alpha, beta = 3e-3, 0.07
     h = handle(shape, psf, bc, prec, transform)
     h.setup(dev(uk, prec), alpha, beta, variant)
-    assert h.transform() == transform
+    assert h.transform() == form(transform)
     ukq = host(dev(uk, prec))
     ref = O.precond_setup(O.kappa(ukq, beta), alpha, O.psf_symbol_eigenvalues(psf, *shape, bc), bc, variant)
     r = rng.standard_normal(shape)
@@ -86,7 +97,7 @@ def restore_parity(p, transform, variant="x_d", prec="f32_mixed"):
     vq = host(dev(p.v, prec))
     uo, so = O.fp_solve(vq, p.psf, p.bc, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant)
     h = handle(p.v.shape, p.psf, p.bc, prec, transform)
-    assert h.transform() == transform
+    assert h.transform() == form(transform)
     v = dev(p.v, prec)
     u, st = h.solve(v, p.alpha, p.beta, p.n_outer, p.inner_tol, p.max_inner, variant)
     err = rel2(host(u), uo)
@@ -105,7 +116,7 @@ def restore_parity(p, transform, variant="x_d", prec="f32_mixed"):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
-@pytest.mark.parametrize("transform", ["fft", "gemm"])
+@pytest.mark.parametrize("transform", ["fft", "gemm32", "gemm64"])
 @pytest.mark.parametrize("variant", ["x", "d_x", "x_d"])
 @pytest.mark.parametrize("bc", [AR, R])
 def test_restoration_both_forms_small_ragged(bc, variant, transform, prec):
@@ -115,7 +126,7 @@ def test_restoration_both_forms_small_ragged(bc, variant, transform, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
-@pytest.mark.parametrize("transform", ["fft", "gemm"])
+@pytest.mark.parametrize("transform", ["fft", "gemm32", "gemm64"])
 def test_restoration_both_forms_c1(transform, prec):
     print(f"case c1 {transform} {prec}", flush=True)
     restore_parity(synth.config("c1"), transform, prec=prec)
@@ -124,9 +135,16 @@ def test_restoration_both_forms_c1(transform, prec):
 @pytest.mark.slow
 @pytest.mark.parametrize("prec", ["f64", "f32_mixed"])
 def test_restoration_product_form_512(prec):
-    """The 512^2 anti-reflective workload (15 steps) with the product form."""
+    """The 512^2 anti-reflective workload (15 steps) with the product form
+    and the tile the build-time timing picks."""
     print(f"case m512 gemm {prec}", flush=True)
     restore_parity(synth.config("m512"), "gemm", prec=prec)
+
+
+def test_restoration_product_form_512_tile64():
+    """The 512^2 workload with 64 x 64 product tiles forced (FP32-mixed)."""
+    print("case m512 gemm64 f32_mixed", flush=True)
+    restore_parity(synth.config("m512"), "gemm64", prec="f32_mixed")
 
 
 def separable_psf(py, px, sy, sx):
