@@ -488,8 +488,24 @@ __device__ __forceinline__ void stockham_stage(const cx<T>* x, cx<T>* y, int M, 
         else dft2(a[0], a[1]);
         const int base = q + s * R * p;
         y[pidx(base)] = a[0];
+        // w^k = exp(-2 pi i p k / n) for k = 1..R-1 from the one table entry
+        // w = tw[p s] (consecutive lanes read consecutive entries): products
+        // of w, w^2 and w^4, at most three roundings deep
+        const cx<T> w1 = tw[p * s];
+        cx<T> wk[R];
+        wk[1] = w1;
+        if constexpr (R >= 4) {
+            wk[2] = cmul(w1, w1);
+            wk[3] = cmul(wk[2], w1);
+        }
+        if constexpr (R == 8) {
+            wk[4] = cmul(wk[2], wk[2]);
+            wk[5] = cmul(wk[4], w1);
+            wk[6] = cmul(wk[4], wk[2]);
+            wk[7] = cmul(wk[4], wk[3]);
+        }
 #pragma unroll
-        for (int k = 1; k < R; ++k) y[pidx(base + s * k)] = cmul(a[k], tw[p * k * s]);
+        for (int k = 1; k < R; ++k) y[pidx(base + s * k)] = cmul(a[k], wk[k]);
     }
 }
 
@@ -1452,22 +1468,18 @@ struct NtCfg<double> {
 };
 constexpr int kNtR = 2;  // rounds per stage
 
-// The stage loop runs branch-free when each wave's share of K (a quarter
-// with 32 x 32 tiles, all of it with 64 x 64 tiles) is a whole number of
-// stages.
+// The stage loop runs branch-free when each wave's quarter of K is a whole
+// number of stages.
 template <typename T>
-__host__ __device__ constexpr bool mgemm_fast_k(int K, int tile = 32) {
-    return K % ((tile == 64 ? 1 : 4) * kNtR * 4 * NtCfg<T>::VEC) == 0;
+__host__ __device__ constexpr bool mgemm_fast_k(int K) {
+    return K % (4 * kNtR * 4 * NtCfg<T>::VEC) == 0;
 }
 
 // kFast: each wave's K range is a whole number of stages, so the stage-pair
 // loop has no branches (its last prefetch re-reads the final stage) and the
 // compiler can count the loads in flight exactly; otherwise a general loop
 // with masked tails.
-// kSplit = false: the block tile is 64 x 64 and wave w owns its 32 x 32
-// quadrant (w / 2, w % 2) over the whole of K (no LDS reduction; every
-// operand row is read by two waves of the block).
-template <typename T, bool kFast, bool kSplit = true>
+template <typename T, bool kFast>
 __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
     using Cfg = MfmaCfg<T>;
     using acc_t = typename Cfg::acc_t;
@@ -1489,8 +1501,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         if (done) return true;
         return a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red);
     };
-    const int m0 = kSplit ? by * 32 : by * 64 + (wave >> 1) * 32;
-    const int n0 = kSplit ? bx * 32 : bx * 64 + (wave & 1) * 32;
+    const int m0 = by * 32, n0 = bx * 32;
     const int g = lane >> 4, idx = lane & 15;
     // rows outside the matrix feed only rows / columns of C that are not
     // stored: their addresses are clamped to row 0
@@ -1500,7 +1511,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     const gmem_t<T>* pb1 = gmem(a.Bt) + size_t(n0 + 16 + idx < N ? n0 + 16 + idx : 0) * K;
     using gvec_t = const gmem_t<vec_t>;
     const int kq = ((K + 4 * STEP - 1) / (4 * STEP)) * STEP;  // this wave's share of K
-    const int kbeg = kSplit ? wave * kq : 0, kend = kSplit ? min(K, kbeg + kq) : K;
+    const int kbeg = wave * kq, kend = min(K, kbeg + kq);
     const int kg = VEC * g;
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
     vec_t fa0[2][kNtR], fa1[2][kNtR], fb0[2][kNtR], fb1[2][kNtR];
@@ -1510,7 +1521,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     const int ti = wave >> 1, tj = wave & 1;
     const int jc = n0 + 16 * tj + idx;
     T e1v[4], e2v[4];
-    if constexpr (kSplit) {
+    {
         const bool has1 = a.epi >= 1 && a.E1, has2 = a.epi == 2;
         const gmem_t<T>* ones = gmem(nt_ones<T>());
         const gmem_t<T>* zeros = gmem(reinterpret_cast<const T*>(g_nt_zeros));
@@ -1602,34 +1613,6 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
             compute_stage(0);
         }
     }
-    if constexpr (!kSplit) {
-        // each wave stores its own quadrant (four 16 x 16 MFMA tiles)
-        const bool has1 = a.epi >= 1 && a.E1;
-        double part = 0.0;
-        auto put = [&](const acc_t& c, int ri, int cj) {
-            const int j = n0 + 16 * cj + idx;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = m0 + 16 * ri + Cfg::orow(lane, q);
-                if (i < M && j < N) {
-                    const size_t gidx = size_t(i) * N + j;
-                    const T v = has1 ? c[q] * gmem(a.E1)[gidx] : c[q];
-                    if (a.transC) gmem(a.C)[size_t(j) * M + i] = v;
-                    else gmem(a.C)[gidx] = v;
-                    if (a.epi == 2) part += double(gmem(a.E2)[gidx]) * double(v);
-                }
-            }
-        };
-        put(c00, 0, 0);
-        put(c01, 0, 1);
-        put(c10, 1, 0);
-        put(c11, 1, 1);
-        if (a.epi == 2) {
-            const double sm = block_sum(part, red);
-            if (tid == 0) gmem(a.part)[by * gx + bx] = sm;
-        }
-        return;
-    }
     // sum the four waves' partial tiles: wave w finishes tile (w / 2, w % 2)
     {
         T* mine = red_tile + wave * 16 * 64;
@@ -1663,11 +1646,149 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     }
 }
 
-template <typename T, bool kFast, bool kSplit>
+// 64 x 64 block tile staged through LDS: per K slice of 128 bytes per row
+// (32 f32 / 16 f64), the block copies 64 rows of A and of Bt with coalesced
+// 16-byte loads (eight lanes per row, one cache line) into a double-buffered
+// LDS tile (rows padded by 16 bytes: the 16-byte fragment reads of 16
+// consecutive rows hit distinct banks), and wave w multiplies its 32 x 32
+// quadrant (w / 2, w % 2) from it: lane group g reads VEC consecutive k of its
+// row per 16-byte read, one read feeding VEC instructions (the permutation of
+// K of the direct kernel, shared by A and Bt).  One barrier per slice; the
+// next slice's global loads are in flight while the current one is multiplied.
+template <typename T>
+__device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
+    using Cfg = MfmaCfg<T>;
+    using acc_t = typename Cfg::acc_t;
+    constexpr int VEC = NtCfg<T>::VEC, STEP = 4 * VEC;
+    constexpr int BK = 128 / int(sizeof(T));      // k per slice
+    constexpr int LD = BK + VEC;                  // padded row (elements)
+    constexpr int CPR = BK / VEC;                 // 16-byte chunks per row (8)
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    __shared__ __align__(16) T As[2][64 * LD];
+    __shared__ __align__(16) T Bs[2][64 * LD];
+    __shared__ double red[17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int M = a.M, N = a.N, K = a.K;
+    const int bm = by * 64, bn = bx * 64;
+    // this thread's two chunks of each operand tile: rows r0, r0 + 32, chunk cc
+    const int r0 = tid / CPR, cc = tid % CPR;
+    const gmem_t<T>* pa[2];
+    const gmem_t<T>* pb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ra = bm + r0 + 32 * h, rb = bn + r0 + 32 * h;
+        pa[h] = gmem(a.A) + size_t(ra < M ? ra : 0) * K;
+        pb[h] = gmem(a.Bt) + size_t(rb < N ? rb : 0) * K;
+    }
+    vec_t va[2], vb[2];
+    auto gload = [&](int k0) {
+        const int k = k0 + cc * VEC;
+        if (k0 + BK <= K && (K % VEC) == 0) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                va[h] = *reinterpret_cast<const gmem_t<vec_t>*>(pa[h] + k);
+                vb[h] = *reinterpret_cast<const gmem_t<vec_t>*>(pb[h] + k);
+            }
+        } else {  // tail slice: zeros past K
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const bool in = k + e < K;
+                    va[h][e] = in ? pa[h][k + e] : T(0);
+                    vb[h][e] = in ? pb[h][k + e] : T(0);
+                }
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<vec_t*>(&As[buf][(r0 + 32 * h) * LD + cc * VEC]) = va[h];
+            *reinterpret_cast<vec_t*>(&Bs[buf][(r0 + 32 * h) * LD + cc * VEC]) = vb[h];
+        }
+    };
+    const int g = lane >> 4, idx = lane & 15;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
+    auto compute = [&](int buf) {
+        const T* A0 = &As[buf][(wm + idx) * LD + VEC * g];
+        const T* A1 = A0 + 16 * LD;
+        const T* B0 = &Bs[buf][(wn + idx) * LD + VEC * g];
+        const T* B1 = B0 + 16 * LD;
+#pragma unroll
+        for (int u = 0; u < BK / STEP; ++u) {
+            const vec_t fa0 = *reinterpret_cast<const vec_t*>(A0 + u * STEP);
+            const vec_t fa1 = *reinterpret_cast<const vec_t*>(A1 + u * STEP);
+            const vec_t fb0 = *reinterpret_cast<const vec_t*>(B0 + u * STEP);
+            const vec_t fb1 = *reinterpret_cast<const vec_t*>(B1 + u * STEP);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                c00 = Cfg::mma(fa0[e], fb0[e], c00);
+                c01 = Cfg::mma(fa0[e], fb1[e], c01);
+                c10 = Cfg::mma(fa1[e], fb0[e], c10);
+                c11 = Cfg::mma(fa1[e], fb1[e], c11);
+            }
+        }
+    };
+    const int nsl = (K + BK - 1) / BK;
+    gload(0);
+    // PCG state: evaluated while the first slice is in flight
+    if (a.st) {
+        const int done = a.st->done;
+        const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, 256) : 0.0;
+        const double r0n = a.st->r0norm, tol = a.st->tol;
+        const int cap = a.st->cap;
+        if (done) return;
+        if (a.check && pcg_stop_test(a.st, rrp, a.iter, r0n, tol, cap, bx == 0 && by == 0 && tid == 0, red)) return;
+    }
+    sstore(0);
+    __syncthreads();
+    for (int sl = 0; sl < nsl; ++sl) {
+        if (sl + 1 < nsl) gload((sl + 1) * BK);
+        compute(sl & 1);
+        if (sl + 1 < nsl) sstore((sl + 1) & 1);
+        __syncthreads();
+    }
+    // epilogue: each wave stores its quadrant
+    const int m0 = bm + wm, n0 = bn + wn;
+    const bool has1 = a.epi >= 1 && a.E1;
+    double part = 0.0;
+    auto put = [&](const acc_t& c, int ri, int cj) {
+        const int j = n0 + 16 * cj + idx;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = m0 + 16 * ri + Cfg::orow(lane, q);
+            if (i < M && j < N) {
+                const size_t gidx = size_t(i) * N + j;
+                const T v = has1 ? c[q] * gmem(a.E1)[gidx] : c[q];
+                if (a.transC) gmem(a.C)[size_t(j) * M + i] = v;
+                else gmem(a.C)[gidx] = v;
+                if (a.epi == 2) part += double(gmem(a.E2)[gidx]) * double(v);
+            }
+        }
+    };
+    put(c00, 0, 0);
+    put(c01, 0, 1);
+    put(c10, 1, 0);
+    put(c11, 1, 1);
+    if (a.epi == 2) {
+        const double sm = block_sum(part, red);
+        if (tid == 0) gmem(a.part)[by * gx + bx] = sm;
+    }
+}
+
+template <typename T, bool kFast>
 __global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
     int bx, by;
     tile_of_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, bx, by);
-    mgemm_body<T, kFast, kSplit>(a, bx, by, gridDim.x);
+    mgemm_body<T, kFast>(a, bx, by, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_mgemm64(MGemmArgs<T> a) {
+    int bx, by;
+    tile_of_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, bx, by);
+    mgemm_lds_body<T>(a, bx, by, gridDim.x);
 }
 
 // Batched product: image blockIdx.z, its own tile grid inside the launch
@@ -1682,8 +1803,7 @@ __global__ void __launch_bounds__(256) k_mgemm_b(const MGemmArgs<T>* __restrict_
     if (bx >= gx || by >= gy || (a.st && a.st->done)) return;
     a.iter = it;
     if (ts == 64) {
-        if (mgemm_fast_k<T>(a.K, 64)) mgemm_body<T, true, false>(a, bx, by, gx);
-        else mgemm_body<T, false, false>(a, bx, by, gx);
+        mgemm_lds_body<T>(a, bx, by, gx);
     } else {
         if (mgemm_fast_k<T>(a.K)) mgemm_body<T, true>(a, bx, by, gx);
         else mgemm_body<T, false>(a, bx, by, gx);
@@ -2451,14 +2571,9 @@ hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
     const int ts = a.tile == 64 ? 64 : 32;
     dim3 grid((a.N + ts - 1) / ts, (a.M + ts - 1) / ts);
     if (nblocks) *nblocks = int(grid.x * grid.y);
-    const bool fast = mgemm_fast_k<T>(a.K, ts);
-    if (ts == 64) {
-        if (fast) tvd_launch(k_mgemm<T, true, false>, grid, dim3(256), 0, s, a);
-        else tvd_launch(k_mgemm<T, false, false>, grid, dim3(256), 0, s, a);
-    } else {
-        if (fast) tvd_launch(k_mgemm<T, true, true>, grid, dim3(256), 0, s, a);
-        else tvd_launch(k_mgemm<T, false, true>, grid, dim3(256), 0, s, a);
-    }
+    if (ts == 64) tvd_launch(k_mgemm64<T>, grid, dim3(256), 0, s, a);
+    else if (mgemm_fast_k<T>(a.K)) tvd_launch(k_mgemm<T, true>, grid, dim3(256), 0, s, a);
+    else tvd_launch(k_mgemm<T, false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
