@@ -259,9 +259,14 @@ const char* tvdeblur_last_error(tvdeblur_t h);
  * iteration (stats.inner_iters) = two preconditioner solves and two operator
  * products; the test ||r_i|| < inner_tol ||r_0|| runs once per iteration, on
  * the updated residual.  p->replay_host runs exactly the given counts.
- * Requirements: anti-reflective BC (set_bc), a separable PSF (h = g_y g_x^T)
- * of half-widths <= 16.  The P / D_P / P_D solves always run as matrix-core products with T^{-1} and T (the handle's
- * transform setting applies to tvdeblur_solve only).
+ * Requirements: anti-reflective BC (set_bc); any PSF set_psf accepts.  A
+ * separable PSF (h = g_y g_x^T) of half-widths <= 16 runs the operator
+ * H H z + alpha L z in one tile pass; other PSFs (rank r > 1, or wider)
+ * run it as two rank-r band passes, H z and then H (H z) with the stencil.
+ * The P / D_P / P_D solves run in the handle's transform form: products
+ * with T^{-1} and T (TVD_TRANSFORM_GEMM) or line transforms (FFT: S^ with
+ * the two end values' linear interpolant removed before it and restored
+ * after it).
  * Errors: TVD_EINVAL (also for an unsupported BC / PSF / preconditioner),
  * TVD_ESTATE, TVD_ESIZE, TVD_EDEVICE, TVD_ENOMEM, TVD_EBREAKDOWN (rho,
  * <rhat, v> or omega became 0; u_dev then holds the last iterate). */

@@ -1195,9 +1195,17 @@ class Solver final : public SolverBase {
     void ensure_reblur() {
         if (bc_ != TVD_BC_ANTIREFLECTIVE)
             throw ApiError{TVD_EINVAL, "the reblurring system needs anti-reflective BCs"};
-        if (rank_ != 1 || !yfull_ || !gemm_ok_)
-            throw ApiError{TVD_EINVAL, "the reblurring system needs a separable PSF of half-width <= 16"};
+        if (!gemm_ok_) throw ApiError{TVD_EINVAL, "the reblurring system needs the matrix-core product form"};
         if (reblur_ready_) return;
+        // separable PSF whose H H band fits the fused y-pass: the whole
+        // operator in one tile pass; otherwise (a PSF of rank > 1, or a wider
+        // band) H H z runs as two rank-r band launches, H z then H (H z) with
+        // the stencil and the dots
+        reblur_banded_ = !(rank_ == 1 && yfull_);
+        if (!reblur_banded_) reblur_bands();
+        reblur_buffers();
+    }
+    void reblur_bands() {
         const std::vector<double> Hy = blur_matrix_1d(factors_.gy[0], ny_, bc_);
         const std::vector<double> Hx = blur_matrix_1d(factors_.gx[0], nx_, bc_);
         // H'H = H H: matmul_tn(A, B) = A^T B
@@ -1214,6 +1222,8 @@ class Solver final : public SolverBase {
         xbandR_ = geo_.upload<T>(d, s_);
         kloR_ = tb.lo;
         khiR_ = tb.hi;
+    }
+    void reblur_buffers() {
         auto mats = [&](int n, const T*& Tm, const T*& Ti) {
             std::vector<double> t, ti;
             ar_transform_matrices(n, t, ti);
@@ -1238,7 +1248,9 @@ class Solver final : public SolverBase {
         Ph_ = A(N_);
         Sh_ = A(N_);
         nb_bcg_ = bcg_block_count(int(N_));
-        nb_yb_ = ((nx_ + 63) / 64) * ((ny_ + 15) / 16);
+        // partials of the operator product: one per y-pass block, or per
+        // block of the second band launch
+        nb_yb_ = reblur_banded_ ? band_blocks(ny_, nx_, ty_ht_) : ((nx_ + 63) / 64) * ((ny_ + 15) / 16);
         bcg_rr_ = D(nb_bcg_);
         bcg_rho_ = D(nb_bcg_);
         y_sig_ = D(nb_yb_);
@@ -1258,7 +1270,7 @@ class Solver final : public SolverBase {
         a.nx = nx_;
         a.wy = my_;
         a.wx = mx_;
-        a.nterms = 1;
+        a.nterms = rank_;
         a.By = HyD_;
         a.Bx = HxD_;
         a.X = v;
@@ -1267,6 +1279,41 @@ class Solver final : public SolverBase {
     }
     // r = b - A'x with FP64 coefficients and ||r||^2 partials (one per step).
     void residual_reblur(const T* x, T* r, double* rr_out) {
+        if (reblur_banded_) {  // H x into TmpD_, then b - H (H x) - alpha L x
+            BandArgsT<T, T, double, double> h{};
+            h.wrap = wrap_;
+            h.ny = ny_;
+            h.nx = nx_;
+            h.wy = my_;
+            h.wx = mx_;
+            h.nterms = rank_;
+            h.By = HyD_;
+            h.Bx = HxD_;
+            h.X = x;
+            h.Y = TmpD_;
+            TVD_HIP(launch_band(h, pick_ty(h), s_, nullptr));
+            BandArgsT<double, T, double, T> a{};
+            a.wrap = wrap_;
+            a.ny = ny_;
+            a.nx = nx_;
+            a.wy = my_;
+            a.wx = mx_;
+            a.nterms = rank_;
+            a.By = HyD_;
+            a.Bx = HxD_;
+            a.X = TmpD_;
+            a.kap = Kapd_;
+            a.cst = l_bc_ == TVD_BC_ANTIREFLECTIVE ? CstD_ : nullptr;
+            a.alpha = alpha_;
+            a.S = x;
+            a.Bvec = BD_;
+            a.Y = r;
+            a.dot_part = rr_out;
+            a.dotmode = 2;
+            a.st = st_;
+            TVD_HIP(launch_band(a, ty_ht_hp_, s_, nullptr));
+            return;
+        }
         BandArgsT<T, T, double, T> a{};
         a.wrap = wrap_;
         a.ny = ny_;
@@ -1290,6 +1337,37 @@ class Solver final : public SolverBase {
     // q = A'z (H H in the fused y-pass, + alpha L z) with <dotw, q> partials
     // (and <q, q> when qq is set).
     void ypass_reblur(const T* z, T* q, const T* dotw, double* pq, double* qq) {
+        if (reblur_banded_) {  // H z into Tmp_, then H (H z) + alpha L z and the dots
+            BandArgs<T> h = band_base();
+            h.wy = my_;
+            h.wx = mx_;
+            h.nterms = rank_;
+            h.By = Hy_;
+            h.Bx = Hx_;
+            h.X = z;
+            h.Y = Tmp_;
+            h.st = st_;
+            launch(h, ty_h_);
+            BandArgs<T> b = band_base();
+            b.wy = my_;
+            b.wx = mx_;
+            b.nterms = rank_;
+            b.By = Hy_;
+            b.Bx = Hx_;
+            b.X = Tmp_;
+            b.kap = Kap_;
+            b.cst = l_bc_ == TVD_BC_ANTIREFLECTIVE ? Cst_ : nullptr;
+            b.alpha = alpha_;
+            b.S = z;
+            b.Y = q;
+            b.W = dotw;
+            b.dot_part = pq;
+            b.dot_part2 = qq;
+            b.dotmode = 3;
+            b.st = st_;
+            launch(b, ty_ht_);
+            return;
+        }
         YPassArgs<T> a{};
         a.wrap = wrap_;
         a.ny = ny_;
@@ -2169,6 +2247,7 @@ class Solver final : public SolverBase {
     PsfFactors factors_{};
     bool reblur_ready_ = false, reblur_mode_ = false;
     double* lines_part_ = nullptr;  // <r, z> partials of the reblurring line passes (unused)
+    bool reblur_banded_ = false;    // H H z as two rank-r band launches (not the fused y-pass)
     const T *KyR_ = nullptr, *xbandR_ = nullptr;
     const double *KyRD_ = nullptr, *KxRD_ = nullptr, *arwy_ = nullptr, *arwx_ = nullptr;
     int kloR_ = 0, khiR_ = 0;
@@ -2463,7 +2542,7 @@ class BatchSolver final : public BatchBase {
         std::vector<FpArgs<T>> fa;
         std::vector<FinArgs> fi;
         g_rf_ = g_ri_ = g_col_ = BatchGrid{0, 1, B_, 0, line_threads_};
-        g_mg_ = BatchGrid{0, 0, B_, 0, 256};
+        g_mg_ = BatchGrid{0, 0, B_, 0, 256, img_.empty() ? 32 : img_[0]->gtile_};
         g_upd_ = BatchGrid{0, 1, B_, 0, 256};
         g_xp_ = BatchGrid{0, 1, B_, 0, 256};
         for (auto& P : img_) {

@@ -85,7 +85,10 @@ struct BandArgsT {
     const TA* Bvec;        // residual form Y = Bvec - result when non-null
     TY* Y;
     double* dot_part;      // per-block partials
-    int dotmode;           // 0 none, 1 <stencil input, result>, 2 <Y, Y>
+    int dotmode;           // 0 none, 1 <stencil input, result>, 2 <Y, Y>,
+                           // 3 <W, Y> (and <Y, Y> into dot_part2 when set)
+    const TS* W;
+    double* dot_part2;
     const PcgState* st;    // exit when st->done (nullable)
     int tile_y;            // tile height (8 or 16), chosen by the launcher
     int bgx, bgy;          // this image's grid (set by the launcher; batched launches)
@@ -360,6 +363,7 @@ struct BatchGrid {
     int gx, gy, count;
     size_t lds;
     int threads;
+    int tile;  // batched products: block tile (32 or 64)
 };
 template <typename T>
 hipError_t launch_kappa_b(const KappaArgs<T>* a, BatchGrid g, hipStream_t s);

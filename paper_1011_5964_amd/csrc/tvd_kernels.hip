@@ -187,7 +187,7 @@ __device__ __forceinline__ void stage_lds(int count, int tid, int nthreads, Load
 template <typename TX, typename TS, typename T, typename TOut>
 __device__ __forceinline__ void band_body(const BandArgsT<TX, TS, T, TOut>& a, int bx, int by, int gx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[17];
+    __shared__ double red[34];
     if (a.st && a.st->done) return;
 
     const int tid = threadIdx.x;
@@ -344,7 +344,7 @@ __device__ __forceinline__ void band_body(const BandArgsT<TX, TS, T, TOut>& a, i
         __syncthreads();
     }
 
-    double dot = 0.0;
+    double dot = 0.0, dot2 = 0.0;
 #pragma unroll
     for (int k = 0; k < kBandTYMax / 4; ++k) {
         if (k >= nacc) break;
@@ -396,8 +396,18 @@ __device__ __forceinline__ void band_body(const BandArgsT<TX, TS, T, TOut>& a, i
         a.Y[g] = out;
         if (a.dotmode == 1) dot += double(cen) * double(out);
         else if (a.dotmode == 2) dot += double(out) * double(out);
+        else if (a.dotmode == 3) {
+            dot += double(a.W[g]) * double(out);
+            dot2 += double(out) * double(out);
+        }
     }
-    if (a.dotmode) {
+    if (a.dotmode == 3) {
+        block_sum2(dot, dot2, red);
+        if (tid == 0) {
+            a.dot_part[by * gx + bx] = dot;
+            if (a.dot_part2) a.dot_part2[by * gx + bx] = dot2;
+        }
+    } else if (a.dotmode) {
         const double s = block_sum(dot, red);
         if (tid == 0) a.dot_part[by * gx + bx] = s;
     }
@@ -1449,13 +1459,14 @@ __device__ __forceinline__ void mma_slice(const T* As, const T* Bs, int lane, in
 // C = A Bt^T (MGemmArgs): a block owns a 32 x 32 tile of C and splits K over
 // its four waves; each wave accumulates the whole tile (2 x 2 MFMA 16x16
 // tiles) over its quarter of K, and the four partial tiles are summed through
-// LDS before the epilogue.  A and Bt are both k-contiguous, so every lane
-// loads its own fragments from global memory (L2) straight into registers,
-// VEC consecutive k per 16-byte load: lane group g = lane / 16 supplies
-// k = STEP j + VEC g .. + VEC - 1 (a permutation of K, the same for A and Bt),
-// so one load feeds VEC instructions.  A round (STEP k) is four loads (two
-// row halves of A and of Bt) for 4 VEC instructions; loads run one stage of
-// kNtR rounds ahead of the MFMAs.
+// LDS before the epilogue.  A and Bt are both k-contiguous.  Each wave stages
+// its K range through its own LDS tile, one slice of 128 bytes per row at a
+// time: 32 rows of A and of Bt copied with coalesced 16-byte loads (eight
+// lanes per row, one cache line), the next slice's loads in flight while the
+// current one is multiplied.  From LDS, lane group g = lane / 16 reads VEC
+// consecutive k of its row per 16-byte read: k = STEP j + VEC g .. + VEC - 1
+// (a permutation of K, the same for A and Bt), so one read feeds VEC
+// instructions.
 template <typename T>
 struct NtCfg;
 template <>
@@ -1466,25 +1477,11 @@ template <>
 struct NtCfg<double> {
     static constexpr int VEC = 2;
 };
-constexpr int kNtR = 2;  // rounds per stage
-
-// The stage loop runs branch-free when each wave's quarter of K is a whole
-// number of stages.
 template <typename T>
-__host__ __device__ constexpr bool mgemm_fast_k(int K) {
-    return K % (4 * kNtR * 4 * NtCfg<T>::VEC) == 0;
-}
-
-// kFast: each wave's K range is a whole number of stages, so the stage-pair
-// loop has no branches (its last prefetch re-reads the final stage) and the
-// compiler can count the loads in flight exactly; otherwise a general loop
-// with masked tails.
-template <typename T, bool kFast>
 __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
     using Cfg = MfmaCfg<T>;
     using acc_t = typename Cfg::acc_t;
     constexpr int VEC = NtCfg<T>::VEC, STEP = 4 * VEC;  // k consumed per round
-    constexpr int SK = kNtR * STEP;                     // k per stage
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
     __shared__ T red_tile[4 * 16 * 64];                 // [wave][tile value][lane]
     __shared__ double red[17];
@@ -1503,18 +1500,10 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     };
     const int m0 = by * 32, n0 = bx * 32;
     const int g = lane >> 4, idx = lane & 15;
-    // rows outside the matrix feed only rows / columns of C that are not
-    // stored: their addresses are clamped to row 0
-    const gmem_t<T>* pa0 = gmem(a.A) + size_t(m0 + idx < M ? m0 + idx : 0) * K;
-    const gmem_t<T>* pa1 = gmem(a.A) + size_t(m0 + 16 + idx < M ? m0 + 16 + idx : 0) * K;
-    const gmem_t<T>* pb0 = gmem(a.Bt) + size_t(n0 + idx < N ? n0 + idx : 0) * K;
-    const gmem_t<T>* pb1 = gmem(a.Bt) + size_t(n0 + 16 + idx < N ? n0 + 16 + idx : 0) * K;
     using gvec_t = const gmem_t<vec_t>;
     const int kq = ((K + 4 * STEP - 1) / (4 * STEP)) * STEP;  // this wave's share of K
     const int kbeg = wave * kq, kend = min(K, kbeg + kq);
-    const int kg = VEC * g;
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
-    vec_t fa0[2][kNtR], fa1[2][kNtR], fb0[2][kNtR], fb1[2][kNtR];
     // epilogue operands of this lane's four outputs, loaded with the first
     // operands rather than after the product (absent or outside C: ones for
     // E1, zeros for E2)
@@ -1534,83 +1523,77 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
             e2v[q] = *((in && has2) ? gmem(a.E2) + gidx : zeros);
         }
     }
-    auto compute_stage = [&](int buf) {
+    {
+        // per-wave LDS staging of this wave's K range: slices of BK k (128
+        // bytes per row), rows padded by 16 bytes
+        constexpr int BK = 128 / int(sizeof(T)), LD = BK + VEC, CPR = BK / VEC;
+        __shared__ __align__(16) T Ws[4][2][32 * LD];
+        T* As = Ws[wave][0];
+        T* Bs = Ws[wave][1];
+        const int rr = lane / CPR, cc = lane % CPR;  // rows rr + 8 h, chunk cc
+        // rows outside the matrix feed only rows / columns of C that are not
+        // stored: their addresses are clamped to row 0; k past the wave's
+        // range loads as zero
+        const gmem_t<T>* ra[4];
+        const gmem_t<T>* rb[4];
 #pragma unroll
-        for (int u = 0; u < kNtR; ++u)
+        for (int h = 0; h < 4; ++h) {
+            const int ia = m0 + rr + 8 * h, ib = n0 + rr + 8 * h;
+            ra[h] = gmem(a.A) + size_t(ia < M ? ia : 0) * K;
+            rb[h] = gmem(a.Bt) + size_t(ib < N ? ib : 0) * K;
+        }
+        vec_t la[4], lb[4];
+        auto gload = [&](int k0) {
+            const int k = k0 + cc * VEC;
+            if (k0 + BK <= kend && (K % VEC) == 0) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                c00 = Cfg::mma(fa0[buf][u][e], fb0[buf][u][e], c00);
-                c01 = Cfg::mma(fa0[buf][u][e], fb1[buf][u][e], c01);
-                c10 = Cfg::mma(fa1[buf][u][e], fb0[buf][u][e], c10);
-                c11 = Cfg::mma(fa1[buf][u][e], fb1[buf][u][e], c11);
-            }
-    };
-    if constexpr (kFast) {
-        auto load_full = [&](int buf, int k0) {
+                for (int h = 0; h < 4; ++h) {
+                    la[h] = *reinterpret_cast<gvec_t*>(ra[h] + k);
+                    lb[h] = *reinterpret_cast<gvec_t*>(rb[h] + k);
+                }
+            } else {
 #pragma unroll
-            for (int u = 0; u < kNtR; ++u) {
-                const int k = k0 + u * STEP + kg;
-                fa0[buf][u] = *reinterpret_cast<gvec_t*>(pa0 + k);
-                fa1[buf][u] = *reinterpret_cast<gvec_t*>(pa1 + k);
-                fb0[buf][u] = *reinterpret_cast<gvec_t*>(pb0 + k);
-                fb1[buf][u] = *reinterpret_cast<gvec_t*>(pb1 + k);
+                for (int h = 0; h < 4; ++h)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const bool in = k + e < kend;
+                        la[h][e] = in ? ra[h][k + e] : T(0);
+                        lb[h][e] = in ? rb[h][k + e] : T(0);
+                    }
             }
         };
-        // scheduling barriers keep each stage's loads ahead of the previous
-        // stage's MFMAs (the scheduler would otherwise pull every load next
-        // to its use and leave almost nothing in flight); an odd last stage
-        // is computed after the loop from the buffer it was loaded into
-        const int nst = (kend - kbeg) / SK;
-        const int last = kend - SK;
-        if (nst > 0) load_full(0, kbeg);
-        if (state_stops()) return;
-        if (nst > 0) {
-            int st = 0;
-            for (; st + 2 <= nst; st += 2) {
-                load_full(1, kbeg + (st + 1) * SK);
-                __builtin_amdgcn_sched_barrier(0);
-                compute_stage(0);
-                __builtin_amdgcn_sched_barrier(0);
-                load_full(0, min(kbeg + (st + 2) * SK, last));
-                __builtin_amdgcn_sched_barrier(0);
-                compute_stage(1);
-                __builtin_amdgcn_sched_barrier(0);
+        auto sstore = [&]() {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                *reinterpret_cast<vec_t*>(As + (rr + 8 * h) * LD + cc * VEC) = la[h];
+                *reinterpret_cast<vec_t*>(Bs + (rr + 8 * h) * LD + cc * VEC) = lb[h];
             }
-            if (st < nst) compute_stage(0);
-        }
-    } else {
-        if (state_stops()) return;
-        const bool vec_ok = (K % VEC) == 0;  // uniform
-        auto load_masked = [&](int buf, int k0) {
+        };
+        const T* A0 = As + idx * LD + VEC * g;
+        const T* B0 = Bs + idx * LD + VEC * g;
+        auto compute = [&]() {
 #pragma unroll
-            for (int u = 0; u < kNtR; ++u) {
-                const int k = k0 + u * STEP + kg;
-                if (vec_ok) {
-                    const int kc = min(k, K - VEC);
-                    const bool in = k < kend;
-                    const vec_t x0 = *reinterpret_cast<gvec_t*>(pa0 + kc);
-                    const vec_t x1 = *reinterpret_cast<gvec_t*>(pa1 + kc);
-                    const vec_t y0 = *reinterpret_cast<gvec_t*>(pb0 + kc);
-                    const vec_t y1 = *reinterpret_cast<gvec_t*>(pb1 + kc);
-                    fa0[buf][u] = in ? x0 : vec_t{};
-                    fa1[buf][u] = in ? x1 : vec_t{};
-                    fb0[buf][u] = in ? y0 : vec_t{};
-                    fb1[buf][u] = in ? y1 : vec_t{};
-                } else {
+            for (int u = 0; u < BK / STEP; ++u) {
+                const vec_t fa0 = *reinterpret_cast<const vec_t*>(A0 + u * STEP);
+                const vec_t fa1 = *reinterpret_cast<const vec_t*>(A0 + 16 * LD + u * STEP);
+                const vec_t fb0 = *reinterpret_cast<const vec_t*>(B0 + u * STEP);
+                const vec_t fb1 = *reinterpret_cast<const vec_t*>(B0 + 16 * LD + u * STEP);
 #pragma unroll
-                    for (int c = 0; c < VEC; ++c) {
-                        const bool in = k + c < kend;
-                        fa0[buf][u][c] = in ? pa0[k + c] : T(0);
-                        fa1[buf][u][c] = in ? pa1[k + c] : T(0);
-                        fb0[buf][u][c] = in ? pb0[k + c] : T(0);
-                        fb1[buf][u][c] = in ? pb1[k + c] : T(0);
-                    }
+                for (int e = 0; e < VEC; ++e) {
+                    c00 = Cfg::mma(fa0[e], fb0[e], c00);
+                    c01 = Cfg::mma(fa0[e], fb1[e], c01);
+                    c10 = Cfg::mma(fa1[e], fb0[e], c10);
+                    c11 = Cfg::mma(fa1[e], fb1[e], c11);
                 }
             }
         };
-        for (int k0 = kbeg; k0 < kend; k0 += SK) {
-            load_masked(0, k0);
-            compute_stage(0);
+        const int nsl = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+        if (nsl > 0) gload(kbeg);
+        if (state_stops()) return;
+        for (int sl = 0; sl < nsl; ++sl) {
+            sstore();  // the wave's LDS reads of the previous slice are done (in-order LDS)
+            if (sl + 1 < nsl) gload(kbeg + (sl + 1) * BK);
+            compute();
         }
     }
     // sum the four waves' partial tiles: wave w finishes tile (w / 2, w % 2)
@@ -1777,11 +1760,11 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     }
 }
 
-template <typename T, bool kFast>
+template <typename T>
 __global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
     int bx, by;
     tile_of_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, bx, by);
-    mgemm_body<T, kFast>(a, bx, by, gridDim.x);
+    mgemm_body<T>(a, bx, by, gridDim.x);
 }
 
 template <typename T>
@@ -1791,23 +1774,19 @@ __global__ void __launch_bounds__(256) k_mgemm64(MGemmArgs<T> a) {
     mgemm_lds_body<T>(a, bx, by, gridDim.x);
 }
 
-// Batched product: image blockIdx.z, its own tile grid inside the launch
+// Batched products: image blockIdx.z, its own tile grid inside the launch
 // grid; images whose PCG has stopped skip their blocks.  it: PCG iteration.
-template <typename T>
+// One kernel per block tile (each with only its own LDS).
+template <typename T, int kTile>
 __global__ void __launch_bounds__(256) k_mgemm_b(const MGemmArgs<T>* __restrict__ as, int it) {
     MGemmArgs<T> a = as[blockIdx.z];
-    const int ts = a.tile == 64 ? 64 : 32;
-    const int gx = (a.N + ts - 1) / ts, gy = (a.M + ts - 1) / ts;
+    const int gx = (a.N + kTile - 1) / kTile, gy = (a.M + kTile - 1) / kTile;
     const int b = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int bx = b % gridDim.x, by = b / gridDim.x;
     if (bx >= gx || by >= gy || (a.st && a.st->done)) return;
     a.iter = it;
-    if (ts == 64) {
-        mgemm_lds_body<T>(a, bx, by, gx);
-    } else {
-        if (mgemm_fast_k<T>(a.K)) mgemm_body<T, true>(a, bx, by, gx);
-        else mgemm_body<T, false>(a, bx, by, gx);
-    }
+    if constexpr (kTile == 64) mgemm_lds_body<T>(a, bx, by, gx);
+    else mgemm_body<T>(a, bx, by, gx);
 }
 
 // FP64 sums of products C = sum_t coef_t op(A_t) B_t on the matrix cores
@@ -2572,14 +2551,14 @@ hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
     dim3 grid((a.N + ts - 1) / ts, (a.M + ts - 1) / ts);
     if (nblocks) *nblocks = int(grid.x * grid.y);
     if (ts == 64) tvd_launch(k_mgemm64<T>, grid, dim3(256), 0, s, a);
-    else if (mgemm_fast_k<T>(a.K)) tvd_launch(k_mgemm<T, true>, grid, dim3(256), 0, s, a);
-    else tvd_launch(k_mgemm<T, false>, grid, dim3(256), 0, s, a);
+    else tvd_launch(k_mgemm<T>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_mgemm_b(const MGemmArgs<T>* a, int it, BatchGrid g, hipStream_t s) {
-    tvd_launch(k_mgemm_b<T>, dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a, it);
+    if (g.tile == 64) tvd_launch((k_mgemm_b<T, 64>), dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a, it);
+    else tvd_launch((k_mgemm_b<T, 32>), dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a, it);
     return hipGetLastError();
 }
 
