@@ -2518,6 +2518,27 @@ class BatchSolver final : public BatchBase {
             g_y_.lds = std::max(g_y_.lds, ypass_lds_bytes(2 * S->my_, sizeof(T)));
             g_yf_lds_ = std::max(g_yf_lds_, ypass_full_lds_bytes(2 * S->my_, S->kw_, sizeof(T)));
         }
+        // compact grids of the whole-operator y-pass and of the products:
+        // per-image block offsets (one block per real tile)
+        {
+            std::vector<int> py(1, 0), p32(1, 0), p64(1, 0);
+            for (auto& S : img_) {
+                py.push_back(py.back() + ((S->nx_ + 63) / 64) * ((S->ny_ + 15) / 16));
+                p32.push_back(p32.back() + ((S->nx_ + 31) / 32) * ((S->ny_ + 31) / 32));
+                p64.push_back(p64.back() + ((S->nx_ + 63) / 64) * ((S->ny_ + 63) / 64));
+            }
+            auto up = [&](const std::vector<int>& v) {
+                int* d = static_cast<int*>(arena_.alloc(v.size() * sizeof(int)));
+                TVD_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s_));
+                return d;
+            };
+            pre_y_ = up(py);
+            pre_mg32_ = up(p32);
+            pre_mg64_ = up(p64);
+            tot_y_ = py.back();
+            tot_mg32_ = p32.back();
+            tot_mg64_ = p64.back();
+        }
         TVD_HIP(hipStreamSynchronize(s_));
     }
 
@@ -2543,6 +2564,8 @@ class BatchSolver final : public BatchBase {
         std::vector<FinArgs> fi;
         g_rf_ = g_ri_ = g_col_ = BatchGrid{0, 1, B_, 0, line_threads_};
         g_mg_ = BatchGrid{0, 0, B_, 0, 256, img_.empty() ? 32 : img_[0]->gtile_};
+        g_mg_.prefix = img_.empty() ? nullptr : (g_mg_.tile == 64 ? pre_mg64_ : pre_mg32_);
+        g_mg_.total = g_mg_.tile == 64 ? tot_mg64_ : tot_mg32_;
         g_upd_ = BatchGrid{0, 1, B_, 0, 256};
         g_xp_ = BatchGrid{0, 1, B_, 0, 256};
         for (auto& P : img_) {
@@ -2683,6 +2706,8 @@ class BatchSolver final : public BatchBase {
         if (bmode_ == 1 && yfull_) {
             BatchGrid g = g_y_;
             g.lds = g_yf_lds_;
+            g.prefix = pre_y_;
+            g.total = tot_y_;
             TVD_HIP(launch_ypass_full_b<T>(a, g, s_));
         } else {
             TVD_HIP(launch_ypass_b<T>(a, g_y_, s_));
@@ -2934,6 +2959,8 @@ class BatchSolver final : public BatchBase {
               *gm4_[2] = {};
     XPassArgs<T>* xp_ = nullptr;
     BatchGrid g_mg_{}, g_upd_{}, g_xp_{};
+    const int *pre_y_ = nullptr, *pre_mg32_ = nullptr, *pre_mg64_ = nullptr;  // compact-grid block offsets
+    int tot_y_ = 0, tot_mg32_ = 0, tot_mg64_ = 0;
     bool gemm_ok_ = false;
     bool yfull_ = false;     // product form: k_ypass_full for every image
     size_t g_yf_lds_ = 0;

@@ -364,6 +364,10 @@ struct BatchGrid {
     size_t lds;
     int threads;
     int tile;  // batched products: block tile (32 or 64)
+    // compact grids: blocks [prefix[i], prefix[i+1]) belong to image i and
+    // the launch has prefix[count] blocks (nullptr: gx x gy x count grid)
+    const int* prefix;
+    int total;
 };
 template <typename T>
 hipError_t launch_kappa_b(const KappaArgs<T>* a, BatchGrid g, hipStream_t s);

@@ -1406,12 +1406,36 @@ __global__ void __launch_bounds__(kYThreads) k_ypass_full_bcg(YPassArgs<T> a) {
     ypass_full_body<T, true, true>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
+// Image of block b of a compact batched grid: the last i with prefix[i] <= b.
+__device__ __forceinline__ int batch_image(const int* __restrict__ prefix, int count, int b) {
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kYThreads) k_ypass_full_b(const YPassArgs<T>* __restrict__ as) {
     const YPassArgs<T> a = as[blockIdx.z];
     const int gx = (a.nx + kYTX - 1) / kYTX, gy = (a.ny + kYTY - 1) / kYTY;
     if (int(blockIdx.x) >= gx || int(blockIdx.y) >= gy || a.st->done) return;
     ypass_full_body<T, false>(a, blockIdx.x, blockIdx.y, gx);
+}
+
+// The same on a compact grid (one block per tile of each image).
+template <typename T>
+__global__ void __launch_bounds__(kYThreads) k_ypass_full_bc(const YPassArgs<T>* __restrict__ as,
+                                                             const int* __restrict__ prefix, int count) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int img = batch_image(prefix, count, b);
+    const YPassArgs<T> a = as[img];
+    if (a.st->done) return;
+    const int gx = (a.nx + kYTX - 1) / kYTX;
+    const int local = b - prefix[img];
+    ypass_full_body<T, false>(a, local % gx, local / gx, gx);
 }
 
 // ------------------------------------------------------------------------
@@ -1787,6 +1811,20 @@ __global__ void __launch_bounds__(256) k_mgemm_b(const MGemmArgs<T>* __restrict_
     a.iter = it;
     if constexpr (kTile == 64) mgemm_lds_body<T>(a, bx, by, gx);
     else mgemm_body<T>(a, bx, by, gx);
+}
+
+template <typename T, int kTile>
+__global__ void __launch_bounds__(256) k_mgemm_bc(const MGemmArgs<T>* __restrict__ as, int it,
+                                                  const int* __restrict__ prefix, int count) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int img = batch_image(prefix, count, b);
+    MGemmArgs<T> a = as[img];
+    if (a.st && a.st->done) return;
+    a.iter = it;
+    const int gx = (a.N + kTile - 1) / kTile;
+    const int local = b - prefix[img];
+    if constexpr (kTile == 64) mgemm_lds_body<T>(a, local % gx, local / gx, gx);
+    else mgemm_body<T>(a, local % gx, local / gx, gx);
 }
 
 // FP64 sums of products C = sum_t coef_t op(A_t) B_t on the matrix cores
@@ -2557,6 +2595,11 @@ hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
 
 template <typename T>
 hipError_t launch_mgemm_b(const MGemmArgs<T>* a, int it, BatchGrid g, hipStream_t s) {
+    if (g.prefix) {
+        if (g.tile == 64) tvd_launch((k_mgemm_bc<T, 64>), dim3(g.total), dim3(256), 0, s, a, it, g.prefix, g.count);
+        else tvd_launch((k_mgemm_bc<T, 32>), dim3(g.total), dim3(256), 0, s, a, it, g.prefix, g.count);
+        return hipGetLastError();
+    }
     if (g.tile == 64) tvd_launch((k_mgemm_b<T, 64>), dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a, it);
     else tvd_launch((k_mgemm_b<T, 32>), dim3(g.gx, g.gy, g.count), dim3(256), 0, s, a, it);
     return hipGetLastError();
@@ -3033,6 +3076,11 @@ hipError_t launch_ypass_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_ypass_full_b(const YPassArgs<T>* a, BatchGrid g, hipStream_t s) {
+    if (g.prefix) {
+        allow_lds(reinterpret_cast<const void*>(&k_ypass_full_bc<T>), g.lds);
+        tvd_launch(k_ypass_full_bc<T>, dim3(g.total), dim3(kYThreads), g.lds, s, a, g.prefix, g.count);
+        return hipGetLastError();
+    }
     allow_lds(reinterpret_cast<const void*>(&k_ypass_full_b<T>), g.lds);
     tvd_launch(k_ypass_full_b<T>, dim3(g.gx, g.gy, g.count), dim3(kYThreads), g.lds, s, a);
     return hipGetLastError();

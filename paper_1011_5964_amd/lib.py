@@ -309,8 +309,8 @@ class TVDeblur:
             self._check(self.lib.tvdeblur_set_workspace(self.h, None, 0))
             self._ws = None
             return
-        if not ws.is_cuda or not ws.is_contiguous():
-            raise ValueError("workspace must be a contiguous device tensor")
+        if not ws.is_cuda or not ws.is_contiguous() or ws.device != self.device:
+            raise ValueError(f"workspace must be a contiguous tensor on {self.device}")
         self._check(self.lib.tvdeblur_set_workspace(self.h, _ptr(ws), ws.numel() * ws.element_size()))
         self._ws = ws
 
