@@ -1549,8 +1549,10 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     }
     {
         // per-wave LDS staging of this wave's K range: slices of BK k (128
-        // bytes per row), rows padded by 16 bytes
-        constexpr int BK = 128 / int(sizeof(T)), LD = BK + VEC, CPR = BK / VEC;
+        // bytes per row); the 16-byte chunk c of row r sits at c ^ ((r >> 1) & 7),
+        // so the fragment reads of 16 consecutive rows and the row-chunk
+        // stores both hit distinct banks
+        constexpr int BK = 128 / int(sizeof(T)), LD = BK, CPR = BK / VEC;
         __shared__ __align__(16) T Ws[4][2][32 * LD];
         T* As = Ws[wave][0];
         T* Bs = Ws[wave][1];
@@ -1589,19 +1591,22 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         auto sstore = [&]() {
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                *reinterpret_cast<vec_t*>(As + (rr + 8 * h) * LD + cc * VEC) = la[h];
-                *reinterpret_cast<vec_t*>(Bs + (rr + 8 * h) * LD + cc * VEC) = lb[h];
+                const int r = rr + 8 * h, sc = (cc ^ ((r >> 1) & 7)) * VEC;
+                *reinterpret_cast<vec_t*>(As + r * LD + sc) = la[h];
+                *reinterpret_cast<vec_t*>(Bs + r * LD + sc) = lb[h];
             }
         };
-        const T* A0 = As + idx * LD + VEC * g;
-        const T* B0 = Bs + idx * LD + VEC * g;
+        const int sw = (idx >> 1) & 7;  // rows idx and idx + 16 share it
+        const T* A0 = As + idx * LD;
+        const T* B0 = Bs + idx * LD;
         auto compute = [&]() {
 #pragma unroll
             for (int u = 0; u < BK / STEP; ++u) {
-                const vec_t fa0 = *reinterpret_cast<const vec_t*>(A0 + u * STEP);
-                const vec_t fa1 = *reinterpret_cast<const vec_t*>(A0 + 16 * LD + u * STEP);
-                const vec_t fb0 = *reinterpret_cast<const vec_t*>(B0 + u * STEP);
-                const vec_t fb1 = *reinterpret_cast<const vec_t*>(B0 + 16 * LD + u * STEP);
+                const int c = ((g + 4 * u) ^ sw) * VEC;
+                const vec_t fa0 = *reinterpret_cast<const vec_t*>(A0 + c);
+                const vec_t fa1 = *reinterpret_cast<const vec_t*>(A0 + 16 * LD + c);
+                const vec_t fb0 = *reinterpret_cast<const vec_t*>(B0 + c);
+                const vec_t fb1 = *reinterpret_cast<const vec_t*>(B0 + 16 * LD + c);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     c00 = Cfg::mma(fa0[e], fb0[e], c00);
@@ -1656,8 +1661,9 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
 // 64 x 64 block tile staged through LDS: per K slice of 128 bytes per row
 // (32 f32 / 16 f64), the block copies 64 rows of A and of Bt with coalesced
 // 16-byte loads (eight lanes per row, one cache line) into a double-buffered
-// LDS tile (rows padded by 16 bytes: the 16-byte fragment reads of 16
-// consecutive rows hit distinct banks), and wave w multiplies its 32 x 32
+// LDS tile (16-byte chunks swizzled within each row, chunk c of row r at
+// c ^ ((r >> 1) & 7): the fragment reads of 16 consecutive rows and the
+// row-chunk stores hit distinct banks), and wave w multiplies its 32 x 32
 // quadrant (w / 2, w % 2) from it: lane group g reads VEC consecutive k of its
 // row per 16-byte read, one read feeding VEC instructions (the permutation of
 // K of the direct kernel, shared by A and Bt).  One barrier per slice; the
@@ -1668,7 +1674,7 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     using acc_t = typename Cfg::acc_t;
     constexpr int VEC = NtCfg<T>::VEC, STEP = 4 * VEC;
     constexpr int BK = 128 / int(sizeof(T));      // k per slice
-    constexpr int LD = BK + VEC;                  // padded row (elements)
+    constexpr int LD = BK;                        // row (elements); 16-byte chunks swizzled
     constexpr int CPR = BK / VEC;                 // 16-byte chunks per row (8)
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
     __shared__ __align__(16) T As[2][64 * LD];
@@ -1710,24 +1716,28 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            *reinterpret_cast<vec_t*>(&As[buf][(r0 + 32 * h) * LD + cc * VEC]) = va[h];
-            *reinterpret_cast<vec_t*>(&Bs[buf][(r0 + 32 * h) * LD + cc * VEC]) = vb[h];
+            const int r = r0 + 32 * h, sc = (cc ^ ((r >> 1) & 7)) * VEC;
+            *reinterpret_cast<vec_t*>(&As[buf][r * LD + sc]) = va[h];
+            *reinterpret_cast<vec_t*>(&Bs[buf][r * LD + sc]) = vb[h];
         }
     };
     const int g = lane >> 4, idx = lane & 15;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
     auto compute = [&](int buf) {
-        const T* A0 = &As[buf][(wm + idx) * LD + VEC * g];
+        // rows wm + idx (+16): (row >> 1) & 7 is the same for row and row + 16
+        const int sa = ((wm + idx) >> 1) & 7, sb = ((wn + idx) >> 1) & 7;
+        const T* A0 = &As[buf][(wm + idx) * LD];
         const T* A1 = A0 + 16 * LD;
-        const T* B0 = &Bs[buf][(wn + idx) * LD + VEC * g];
+        const T* B0 = &Bs[buf][(wn + idx) * LD];
         const T* B1 = B0 + 16 * LD;
 #pragma unroll
         for (int u = 0; u < BK / STEP; ++u) {
-            const vec_t fa0 = *reinterpret_cast<const vec_t*>(A0 + u * STEP);
-            const vec_t fa1 = *reinterpret_cast<const vec_t*>(A1 + u * STEP);
-            const vec_t fb0 = *reinterpret_cast<const vec_t*>(B0 + u * STEP);
-            const vec_t fb1 = *reinterpret_cast<const vec_t*>(B1 + u * STEP);
+            const int ca = ((g + 4 * u) ^ sa) * VEC, cb = ((g + 4 * u) ^ sb) * VEC;
+            const vec_t fa0 = *reinterpret_cast<const vec_t*>(A0 + ca);
+            const vec_t fa1 = *reinterpret_cast<const vec_t*>(A1 + ca);
+            const vec_t fb0 = *reinterpret_cast<const vec_t*>(B0 + cb);
+            const vec_t fb1 = *reinterpret_cast<const vec_t*>(B1 + cb);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 c00 = Cfg::mma(fa0[e], fb0[e], c00);
