@@ -1481,9 +1481,9 @@ __device__ __forceinline__ void mma_slice(const T* As, const T* Bs, int lane, in
 }
 
 // C = A Bt^T (MGemmArgs): a block owns a 32 x 32 tile of C and splits K over
-// its four waves; each wave accumulates the whole tile (2 x 2 MFMA 16x16
-// tiles) over its quarter of K, and the four partial tiles are summed through
-// LDS before the epilogue.  A and Bt are both k-contiguous.  Each wave stages
+// its kW waves (4 or 8); each wave accumulates the whole tile (2 x 2 MFMA
+// 16x16 tiles) over its share of K, and the partial tiles are summed through
+// LDS before the epilogue (by waves 0..3, one 16 x 16 quadrant each).  A and Bt are both k-contiguous.  Each wave stages
 // its K range through its own LDS tile, one slice of 128 bytes per row at a
 // time: 32 rows of A and of Bt copied with coalesced 16-byte loads (eight
 // lanes per row, one cache line), the next slice's loads in flight while the
@@ -1501,13 +1501,13 @@ template <>
 struct NtCfg<double> {
     static constexpr int VEC = 2;
 };
-template <typename T>
+template <typename T, int kW = 4>
 __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
     using Cfg = MfmaCfg<T>;
     using acc_t = typename Cfg::acc_t;
     constexpr int VEC = NtCfg<T>::VEC, STEP = 4 * VEC;  // k consumed per round
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
-    __shared__ T red_tile[4 * 16 * 64];                 // [wave][tile value][lane]
+    __shared__ T red_tile[kW * 16 * 64];                // [wave][tile value][lane]
     __shared__ double red[17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int M = a.M, N = a.N, K = a.K;
@@ -1516,22 +1516,23 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     auto state_stops = [&]() -> bool {
         if (!a.st) return false;
         const int done = a.st->done;
-        const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, 256) : 0.0;
+        const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, kW * 64) : 0.0;
         const double r0 = a.st->r0norm, tol = a.st->tol;
         const int cap = a.st->cap;
         if (done) return true;
         return a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red);
     };
     const int m0 = by * 32, n0 = bx * 32;
+    constexpr int NT = kW * 64;
     const int g = lane >> 4, idx = lane & 15;
     using gvec_t = const gmem_t<vec_t>;
-    const int kq = ((K + 4 * STEP - 1) / (4 * STEP)) * STEP;  // this wave's share of K
+    const int kq = ((K + kW * STEP - 1) / (kW * STEP)) * STEP;  // this wave's share of K
     const int kbeg = wave * kq, kend = min(K, kbeg + kq);
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
     // epilogue operands of this lane's four outputs, loaded with the first
     // operands rather than after the product (absent or outside C: ones for
     // E1, zeros for E2)
-    const int ti = wave >> 1, tj = wave & 1;
+    const int ti = (wave & 3) >> 1, tj = wave & 1;
     const int jc = n0 + 16 * tj + idx;
     T e1v[4], e2v[4];
     {
@@ -1553,7 +1554,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         // so the fragment reads of 16 consecutive rows and the row-chunk
         // stores both hit distinct banks
         constexpr int BK = 128 / int(sizeof(T)), LD = BK, CPR = BK / VEC;
-        __shared__ __align__(16) T Ws[4][2][32 * LD];
+        __shared__ __align__(16) T Ws[kW][2][32 * LD];
         T* As = Ws[wave][0];
         T* Bs = Ws[wave][1];
         const int rr = lane / CPR, cc = lane % CPR;  // rows rr + 8 h, chunk cc
@@ -1640,9 +1641,14 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+        if (wave >= 4) break;
         const int rv = (wave * 4 + q) * 64 + lane;
-        const T v0 = red_tile[rv] + red_tile[16 * 64 + rv];
-        const T v1 = red_tile[2 * 16 * 64 + rv] + red_tile[3 * 16 * 64 + rv];
+        T v0 = red_tile[rv] + red_tile[16 * 64 + rv];
+        T v1 = red_tile[2 * 16 * 64 + rv] + red_tile[3 * 16 * 64 + rv];
+        if constexpr (kW == 8) {
+            v0 += red_tile[4 * 16 * 64 + rv] + red_tile[5 * 16 * 64 + rv];
+            v1 += red_tile[6 * 16 * 64 + rv] + red_tile[7 * 16 * 64 + rv];
+        }
         const T v = (v0 + v1) * e1v[q];  // e1v = 1 without a scale: exact
         const int i = m0 + 16 * ti + Cfg::orow(lane, q);
         if (i < M && jc < N) {
@@ -1794,11 +1800,17 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     }
 }
 
+// Waves per block of the single-image split-K product: 8 for FP64 (its
+// longer MFMAs leave room for a second wave per SIMD; 8% off the FP64
+// restore at 512^2), 4 for FP32 (8 measured no faster).
 template <typename T>
-__global__ void __launch_bounds__(256) k_mgemm(MGemmArgs<T> a) {
+constexpr int kMgemmWaves = sizeof(T) == 8 ? 8 : 4;
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_mgemm(MGemmArgs<T> a) {
     int bx, by;
     tile_of_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, bx, by);
-    mgemm_body<T>(a, bx, by, gridDim.x);
+    mgemm_body<T, kMgemmWaves<T>>(a, bx, by, gridDim.x);
 }
 
 template <typename T>
@@ -2599,7 +2611,7 @@ hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
     dim3 grid((a.N + ts - 1) / ts, (a.M + ts - 1) / ts);
     if (nblocks) *nblocks = int(grid.x * grid.y);
     if (ts == 64) tvd_launch(k_mgemm64<T>, grid, dim3(256), 0, s, a);
-    else tvd_launch(k_mgemm<T>, grid, dim3(256), 0, s, a);
+    else tvd_launch(k_mgemm<T>, grid, dim3(64 * kMgemmWaves<T>), 0, s, a);
     return hipGetLastError();
 }
 
