@@ -1483,9 +1483,9 @@ __device__ __forceinline__ void mma_slice(const T* As, const T* Bs, int lane, in
 // C = A Bt^T (MGemmArgs): a block owns a 32 x 32 tile of C and splits K over
 // its kW waves (4 or 8); each wave accumulates the whole tile (2 x 2 MFMA
 // 16x16 tiles) over its share of K, and the partial tiles are summed through
-// LDS before the epilogue (by waves 0..3, one 16 x 16 quadrant each).  A and Bt are both k-contiguous.  Each wave stages
-// its K range through its own LDS tile, one slice of 128 bytes per row at a
-// time: 32 rows of A and of Bt copied with coalesced 16-byte loads (eight
+// LDS before the epilogue (by waves 0..3, one 16 x 16 quadrant each).  A and
+// Bt are both k-contiguous.  Each wave stages its K range through its own LDS
+// tile, one slice of 128 bytes per row at a time: 32 rows of A and of Bt copied with coalesced 16-byte loads (eight
 // lanes per row, one cache line), the next slice's loads in flight while the
 // current one is multiplied.  From LDS, lane group g = lane / 16 reads VEC
 // consecutive k of its row per 16-byte read: k = STEP j + VEC g .. + VEC - 1
@@ -1523,7 +1523,6 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
         return a.check && pcg_stop_test(a.st, rrp, a.iter, r0, tol, cap, bx == 0 && by == 0 && tid == 0, red);
     };
     const int m0 = by * 32, n0 = bx * 32;
-    constexpr int NT = kW * 64;
     const int g = lane >> 4, idx = lane & 15;
     using gvec_t = const gmem_t<vec_t>;
     const int kq = ((K + kW * STEP - 1) / (kW * STEP)) * STEP;  // this wave's share of K
@@ -1664,6 +1663,42 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     }
 }
 
+// FP32 products from bf16 matrix instructions: each FP32 operand is split
+// into three bf16 parts x = h + m + l (h = bf16(x), m = bf16(x - h),
+// l = bf16(x - h - m), round to nearest; both differences are exact in FP32)
+// and the product is the sum of the six part products of order 2^-16 |x y|
+// and above (hh, hm, mh, mm, hl, lh; |m| <= 2^-8 |x|, |l| <= 2^-16 |x|).  The
+// dropped ml + lm + ll is below 2^-23 |x y| and each part product is exact in
+// FP32, so the result is as accurate as an FP32 product; the bf16 matrix rate
+// is sixteen times the FP32 one.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Split four FP32 values into their h, m and l parts, four bf16 each (8 bytes).
+__device__ __forceinline__ void split3_bf16(const float (&x)[4], uint2& h, uint2& m, uint2& l) {
+    uint32_t hw[2], mw[2], lw[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const f32x2_t v = {x[2 * p], x[2 * p + 1]};
+        const bf16x2_t vh = __builtin_convertvector(v, bf16x2_t);
+        const f32x2_t r1 = v - __builtin_convertvector(vh, f32x2_t);
+        const bf16x2_t vm = __builtin_convertvector(r1, bf16x2_t);
+        const f32x2_t r2 = r1 - __builtin_convertvector(vm, f32x2_t);
+        const bf16x2_t vl = __builtin_convertvector(r2, bf16x2_t);
+        hw[p] = __builtin_bit_cast(uint32_t, vh);
+        mw[p] = __builtin_bit_cast(uint32_t, vm);
+        lw[p] = __builtin_bit_cast(uint32_t, vl);
+    }
+    h = make_uint2(hw[0], hw[1]);
+    m = make_uint2(mw[0], mw[1]);
+    l = make_uint2(lw[0], lw[1]);
+}
+
+// FP32 64 x 64 block products through the split bf16 form (above); off, they
+// run on the FP32 matrix instructions.
+constexpr bool kSplitBf16 = true;
+
 // 64 x 64 block tile staged through LDS: per K slice of 128 bytes per row
 // (32 f32 / 16 f64), the block copies 64 rows of A and of Bt with coalesced
 // 16-byte loads (eight lanes per row, one cache line) into a double-buffered
@@ -1673,18 +1708,31 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
 // quadrant (w / 2, w % 2) from it: lane group g reads VEC consecutive k of its
 // row per 16-byte read, one read feeding VEC instructions (the permutation of
 // K of the direct kernel, shared by A and Bt).  One barrier per slice; the
-// next slice's global loads are in flight while the current one is multiplied.
+// global loads of the next two slices are in flight while the current one is
+// multiplied.
+//
+// Split form (FP32 with kSplitBf16): the copy stores each operand tile as three
+// bf16 planes (h, m, l), a row of a plane being the slice's 32 k in 64 bytes,
+// 16-byte chunk c of row r at c ^ ((r >> 2) & 3) (the 16 rows of a fragment
+// read and the 8-byte stores of the copy hit distinct banks); lane group g
+// reads chunk g (k = 8 g .. 8 g + 7) of its row of each plane, and one slice is
+// one bf16 16x16x32 step: six instructions per 16 x 16 tile.
 template <typename T>
 __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
     using Cfg = MfmaCfg<T>;
     using acc_t = typename Cfg::acc_t;
+    constexpr bool SPLIT = kSplitBf16 && std::is_same<T, float>::value;
     constexpr int VEC = NtCfg<T>::VEC, STEP = 4 * VEC;
     constexpr int BK = 128 / int(sizeof(T));      // k per slice
     constexpr int LD = BK;                        // row (elements); 16-byte chunks swizzled
     constexpr int CPR = BK / VEC;                 // 16-byte chunks per row (8)
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
-    __shared__ __align__(16) T As[2][64 * LD];
-    __shared__ __align__(16) T Bs[2][64 * LD];
+    // per operand and buffer: the T tile (64 rows x 128 bytes), or three bf16
+    // planes of 64 rows x 64 bytes
+    constexpr int TILE_BYTES = SPLIT ? 3 * 64 * 64 : 64 * LD * int(sizeof(T));
+    __shared__ __align__(16) unsigned char smem[4 * TILE_BYTES];
+    T (*As)[64 * LD] = reinterpret_cast<T (*)[64 * LD]>(smem);
+    T (*Bs)[64 * LD] = reinterpret_cast<T (*)[64 * LD]>(smem + 2 * TILE_BYTES);
     __shared__ double red[17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int M = a.M, N = a.N, K = a.K;
@@ -1699,14 +1747,32 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
         pa[h] = gmem(a.A) + size_t(ra < M ? ra : 0) * K;
         pb[h] = gmem(a.Bt) + size_t(rb < N ? rb : 0) * K;
     }
-    vec_t va[2], vb[2];
-    auto gload = [&](int k0) {
+    vec_t va[2][2], vb[2][2];  // [register slot][row half]
+    // Rows of whole 16-byte chunks (K % VEC == 0): one 16-byte load per row and
+    // operand for every slice, chunks past K read from a 16-byte block of
+    // zeros (an address select: no branch and no select on a loaded value, so
+    // the wait before a copy covers only the loads that copy needs).
+    const gmem_t<vec_t>* zchunk = reinterpret_cast<const gmem_t<vec_t>*>(gmem(g_nt_zeros));
+    auto gload_al = [&](int k0, int slot) {
+        const int k = k0 + cc * VEC;
+        const bool in = k < K;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            va[slot][h] = *(in ? reinterpret_cast<const gmem_t<vec_t>*>(pa[h] + k) : zchunk);
+            vb[slot][h] = *(in ? reinterpret_cast<const gmem_t<vec_t>*>(pb[h] + k) : zchunk);
+        }
+        // keep the loads here: moved up by the compiler, they shared
+        // registers with the fragment reads and every slice waited for them
+        asm volatile("" ::: "memory");
+    };
+    // Other K: element loads past the last whole slice, zeros past K.
+    auto gload = [&](int k0, int slot) {
         const int k = k0 + cc * VEC;
         if (k0 + BK <= K && (K % VEC) == 0) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                va[h] = *reinterpret_cast<const gmem_t<vec_t>*>(pa[h] + k);
-                vb[h] = *reinterpret_cast<const gmem_t<vec_t>*>(pb[h] + k);
+                va[slot][h] = *reinterpret_cast<const gmem_t<vec_t>*>(pa[h] + k);
+                vb[slot][h] = *reinterpret_cast<const gmem_t<vec_t>*>(pb[h] + k);
             }
         } else {  // tail slice: zeros past K
 #pragma unroll
@@ -1714,23 +1780,77 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     const bool in = k + e < K;
-                    va[h][e] = in ? pa[h][k + e] : T(0);
-                    vb[h][e] = in ? pb[h][k + e] : T(0);
+                    va[slot][h][e] = in ? pa[h][k + e] : T(0);
+                    vb[slot][h][e] = in ? pb[h][k + e] : T(0);
                 }
         }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf, int slot) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int r = r0 + 32 * h, sc = (cc ^ ((r >> 1) & 7)) * VEC;
-            *reinterpret_cast<vec_t*>(&As[buf][r * LD + sc]) = va[h];
-            *reinterpret_cast<vec_t*>(&Bs[buf][r * LD + sc]) = vb[h];
+            const int r = r0 + 32 * h;
+            const vec_t xva = va[slot][h], xvb = vb[slot][h];
+            if constexpr (SPLIT) {
+                // 4 k (8 bytes per plane): half cc & 1 of chunk cc >> 1
+                const int off = r * 64 + 16 * ((cc >> 1) ^ ((r >> 2) & 3)) + 8 * (cc & 1);
+                uint2 ph, pm, pl;
+                const float xa[4] = {xva[0], xva[1], xva[2], xva[3]};
+                split3_bf16(xa, ph, pm, pl);
+                unsigned char* ta = smem + buf * TILE_BYTES + off;
+                *reinterpret_cast<uint2*>(ta) = ph;
+                *reinterpret_cast<uint2*>(ta + 64 * 64) = pm;
+                *reinterpret_cast<uint2*>(ta + 2 * 64 * 64) = pl;
+                const float xb[4] = {xvb[0], xvb[1], xvb[2], xvb[3]};
+                split3_bf16(xb, ph, pm, pl);
+                unsigned char* tb = smem + (2 + buf) * TILE_BYTES + off;
+                *reinterpret_cast<uint2*>(tb) = ph;
+                *reinterpret_cast<uint2*>(tb + 64 * 64) = pm;
+                *reinterpret_cast<uint2*>(tb + 2 * 64 * 64) = pl;
+            } else {
+                const int sc = (cc ^ ((r >> 1) & 7)) * VEC;
+                *reinterpret_cast<vec_t*>(&As[buf][r * LD + sc]) = xva;
+                *reinterpret_cast<vec_t*>(&Bs[buf][r * LD + sc]) = xvb;
+            }
         }
     };
     const int g = lane >> 4, idx = lane & 15;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
+    auto compute_split = [&](int buf) {
+        if constexpr (SPLIT) {
+            // rows wm + idx (+16): (row >> 2) & 3 is the same for row and row + 16
+            const int ra = wm + idx, rb = wn + idx;
+            const int oa = ra * 64 + 16 * (g ^ ((ra >> 2) & 3)), ob = rb * 64 + 16 * (g ^ ((rb >> 2) & 3));
+            const unsigned char* ta = smem + buf * TILE_BYTES + oa;
+            const unsigned char* tb = smem + (2 + buf) * TILE_BYTES + ob;
+            bf16x8_t fa[2][3], fb[2][3];  // [row half][plane h, m, l]
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                fa[0][q] = *reinterpret_cast<const bf16x8_t*>(ta + q * 64 * 64);
+                fa[1][q] = *reinterpret_cast<const bf16x8_t*>(ta + q * 64 * 64 + 16 * 64);
+                fb[0][q] = *reinterpret_cast<const bf16x8_t*>(tb + q * 64 * 64);
+                fb[1][q] = *reinterpret_cast<const bf16x8_t*>(tb + q * 64 * 64 + 16 * 64);
+            }
+            auto tile6 = [&](const bf16x8_t (&x)[3], const bf16x8_t (&y)[3], acc_t c) {
+                // smallest parts first
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[1], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[2], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[2], y[0], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[1], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[0], c, 0, 0, 0);
+                return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[0], c, 0, 0, 0);
+            };
+            c00 = tile6(fa[0], fb[0], c00);
+            c01 = tile6(fa[0], fb[1], c01);
+            c10 = tile6(fa[1], fb[0], c10);
+            c11 = tile6(fa[1], fb[1], c11);
+        }
+    };
     auto compute = [&](int buf) {
+        if constexpr (SPLIT) {
+            compute_split(buf);
+            return;
+        }
         // rows wm + idx (+16): (row >> 1) & 7 is the same for row and row + 16
         const int sa = ((wm + idx) >> 1) & 7, sb = ((wn + idx) >> 1) & 7;
         const T* A0 = &As[buf][(wm + idx) * LD];
@@ -1753,24 +1873,58 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
             }
         }
     };
-    const int nsl = (K + BK - 1) / BK;
-    gload(0);
-    // PCG state: evaluated while the first slice is in flight
-    if (a.st) {
+    // PCG state: evaluated while the first slices are in flight
+    auto state_stops = [&]() -> bool {
+        if (!a.st) return false;
         const int done = a.st->done;
         const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, 256) : 0.0;
         const double r0n = a.st->r0norm, tol = a.st->tol;
         const int cap = a.st->cap;
-        if (done) return;
-        if (a.check && pcg_stop_test(a.st, rrp, a.iter, r0n, tol, cap, bx == 0 && by == 0 && tid == 0, red)) return;
-    }
-    sstore(0);
-    __syncthreads();
-    for (int sl = 0; sl < nsl; ++sl) {
-        if (sl + 1 < nsl) gload((sl + 1) * BK);
-        compute(sl & 1);
-        if (sl + 1 < nsl) sstore((sl + 1) & 1);
+        if (done) return true;
+        return a.check && pcg_stop_test(a.st, rrp, a.iter, r0n, tol, cap, bx == 0 && by == 0 && tid == 0, red);
+    };
+    const int nsl = (K + BK - 1) / BK;
+    if ((K % VEC) == 0) {
+        // slice j is loaded into register slot j & 1 two slices ahead of its
+        // use and copied to LDS buffer j & 1 one slice ahead; the loop is
+        // unrolled by two so that the slots are static, and its body has no
+        // conditional step (past the last slice the loads repeat it, unused)
+        const int last = (nsl - 1) * BK;
+        gload_al(0, 0);
+        gload_al(min(BK, last), 1);
+        if (state_stops()) return;
+        sstore(0, 0);
         __syncthreads();
+        gload_al(min(2 * BK, last), 0);
+        int sl = 0;
+        for (; sl + 2 < nsl; sl += 2) {  // LDS buffer 0: slice sl
+            compute(0);
+            sstore(1, 1);  // slice sl + 1
+            __syncthreads();
+            gload_al(min((sl + 3) * BK, last), 1);
+            compute(1);
+            sstore(0, 0);  // slice sl + 2
+            __syncthreads();
+            gload_al(min((sl + 4) * BK, last), 0);
+        }
+        compute(0);  // slice sl, then slice sl + 1 if there is one
+        if (sl + 1 < nsl) {
+            sstore(1, 1);
+            __syncthreads();
+            compute(1);
+        }
+    } else {
+        // one slice ahead, in register slot 0
+        gload(0, 0);
+        if (state_stops()) return;
+        sstore(0, 0);
+        __syncthreads();
+        for (int sl = 0; sl < nsl; ++sl) {
+            if (sl + 1 < nsl) gload((sl + 1) * BK, 0);
+            compute(sl & 1);
+            if (sl + 1 < nsl) sstore((sl + 1) & 1, 0);
+            __syncthreads();
+        }
     }
     // epilogue: each wave stores its quadrant
     const int m0 = bm + wm, n0 = bn + wn;
@@ -1800,8 +1954,9 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     }
 }
 
-// Waves per block of the single-image split-K product: 8 for FP64 (its
-// longer MFMAs leave room for a second wave per SIMD; 8% off the FP64
+// Waves per block of the single-image split-K product: 8 for FP64 (half the
+// FP32 matrix rate and half the k per 16-byte LDS read, so a second wave per
+// SIMD overlaps one wave's reads with the other's MFMAs: 8% off the FP64
 // restore at 512^2), 4 for FP32 (8 measured no faster).
 template <typename T>
 constexpr int kMgemmWaves = sizeof(T) == 8 ? 8 : 4;
