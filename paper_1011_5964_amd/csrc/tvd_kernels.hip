@@ -1480,6 +1480,58 @@ __device__ __forceinline__ void mma_slice(const T* As, const T* Bs, int lane, in
     for (int kk = 0; kk < Cfg::BK / 4; ++kk) acc = Cfg::mma(as[4 * kk], bs[4 * kk * Cfg::SB], acc);
 }
 
+// FP32 products from bf16 matrix instructions: each FP32 operand is split
+// into three bf16 parts x = h + m + l (h = bf16(x), m = bf16(x - h),
+// l = bf16(x - h - m), round to nearest; both differences are exact in FP32)
+// and the product is the sum of the six part products of order 2^-16 |x y|
+// and above (hh, hm, mh, mm, hl, lh; |m| <= 2^-8 |x|, |l| <= 2^-16 |x|).  The
+// dropped ml + lm + ll is below 2^-23 |x y| and each part product is exact in
+// FP32, so the result is as accurate as an FP32 product; the bf16 matrix rate
+// is sixteen times the FP32 one.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Split four FP32 values into their h, m and l parts, four bf16 each (8 bytes).
+__device__ __forceinline__ void split3_bf16(const float (&x)[4], uint2& h, uint2& m, uint2& l) {
+    uint32_t hw[2], mw[2], lw[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const f32x2_t v = {x[2 * p], x[2 * p + 1]};
+        const bf16x2_t vh = __builtin_convertvector(v, bf16x2_t);
+        const f32x2_t r1 = v - __builtin_convertvector(vh, f32x2_t);
+        const bf16x2_t vm = __builtin_convertvector(r1, bf16x2_t);
+        const f32x2_t r2 = r1 - __builtin_convertvector(vm, f32x2_t);
+        const bf16x2_t vl = __builtin_convertvector(r2, bf16x2_t);
+        hw[p] = __builtin_bit_cast(uint32_t, vh);
+        mw[p] = __builtin_bit_cast(uint32_t, vm);
+        lw[p] = __builtin_bit_cast(uint32_t, vl);
+    }
+    h = make_uint2(hw[0], hw[1]);
+    m = make_uint2(mw[0], mw[1]);
+    l = make_uint2(lw[0], lw[1]);
+}
+
+// One 16 x 16 x 32 step of a split product into c: the six part products of
+// x = (h, m, l) and y, smallest first.  Lane layout as for the FP32 16x16x4
+// instruction (row / column l % 16, result r of lane l at row 4 (l / 16) + r);
+// lane group l / 16 supplies 8 k, the same k for x and y.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4_t mma_split6(const bf16x8_t (&x)[3], const bf16x8_t (&y)[3], f32x4_t c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[2], y[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[0], c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[0], c, 0, 0, 0);
+}
+
+// FP32 64 x 64 block products through the split bf16 form (above); off, they
+// run on the FP32 matrix instructions.  (The split-K 32 x 32 kernel keeps the
+// FP32 instructions: there the split's VALU work sits in each wave's serial
+// path and measured slower at 512^2, 6.59 -> 7.09 us per product.)
+constexpr bool kSplitBf16 = true;
+
 // C = A Bt^T (MGemmArgs): a block owns a 32 x 32 tile of C and splits K over
 // its kW waves (4 or 8); each wave accumulates the whole tile (2 x 2 MFMA
 // 16x16 tiles) over its share of K, and the partial tiles are summed through
@@ -1663,42 +1715,6 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     }
 }
 
-// FP32 products from bf16 matrix instructions: each FP32 operand is split
-// into three bf16 parts x = h + m + l (h = bf16(x), m = bf16(x - h),
-// l = bf16(x - h - m), round to nearest; both differences are exact in FP32)
-// and the product is the sum of the six part products of order 2^-16 |x y|
-// and above (hh, hm, mh, mm, hl, lh; |m| <= 2^-8 |x|, |l| <= 2^-16 |x|).  The
-// dropped ml + lm + ll is below 2^-23 |x y| and each part product is exact in
-// FP32, so the result is as accurate as an FP32 product; the bf16 matrix rate
-// is sixteen times the FP32 one.
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-typedef float f32x2_t __attribute__((ext_vector_type(2)));
-
-// Split four FP32 values into their h, m and l parts, four bf16 each (8 bytes).
-__device__ __forceinline__ void split3_bf16(const float (&x)[4], uint2& h, uint2& m, uint2& l) {
-    uint32_t hw[2], mw[2], lw[2];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        const f32x2_t v = {x[2 * p], x[2 * p + 1]};
-        const bf16x2_t vh = __builtin_convertvector(v, bf16x2_t);
-        const f32x2_t r1 = v - __builtin_convertvector(vh, f32x2_t);
-        const bf16x2_t vm = __builtin_convertvector(r1, bf16x2_t);
-        const f32x2_t r2 = r1 - __builtin_convertvector(vm, f32x2_t);
-        const bf16x2_t vl = __builtin_convertvector(r2, bf16x2_t);
-        hw[p] = __builtin_bit_cast(uint32_t, vh);
-        mw[p] = __builtin_bit_cast(uint32_t, vm);
-        lw[p] = __builtin_bit_cast(uint32_t, vl);
-    }
-    h = make_uint2(hw[0], hw[1]);
-    m = make_uint2(mw[0], mw[1]);
-    l = make_uint2(lw[0], lw[1]);
-}
-
-// FP32 64 x 64 block products through the split bf16 form (above); off, they
-// run on the FP32 matrix instructions.
-constexpr bool kSplitBf16 = true;
-
 // 64 x 64 block tile staged through LDS: per K slice of 128 bytes per row
 // (32 f32 / 16 f64), the block copies 64 rows of A and of Bt with coalesced
 // 16-byte loads (eight lanes per row, one cache line) into a double-buffered
@@ -1717,7 +1733,13 @@ constexpr bool kSplitBf16 = true;
 // read and the 8-byte stores of the copy hit distinct banks); lane group g
 // reads chunk g (k = 8 g .. 8 g + 7) of its row of each plane, and one slice is
 // one bf16 16x16x32 step: six instructions per 16 x 16 tile.
-template <typename T>
+//
+// kG = 2: eight waves in two K groups, each with its own LDS buffers; group
+// g takes slices g, g + 2, ... (both groups run the same number of steps, the
+// second one's last slice past K reading zeros), and group 1 adds its tile
+// to group 0's through LDS before the epilogue.  Twice the waves per CU for
+// grids of about one block per CU.
+template <typename T, int kG = 1>
 __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, int by, int gx) {
     using Cfg = MfmaCfg<T>;
     using acc_t = typename Cfg::acc_t;
@@ -1730,15 +1752,17 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     // per operand and buffer: the T tile (64 rows x 128 bytes), or three bf16
     // planes of 64 rows x 64 bytes
     constexpr int TILE_BYTES = SPLIT ? 3 * 64 * 64 : 64 * LD * int(sizeof(T));
-    __shared__ __align__(16) unsigned char smem[4 * TILE_BYTES];
-    T (*As)[64 * LD] = reinterpret_cast<T (*)[64 * LD]>(smem);
-    T (*Bs)[64 * LD] = reinterpret_cast<T (*)[64 * LD]>(smem + 2 * TILE_BYTES);
+    __shared__ __align__(16) unsigned char smem_all[kG * 4 * TILE_BYTES];
     __shared__ double red[17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = wave >> 2, gtid = tid & 255;  // K group, thread in the group
+    unsigned char* const smem = smem_all + grp * 4 * TILE_BYTES;
+    T (*As)[64 * LD] = reinterpret_cast<T (*)[64 * LD]>(smem);
+    T (*Bs)[64 * LD] = reinterpret_cast<T (*)[64 * LD]>(smem + 2 * TILE_BYTES);
     const int M = a.M, N = a.N, K = a.K;
     const int bm = by * 64, bn = bx * 64;
     // this thread's two chunks of each operand tile: rows r0, r0 + 32, chunk cc
-    const int r0 = tid / CPR, cc = tid % CPR;
+    const int r0 = gtid / CPR, cc = gtid % CPR;
     const gmem_t<T>* pa[2];
     const gmem_t<T>* pb[2];
 #pragma unroll
@@ -1814,7 +1838,7 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
         }
     };
     const int g = lane >> 4, idx = lane & 15;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = ((wave & 3) >> 1) * 32, wn = (wave & 1) * 32;
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
     auto compute_split = [&](int buf) {
         if constexpr (SPLIT) {
@@ -1831,19 +1855,10 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
                 fb[0][q] = *reinterpret_cast<const bf16x8_t*>(tb + q * 64 * 64);
                 fb[1][q] = *reinterpret_cast<const bf16x8_t*>(tb + q * 64 * 64 + 16 * 64);
             }
-            auto tile6 = [&](const bf16x8_t (&x)[3], const bf16x8_t (&y)[3], acc_t c) {
-                // smallest parts first
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[1], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[2], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[2], y[0], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[1], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[0], c, 0, 0, 0);
-                return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[0], c, 0, 0, 0);
-            };
-            c00 = tile6(fa[0], fb[0], c00);
-            c01 = tile6(fa[0], fb[1], c01);
-            c10 = tile6(fa[1], fb[0], c10);
-            c11 = tile6(fa[1], fb[1], c11);
+            c00 = mma_split6(fa[0], fb[0], c00);
+            c01 = mma_split6(fa[0], fb[1], c01);
+            c10 = mma_split6(fa[1], fb[0], c10);
+            c11 = mma_split6(fa[1], fb[1], c11);
         }
     };
     auto compute = [&](int buf) {
@@ -1877,53 +1892,80 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     auto state_stops = [&]() -> bool {
         if (!a.st) return false;
         const int done = a.st->done;
-        const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, 256) : 0.0;
+        const double rrp = a.check ? partial_issue(a.rr_part, a.n_rr, tid, 256 * kG) : 0.0;
         const double r0n = a.st->r0norm, tol = a.st->tol;
         const int cap = a.st->cap;
         if (done) return true;
         return a.check && pcg_stop_test(a.st, rrp, a.iter, r0n, tol, cap, bx == 0 && by == 0 && tid == 0, red);
     };
     const int nsl = (K + BK - 1) / BK;
+    const int J = (nsl + kG - 1) / kG;  // steps (slices per group)
+    // k of the group's j-th slice (the last one again past its last step)
+    auto kof = [&](int j) { return (grp + kG * min(j, J - 1)) * BK; };
     if ((K % VEC) == 0) {
         // slice j is loaded into register slot j & 1 two slices ahead of its
         // use and copied to LDS buffer j & 1 one slice ahead; the loop is
         // unrolled by two so that the slots are static, and its body has no
         // conditional step (past the last slice the loads repeat it, unused)
-        const int last = (nsl - 1) * BK;
-        gload_al(0, 0);
-        gload_al(min(BK, last), 1);
+        gload_al(kof(0), 0);
+        gload_al(kof(1), 1);
         if (state_stops()) return;
         sstore(0, 0);
         __syncthreads();
-        gload_al(min(2 * BK, last), 0);
-        int sl = 0;
-        for (; sl + 2 < nsl; sl += 2) {  // LDS buffer 0: slice sl
+        gload_al(kof(2), 0);
+        int j = 0;
+        for (; j + 2 < J; j += 2) {  // LDS buffer 0: step j
             compute(0);
-            sstore(1, 1);  // slice sl + 1
+            sstore(1, 1);  // step j + 1
             __syncthreads();
-            gload_al(min((sl + 3) * BK, last), 1);
+            gload_al(kof(j + 3), 1);
             compute(1);
-            sstore(0, 0);  // slice sl + 2
+            sstore(0, 0);  // step j + 2
             __syncthreads();
-            gload_al(min((sl + 4) * BK, last), 0);
+            gload_al(kof(j + 4), 0);
         }
-        compute(0);  // slice sl, then slice sl + 1 if there is one
-        if (sl + 1 < nsl) {
+        compute(0);  // step j, then step j + 1 if there is one
+        if (j + 1 < J) {
             sstore(1, 1);
             __syncthreads();
             compute(1);
         }
     } else {
         // one slice ahead, in register slot 0
-        gload(0, 0);
+        gload(kof(0), 0);
         if (state_stops()) return;
         sstore(0, 0);
         __syncthreads();
-        for (int sl = 0; sl < nsl; ++sl) {
-            if (sl + 1 < nsl) gload((sl + 1) * BK, 0);
-            compute(sl & 1);
-            if (sl + 1 < nsl) sstore((sl + 1) & 1, 0);
+        for (int j = 0; j < J; ++j) {
+            if (j + 1 < J) gload(kof(j + 1), 0);
+            compute(j & 1);
+            if (j + 1 < J) sstore((j + 1) & 1, 0);
             __syncthreads();
+        }
+    }
+    if constexpr (kG == 2) {
+        // group 1's tile into group 0's accumulators (through the group LDS
+        // buffers, free once every wave has passed the barrier below)
+        __syncthreads();
+        T* racc = reinterpret_cast<T*>(smem_all) + (wave & 3) * 16 * 64 + lane;
+        if (grp == 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                racc[(0 * 4 + q) * 64] = c00[q];
+                racc[(1 * 4 + q) * 64] = c01[q];
+                racc[(2 * 4 + q) * 64] = c10[q];
+                racc[(3 * 4 + q) * 64] = c11[q];
+            }
+        }
+        __syncthreads();
+        if (grp == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c00[q] += racc[(0 * 4 + q) * 64];
+                c01[q] += racc[(1 * 4 + q) * 64];
+                c10[q] += racc[(2 * 4 + q) * 64];
+                c11[q] += racc[(3 * 4 + q) * 64];
+            }
         }
     }
     // epilogue: each wave stores its quadrant
@@ -1944,10 +1986,12 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
             }
         }
     };
-    put(c00, 0, 0);
-    put(c01, 0, 1);
-    put(c10, 1, 0);
-    put(c11, 1, 1);
+    if (grp == 0) {
+        put(c00, 0, 0);
+        put(c01, 0, 1);
+        put(c10, 1, 0);
+        put(c11, 1, 1);
+    }
     if (a.epi == 2) {
         const double sm = block_sum(part, red);
         if (tid == 0) gmem(a.part)[by * gx + bx] = sm;
@@ -1968,11 +2012,13 @@ __global__ void __launch_bounds__(512) k_mgemm(MGemmArgs<T> a) {
     mgemm_body<T, kMgemmWaves<T>>(a, bx, by, gridDim.x);
 }
 
+// Single-image 64 x 64 products: two K groups (about one block per CU at the
+// sizes where this tile is chosen).
 template <typename T>
-__global__ void __launch_bounds__(256) k_mgemm64(MGemmArgs<T> a) {
+__global__ void __launch_bounds__(512) k_mgemm64(MGemmArgs<T> a) {
     int bx, by;
     tile_of_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, bx, by);
-    mgemm_lds_body<T>(a, bx, by, gridDim.x);
+    mgemm_lds_body<T, 2>(a, bx, by, gridDim.x);
 }
 
 // Batched products: image blockIdx.z, its own tile grid inside the launch
@@ -2765,7 +2811,7 @@ hipError_t launch_mgemm(const MGemmArgs<T>& a, hipStream_t s, int* nblocks) {
     const int ts = a.tile == 64 ? 64 : 32;
     dim3 grid((a.N + ts - 1) / ts, (a.M + ts - 1) / ts);
     if (nblocks) *nblocks = int(grid.x * grid.y);
-    if (ts == 64) tvd_launch(k_mgemm64<T>, grid, dim3(256), 0, s, a);
+    if (ts == 64) tvd_launch(k_mgemm64<T>, grid, dim3(512), 0, s, a);
     else tvd_launch(k_mgemm<T>, grid, dim3(64 * kMgemmWaves<T>), 0, s, a);
     return hipGetLastError();
 }
