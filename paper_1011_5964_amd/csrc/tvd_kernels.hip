@@ -1715,6 +1715,17 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
     }
 }
 
+// LDS layout of one operand tile of the split form (64 rows x 32 k, three bf16
+// planes of 64 bytes per row) in 128-byte rows, as the FP32 tiles: row r of
+// the first 8 KB holds plane h (chunks 0-3) and plane m (chunks 4-7) of tile
+// row r; row r of the last 4 KB holds plane l of tile rows r and r + 32; the
+// 16-byte chunk c of a 128-byte row q sits at c ^ ((q >> 1) & 7).
+__device__ __forceinline__ int split_off(int plane, int r, int c) {
+    const int q = plane < 2 ? r : (r & 31);
+    const int chunk = plane < 2 ? 4 * plane + c : 4 * (r >> 5) + c;
+    return (plane < 2 ? 0 : 64 * 128) + q * 128 + 16 * (chunk ^ ((q >> 1) & 7));
+}
+
 // 64 x 64 block tile staged through LDS: per K slice of 128 bytes per row
 // (32 f32 / 16 f64), the block copies 64 rows of A and of Bt with coalesced
 // 16-byte loads (eight lanes per row, one cache line) into a double-buffered
@@ -1728,9 +1739,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
 // multiplied.
 //
 // Split form (FP32 with kSplitBf16): the copy stores each operand tile as three
-// bf16 planes (h, m, l), a row of a plane being the slice's 32 k in 64 bytes,
-// 16-byte chunk c of row r at c ^ ((r >> 2) & 3) (the 16 rows of a fragment
-// read and the 8-byte stores of the copy hit distinct banks); lane group g
+// bf16 planes (h, m, l) of the slice's 32 k per row (split_off); lane group g
 // reads chunk g (k = 8 g .. 8 g + 7) of its row of each plane, and one slice is
 // one bf16 16x16x32 step: six instructions per 16 x 16 tile.
 //
@@ -1761,27 +1770,33 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     T (*Bs)[64 * LD] = reinterpret_cast<T (*)[64 * LD]>(smem + 2 * TILE_BYTES);
     const int M = a.M, N = a.N, K = a.K;
     const int bm = by * 64, bn = bx * 64;
-    // this thread's two chunks of each operand tile: rows r0, r0 + 32, chunk cc
+    // this thread's two 16-byte chunks of each operand tile (h = 0, 1): rows
+    // r0 and r0 + 32 at chunk cc; in the split form one row, rs, and the two
+    // chunks of its 8 k from 8 c8 (one 16-byte store per bf16 plane)
     const int r0 = gtid / CPR, cc = gtid % CPR;
+    const int rs = gtid >> 2, c8 = gtid & 3;
+    int kk[2];  // the chunks' k within a slice
     const gmem_t<T>* pa[2];
     const gmem_t<T>* pb[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int ra = bm + r0 + 32 * h, rb = bn + r0 + 32 * h;
+        const int rr = SPLIT ? rs : r0 + 32 * h;
+        kk[h] = SPLIT ? 8 * c8 + 4 * h : cc * VEC;
+        const int ra = bm + rr, rb = bn + rr;
         pa[h] = gmem(a.A) + size_t(ra < M ? ra : 0) * K;
         pb[h] = gmem(a.Bt) + size_t(rb < N ? rb : 0) * K;
     }
-    vec_t va[2][2], vb[2][2];  // [register slot][row half]
-    // Rows of whole 16-byte chunks (K % VEC == 0): one 16-byte load per row and
-    // operand for every slice, chunks past K read from a 16-byte block of
+    vec_t va[2][2], vb[2][2];  // [register slot][chunk h]
+    // Rows of whole 16-byte chunks (K % VEC == 0): one 16-byte load per chunk
+    // and operand for every slice, chunks past K read from a 16-byte block of
     // zeros (an address select: no branch and no select on a loaded value, so
     // the wait before a copy covers only the loads that copy needs).
     const gmem_t<vec_t>* zchunk = reinterpret_cast<const gmem_t<vec_t>*>(gmem(g_nt_zeros));
     auto gload_al = [&](int k0, int slot) {
-        const int k = k0 + cc * VEC;
-        const bool in = k < K;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
+            const int k = k0 + kk[h];
+            const bool in = k < K;
             va[slot][h] = *(in ? reinterpret_cast<const gmem_t<vec_t>*>(pa[h] + k) : zchunk);
             vb[slot][h] = *(in ? reinterpret_cast<const gmem_t<vec_t>*>(pb[h] + k) : zchunk);
         }
@@ -1791,49 +1806,48 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     };
     // Other K: element loads past the last whole slice, zeros past K.
     auto gload = [&](int k0, int slot) {
-        const int k = k0 + cc * VEC;
         if (k0 + BK <= K && (K % VEC) == 0) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                va[slot][h] = *reinterpret_cast<const gmem_t<vec_t>*>(pa[h] + k);
-                vb[slot][h] = *reinterpret_cast<const gmem_t<vec_t>*>(pb[h] + k);
+                va[slot][h] = *reinterpret_cast<const gmem_t<vec_t>*>(pa[h] + k0 + kk[h]);
+                vb[slot][h] = *reinterpret_cast<const gmem_t<vec_t>*>(pb[h] + k0 + kk[h]);
             }
         } else {  // tail slice: zeros past K
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    const bool in = k + e < K;
-                    va[slot][h][e] = in ? pa[h][k + e] : T(0);
-                    vb[slot][h][e] = in ? pb[h][k + e] : T(0);
+                    const int k = k0 + kk[h] + e;
+                    const bool in = k < K;
+                    va[slot][h][e] = in ? pa[h][k] : T(0);
+                    vb[slot][h][e] = in ? pb[h][k] : T(0);
                 }
         }
     };
     auto sstore = [&](int buf, int slot) {
+        // the split of a slot stays after the copy before it: scheduled
+        // earlier, it waited for loads issued half a step before
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (SPLIT) {
+            // 8 k of row rs: chunk c8 of each plane, one 16-byte store each
+            auto put3 = [&](const vec_t (&x)[2], unsigned char* t) {
+                uint2 h0, m0, l0, h1, m1, l1;
+                const float x0[4] = {x[0][0], x[0][1], x[0][2], x[0][3]};
+                const float x1[4] = {x[1][0], x[1][1], x[1][2], x[1][3]};
+                split3_bf16(x0, h0, m0, l0);
+                split3_bf16(x1, h1, m1, l1);
+                *reinterpret_cast<uint4*>(t + split_off(0, rs, c8)) = make_uint4(h0.x, h0.y, h1.x, h1.y);
+                *reinterpret_cast<uint4*>(t + split_off(1, rs, c8)) = make_uint4(m0.x, m0.y, m1.x, m1.y);
+                *reinterpret_cast<uint4*>(t + split_off(2, rs, c8)) = make_uint4(l0.x, l0.y, l1.x, l1.y);
+            };
+            put3(va[slot], smem + buf * TILE_BYTES);
+            put3(vb[slot], smem + (2 + buf) * TILE_BYTES);
+        } else {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = r0 + 32 * h;
-            const vec_t xva = va[slot][h], xvb = vb[slot][h];
-            if constexpr (SPLIT) {
-                // 4 k (8 bytes per plane): half cc & 1 of chunk cc >> 1
-                const int off = r * 64 + 16 * ((cc >> 1) ^ ((r >> 2) & 3)) + 8 * (cc & 1);
-                uint2 ph, pm, pl;
-                const float xa[4] = {xva[0], xva[1], xva[2], xva[3]};
-                split3_bf16(xa, ph, pm, pl);
-                unsigned char* ta = smem + buf * TILE_BYTES + off;
-                *reinterpret_cast<uint2*>(ta) = ph;
-                *reinterpret_cast<uint2*>(ta + 64 * 64) = pm;
-                *reinterpret_cast<uint2*>(ta + 2 * 64 * 64) = pl;
-                const float xb[4] = {xvb[0], xvb[1], xvb[2], xvb[3]};
-                split3_bf16(xb, ph, pm, pl);
-                unsigned char* tb = smem + (2 + buf) * TILE_BYTES + off;
-                *reinterpret_cast<uint2*>(tb) = ph;
-                *reinterpret_cast<uint2*>(tb + 64 * 64) = pm;
-                *reinterpret_cast<uint2*>(tb + 2 * 64 * 64) = pl;
-            } else {
-                const int sc = (cc ^ ((r >> 1) & 7)) * VEC;
-                *reinterpret_cast<vec_t*>(&As[buf][r * LD + sc]) = xva;
-                *reinterpret_cast<vec_t*>(&Bs[buf][r * LD + sc]) = xvb;
+            for (int h = 0; h < 2; ++h) {
+                const int r = r0 + 32 * h, sc = (cc ^ ((r >> 1) & 7)) * VEC;
+                *reinterpret_cast<vec_t*>(&As[buf][r * LD + sc]) = va[slot][h];
+                *reinterpret_cast<vec_t*>(&Bs[buf][r * LD + sc]) = vb[slot][h];
             }
         }
     };
@@ -1842,19 +1856,17 @@ __device__ __forceinline__ void mgemm_lds_body(const MGemmArgs<T>& a, int bx, in
     acc_t c00 = {}, c01 = {}, c10 = {}, c11 = {};
     auto compute_split = [&](int buf) {
         if constexpr (SPLIT) {
-            // rows wm + idx (+16): (row >> 2) & 3 is the same for row and row + 16
-            const int ra = wm + idx, rb = wn + idx;
-            const int oa = ra * 64 + 16 * (g ^ ((ra >> 2) & 3)), ob = rb * 64 + 16 * (g ^ ((rb >> 2) & 3));
-            const unsigned char* ta = smem + buf * TILE_BYTES + oa;
-            const unsigned char* tb = smem + (2 + buf) * TILE_BYTES + ob;
+            // rows wm + idx and wm + idx + 16 of A, wn + idx (+16) of Bt
+            const unsigned char* ta = smem + buf * TILE_BYTES;
+            const unsigned char* tb = smem + (2 + buf) * TILE_BYTES;
             bf16x8_t fa[2][3], fb[2][3];  // [row half][plane h, m, l]
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                fa[0][q] = *reinterpret_cast<const bf16x8_t*>(ta + q * 64 * 64);
-                fa[1][q] = *reinterpret_cast<const bf16x8_t*>(ta + q * 64 * 64 + 16 * 64);
-                fb[0][q] = *reinterpret_cast<const bf16x8_t*>(tb + q * 64 * 64);
-                fb[1][q] = *reinterpret_cast<const bf16x8_t*>(tb + q * 64 * 64 + 16 * 64);
-            }
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    fa[hh][q] = *reinterpret_cast<const bf16x8_t*>(ta + split_off(q, wm + idx + 16 * hh, g));
+                    fb[hh][q] = *reinterpret_cast<const bf16x8_t*>(tb + split_off(q, wn + idx + 16 * hh, g));
+                }
             c00 = mma_split6(fa[0], fb[0], c00);
             c01 = mma_split6(fa[0], fb[1], c01);
             c10 = mma_split6(fa[1], fb[0], c10);
