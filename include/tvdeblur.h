@@ -331,10 +331,12 @@ int tvdeblur_op_export(tvdeblur_t h, int which, void* dst_dev);
  * real DFT of length 2(n-1), DCT-II through one of length 2n; Bluestein
  * for lengths that are not powers of two) or as dense products with the n x n
  * basis matrix on the matrix cores (4 products of n^3 multiply-adds per
- * application).  The two differ only in rounding.  TVD_TRANSFORM_AUTO (the
- * default) times one application of each when the handle is built (at the
- * first solve or op after set_psf / set_bc) and keeps the faster; the
- * product form exists for TVD_F32_MIXED handles. */
+ * application; in TVD_F32_MIXED the 64 x 64 tiles compute each FP32 product
+ * as six bf16 products of three-way operand splits, to FP32 accuracy).  The
+ * two differ only in rounding.  TVD_TRANSFORM_AUTO (the default) times one
+ * application of each when the handle is built (at the first solve or op
+ * after set_psf / set_bc) and keeps the line transforms unless the products
+ * are at least 5% faster. */
 #define TVD_TRANSFORM_AUTO  0
 #define TVD_TRANSFORM_FFT   1
 #define TVD_TRANSFORM_GEMM  2
@@ -350,8 +352,9 @@ int tvdeblur_set_transform(tvdeblur_t h, int mode);
  * Errors: TVD_EINVAL, TVD_ESTATE, TVD_EDEVICE. */
 int tvdeblur_get_transform(tvdeblur_t h, int* active);
 
-/* Block tile of the matrix-core products (32: four waves split the K of one
- * 32 x 32 tile; 64: a 64 x 64 tile, one 32 x 32 quadrant per wave) into
+/* Block tile of the matrix-core products (32: four waves (eight in FP64)
+ * split the K of one 32 x 32 tile; 64: a 64 x 64 tile, one 32 x 32 quadrant
+ * per wave, two groups of four waves splitting K for a single image) into
  * *tile (host).  Picked with the transform form by timing at build (both
  * tiles, interleaved, three times each; cached per process by shape, PSF
  * widths, BC and precision).  Builds the handle first if needed.
