@@ -72,8 +72,8 @@ ITER_WORDS_WITH_TRANSPOSES = 17
 # a plain copy kernel of known size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), for
 # the kernel source whose SHA-256 prefix is recorded; ignored (null) once the
 # kernel source has changed since.  Source: profiles/m512_f32_traffic.md.
-TRAFFIC = {"source_sha256": "c562148ec4d992c8",
-           "bytes_per_launch": {"transform_gemm": 7992413, "band_normal": 8947594, "update": 8161099}}
+TRAFFIC = {"source_sha256": "bc786f8fdecec389",
+           "bytes_per_launch": {"transform_gemm": 8281342, "band_normal": 8908638, "update": 8136657}}
 
 # The per-class breakdown samples 1 launch in PROFILE_EVERY of each class
 # (a timed launch delays the next by ~9 us), in a solve outside the timing.

@@ -232,8 +232,10 @@ struct MGemmArgs {
     int n_rr;
     int iter;
     PcgState* st;           // nullptr: plain product
-    int tile;               // block tile: 32 (four waves split K of one 32 x 32
-                            // tile) or 64 (64 x 64, one 32 x 32 quadrant per wave)
+    int tile;               // block tile: 32 (four waves, eight in FP64, split K
+                            // of one 32 x 32 tile) or 64 (64 x 64, one 32 x 32
+                            // quadrant per wave; single image: two groups of
+                            // four waves split K)
 };
 
 // PCG update of the product-form preconditioner path: x += a p, r -= a q

@@ -1439,8 +1439,9 @@ __global__ void __launch_bounds__(kYThreads) k_ypass_full_bc(const YPassArgs<T>*
 }
 
 // ------------------------------------------------------------------------
-// Dense products on the matrix cores (MFMA 16x16x4, one 16 x 16 tile of C
-// per wave).  MfmaCfg holds the instruction and its lane layout per type.
+// Dense products on the matrix cores (MFMA 16x16x4 in FP32 and FP64; the
+// FP32 64 x 64 tiles use bf16 16x16x32 on split operands, see mma_split6).
+// MfmaCfg holds the FP32 / FP64 instruction and its lane layout per type.
 // ------------------------------------------------------------------------
 template <typename T>
 struct MfmaCfg;
@@ -1677,7 +1678,7 @@ __device__ __forceinline__ void mgemm_body(const MGemmArgs<T>& a, int bx, int by
             compute();
         }
     }
-    // sum the four waves' partial tiles: wave w finishes tile (w / 2, w % 2)
+    // sum the kW waves' partial tiles: wave w < 4 finishes tile (w / 2, w % 2)
     {
         T* mine = red_tile + wave * 16 * 64;
 #pragma unroll
