@@ -65,11 +65,12 @@ def form(transform):
 @pytest.mark.parametrize("transform", ["fft", "gemm32", "gemm64"])
 @pytest.mark.parametrize("bc", [AR, R])
 @pytest.mark.parametrize("variant", ["x", "d_x", "x_d"])
-@pytest.mark.parametrize("shape", [(64, 64), (37, 50), (130, 70), (33, 300), (200, 136)])
+@pytest.mark.parametrize("shape", [(64, 64), (37, 50), (130, 70), (33, 300), (200, 136), (24, 40)])
 def test_precond_forms_match_oracle(shape, variant, bc, transform, prec):
     """z = P^{-1} r for both transform implementations on square, ragged and
     elongated images (several 32 x 32 product tiles plus tails in every
-    direction)."""
+    direction; (24, 40): one K slice, so the second K group of the
+    single-image 64 x 64 products reads only zeros)."""
     print(f"case precond {shape} {variant} {bc} {transform} {prec}", flush=True)
     rng = np.random.default_rng(11)
     psf = synth.gaussian_psf(7, 1.2)
